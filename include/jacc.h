@@ -1,0 +1,270 @@
+/*
+ * jacc.h — C ABI of the K-partitioned loop-nest runtime for AMD MI355X (gfx950).
+ *
+ * Model (after JACC, Matsumura, Garcia De Gonzalo, Pena, HiPC 2021,
+ * arXiv 2110.14340):
+ *   - Data regions: arrays are declared to the runtime with create / copyin /
+ *     copyout routines that stand in for OpenACC data directives
+ *     (Sec. "JACC", converted-code listing: jacc_create ... jacc_copyout).
+ *     Any address inside a declared array resolves to it (Sec. "Automated
+ *     Asynchronous Execution": data ranges are kept in an ordered tree so any
+ *     address of declared data is accepted).
+ *   - Parallel loops: a loop nest is launched by one call that carries its
+ *     kernel, its arguments and flags (the jacc_kernel_push routine of the
+ *     converted-code listing).  Here the kernel is one of a fixed set of
+ *     hand-written HIP loop bodies (JACC_LOOP_*), and every argument declares
+ *     the rows of dim 0 it reads or writes relative to the outer iterator.
+ *   - Partitioning: the outermost dimension of every array is divided
+ *     equally into K owner blocks (Sec. "Division of Multidimensional
+ *     Arrays"), B_p = [floor(p*E/K), floor((p+1)*E/K)).  Partition p keeps a
+ *     private device slab holding B_p widened by the array's declared halo
+ *     (or the whole array for arrays declared WHOLE, which are replicated as
+ *     the paper replicates allocations and host-to-device copies on every
+ *     device, Sec. "Predicate-Based Filtering").  A loop runs on partition p
+ *     only the iterations whose write row lies in B_p — the paper's
+ *     write-predicate [a_lb, a_ub] hoisted into the launch bounds, exact for
+ *     loops that write element i of dim 0 from outer iteration i.
+ *   - Coherence: before a partition runs, the rows it reads that its slab
+ *     does not hold in their latest version are copied from the partition
+ *     that wrote them last (device-local copies).  This replaces the paper's
+ *     send-everything-after-each-kernel scheme with range-driven transfers.
+ *   - Asynchrony: partition p's work runs on stream p.  Cross-stream waits
+ *     are inserted only for the rows actually shared (read-after-write and
+ *     write-after-read), skipping waits already satisfied (the paper keeps
+ *     access timestamps and the most recent synchronisation among queues,
+ *     Sec. "Automated Asynchronous Execution").
+ *
+ * Conventions
+ *   - Every call returns a jacc_status (0 = success, negative = error).  The
+ *     library never aborts and no C++ exception crosses this boundary.
+ *   - A failed HIP call makes the context sticky: every later call returns
+ *     JACC_ERR_DEVICE until jacc_finalize.  jacc_last_error gives the text.
+ *   - Host arrays are owned by the caller and must stay valid from enter to
+ *     exit.  Device slabs are owned by the library and freed when the
+ *     array's reference count reaches zero or at jacc_finalize.  Streams
+ *     passed to jacc_init stay owned by the caller.
+ *   - Calls return after enqueueing.  Results become visible on the host at
+ *     jacc_wait, jacc_update(HOST), jacc_data_exit(COPYOUT) or a synchronous
+ *     reduction.
+ */
+#ifndef JACC_H
+#define JACC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct jacc_ctx jacc_ctx; /* opaque; owned by the library */
+
+typedef enum {
+    JACC_OK = 0,
+    JACC_ERR_INVALID = -1,         /* bad argument (NULL, negative size, unknown kind ...) */
+    JACC_ERR_NOT_PRESENT = -2,     /* host address not inside any declared array */
+    JACC_ERR_ALREADY_PRESENT = -3, /* enter of an overlapping range with a different descriptor */
+    JACC_ERR_RANGE = -4,           /* access outside a slab, or partitions writing the same rows */
+    JACC_ERR_ALLOC = -5,           /* the allocator returned NULL */
+    JACC_ERR_DEVICE = -6,          /* a HIP call failed (sticky) */
+    JACC_ERR_UNSUPPORTED = -7      /* a legal request this build does not implement */
+} jacc_status;
+
+/* Device-memory allocator.  alloc returns device memory of at least `bytes`
+ * bytes aligned to 256 bytes, or NULL; free releases it.  The library calls
+ * free only after every stream that used the memory has been synchronised.
+ * Passing NULL to jacc_init selects hipMalloc/hipFree. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} jacc_allocator;
+
+typedef enum { JACC_F64 = 0, JACC_F32 = 1, JACC_I32 = 2, JACC_I64 = 3 } jacc_dtype;
+
+/* Array descriptor.  Row-major; dim 0 is the partitioned (outermost)
+ * dimension with extent E = extent[0]; a "row" is one index of dim 0 and
+ * holds extent[1]*...*extent[ndim-1] elements.  halo_lo/halo_hi are the
+ * largest distances (in rows) below and above the owner block that loops
+ * will read.  whole != 0 keeps a full replica in every partition.
+ * num_partitions: K of this array (0 = the context's K). */
+typedef struct {
+    int32_t dtype;
+    int32_t ndim;            /* 1..4 */
+    int64_t extent[4];
+    int32_t halo_lo, halo_hi;
+    int32_t whole;
+    int32_t num_partitions;
+} jacc_array_desc;
+
+/* data_enter clauses */
+enum { JACC_COPYIN = 1, JACC_CREATE = 2, JACC_COPY = 3 };
+/* data_exit clauses */
+enum { JACC_COPYOUT = 1, JACC_DELETE = 2 };
+/* update directions */
+enum { JACC_UPDATE_HOST = 1, JACC_UPDATE_DEVICE = 2 };
+/* argument access modes */
+enum { JACC_READ = 1, JACC_WRITE = 2, JACC_READWRITE = 3 };
+
+/* Loop argument: the base address of a declared array, its access mode and
+ * the rows of dim 0 that outer iteration i touches, [i+off_lo, i+off_hi]
+ * (inclusive), or the whole array when whole != 0. */
+typedef struct {
+    void *host;
+    int32_t mode;
+    int32_t off_lo, off_hi;
+    int32_t whole;
+} jacc_arg;
+
+/* Iteration space: half-open [lo[d], hi[d]) per loop dimension; dim 0 is the
+ * one split among partitions. */
+typedef struct {
+    int32_t ndim;
+    int32_t pad_;
+    int64_t lo[3], hi[3];
+} jacc_bounds;
+
+/* Launch configuration.  Never changes the arithmetic of any loop body.
+ *   bx, by     workgroup shape in threads (bx a multiple of 64; bx*by <= 1024)
+ *   tile       rows (2-D) or planes (3-D) each thread marches through
+ *   vec        1 or 2 consecutive FP64 elements per lane (2 needs an even row
+ *              length)
+ *   persistent 1 = run the loop inside the batched persistent kernel
+ * Fields equal to 0 take the default. */
+typedef struct {
+    int32_t bx, by, tile, vec, persistent;
+} jacc_config;
+
+/* Loop kinds (hand-written HIP loop bodies) and their arguments, in order:
+ *   JACOBI2D  u_in R [-1,+1]; u_out W [0,0].  2-D bounds (normally [1,N-1)^2).
+ *             u_out[i][j] = 0.25*((u_in[i-1][j]+u_in[i+1][j]) + (u_in[i][j-1]+u_in[i][j+1]))
+ *   HEAT3D    u_in R [-1,+1]; u_out W [0,0].  3-D bounds; scalars[0] = alpha.
+ *             lap = (((x-1 + x+1) + (y-1 + y+1)) + (z-1 + z+1)) - 6*u;  u' = u + alpha*lap
+ *             optional reduction: sum over the box of (u'-u)^2 (stored values)
+ *   SUM       x R [0,0].  1-D bounds over dim 0 rows; whole rows are summed.
+ *             reduction: sum of x (scalars[0] != 0: sum of x^2)
+ *   GEMM      A R [0,0] (M x L); B R WHOLE (L x N); C W [0,0] (M x N).
+ *             2-D bounds [0,M) x [0,N).  C = A*B (FP64 matrix cores)
+ *   SPMV_CSR  row_ptr (int32, n+1) R [0,+1]; col (int32) R WHOLE; val (f64)
+ *             R WHOLE; x R WHOLE; y W [0,0].  1-D bounds [0,n).
+ *             y[i] = sum_{k=row_ptr[i]}^{row_ptr[i+1]-1} val[k]*x[col[k]] */
+enum {
+    JACC_LOOP_JACOBI2D = 1,
+    JACC_LOOP_HEAT3D = 2,
+    JACC_LOOP_SUM = 3,
+    JACC_LOOP_GEMM = 4,
+    JACC_LOOP_SPMV_CSR = 5
+};
+
+/* jacc_init flags */
+enum {
+    JACC_INIT_DRYRUN = 1u << 0, /* plan and trace only: no HIP call, fake device addresses */
+    JACC_INIT_TRACE = 1u << 1,  /* record every planned operation (see jacc_trace_get) */
+    JACC_INIT_SERIALIZE = 1u << 2 /* one stream for every partition, device sync after each op */
+};
+
+/* Create a context with K partitions (1 <= K <= 64).  streams: K hipStream_t
+ * handles owned by the caller, or NULL to let the library create K
+ * non-blocking streams of default priority.  alloc: NULL selects hipMalloc.
+ * On success *out receives the context. */
+int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator *alloc,
+              unsigned flags);
+
+/* Synchronise, free every slab still present, destroy library-created
+ * streams and events, and free the context.  Returns the context's sticky
+ * status (JACC_OK if no device error occurred). */
+int jacc_finalize(jacc_ctx *ctx);
+
+/* Declare the array whose host copy starts at `host` (data directive entry).
+ * A repeated enter of the same range with an equal descriptor increments
+ * its reference count.  clause JACC_COPYIN / JACC_COPY copies every slab's
+ * rows from the host; JACC_CREATE leaves device contents undefined. */
+int jacc_data_enter(jacc_ctx *ctx, void *host, const jacc_array_desc *desc, int clause);
+
+/* Leave the data region of the array containing `host`.  JACC_COPYOUT
+ * gathers every row from the partition that wrote it last into the host
+ * array (synchronously); JACC_DELETE discards device data.  Slabs are freed
+ * when the reference count reaches zero. */
+int jacc_data_exit(jacc_ctx *ctx, void *host, int clause);
+
+/* Copy rows [row_lo, row_hi) of the array containing `host` between host and
+ * device.  JACC_UPDATE_HOST gathers from the latest writers and returns
+ * after the host copy is complete.  JACC_UPDATE_DEVICE scatters to every
+ * slab holding the rows.  row_hi < 0 means the last row. */
+int jacc_update(jacc_ctx *ctx, void *host, int dir, int64_t row_lo, int64_t row_hi);
+
+/* Launch one loop nest over its K partitions.  kind: JACC_LOOP_*; args: the
+ * kind's arguments in its documented order; scalars: kind-specific doubles;
+ * reduce_slot >= 0 stores the loop's reduction in device slot reduce_slot
+ * (0 <= slot < 4096; read later with jacc_reduction_get); reduce_host !=
+ * NULL additionally waits and writes the value there (the paper's
+ * obligatory synchronisation after an explicit reduction).  cfg: NULL takes
+ * the tuned or default configuration.
+ * Errors: JACC_ERR_NOT_PRESENT (an argument is not declared), JACC_ERR_RANGE
+ * (a partition would touch rows outside its slab, or two partitions would
+ * write the same rows — the paper's aliasing case), JACC_ERR_UNSUPPORTED
+ * (arguments partitioned with different K, or an interior pointer),
+ * JACC_ERR_INVALID (bad kind, bounds, argument count or config). */
+int jacc_parallel_loop(jacc_ctx *ctx, int kind, const jacc_bounds *bounds, int nargs,
+                       const jacc_arg *args, const double *scalars, int nscalars,
+                       int reduce_slot, double *reduce_host, const jacc_config *cfg);
+
+/* Block until every stream of the context has finished. */
+int jacc_wait(jacc_ctx *ctx);
+
+/* Wait for the loop that produced reduction slot `slot` and read it. */
+int jacc_reduction_get(jacc_ctx *ctx, int slot, double *out);
+
+/* Read reduction slots [first, first+count) into out after a full wait. */
+int jacc_reduction_read(jacc_ctx *ctx, int first, int count, double *out);
+
+/* Text of the last error on this context (library-owned; valid until the
+ * next call on ctx). */
+const char *jacc_last_error(const jacc_ctx *ctx);
+
+/* Device pointer of partition p's slab of the array containing `host`, and
+ * the slab's first and one-past-last rows.  For callers that run their own
+ * kernels on the data (and for tests). */
+int jacc_slab_info(jacc_ctx *ctx, void *host, int p, void **dev, int64_t *row_lo,
+                   int64_t *row_hi);
+
+/* ---- operation trace (planning and tests) ------------------------------ */
+enum {
+    JACC_OP_ALLOC = 1,   /* array a, partition dst, rows [lo,hi) */
+    JACC_OP_FREE = 2,
+    JACC_OP_H2D = 3,     /* host rows [lo,hi) -> slab dst, on stream */
+    JACC_OP_D2H = 4,     /* slab src rows [lo,hi) -> host, on stream */
+    JACC_OP_COPY = 5,    /* slab src rows [lo,hi) -> slab dst, on stream (== dst) */
+    JACC_OP_KERNEL = 6,  /* loop kind `kind`, partition dst, iterations [lo,hi) of dim 0 */
+    JACC_OP_RECORD = 7,  /* event recorded on stream, covering its ops up to seq */
+    JACC_OP_WAIT = 8,    /* stream waits for stream src up to seq */
+    JACC_OP_SYNC = 9,    /* host waits for stream */
+    JACC_OP_COMBINE = 10, /* reduction combine on stream into slot `kind` */
+    JACC_OP_ACCESS = 11   /* the preceding op on stream touches slab dst of array rows
+                             [lo,hi): kind 1 = read, 2 = write */
+};
+
+typedef struct {
+    int32_t op;
+    int32_t stream;
+    int32_t array;   /* array id (order of first enter), or -1 */
+    int32_t src;     /* source partition / stream, or -1 */
+    int32_t dst;     /* destination partition, or -1 */
+    int32_t kind;    /* loop kind (KERNEL), slot (COMBINE) */
+    int64_t lo, hi;  /* rows or iterations */
+    int64_t seq;     /* per-stream sequence number of this op (WAIT: awaited seq) */
+} jacc_trace_op;
+
+/* Number of recorded trace entries; entry i; clear. */
+int jacc_trace_len(const jacc_ctx *ctx);
+int jacc_trace_get(const jacc_ctx *ctx, int i, jacc_trace_op *out);
+int jacc_trace_clear(jacc_ctx *ctx);
+
+/* Library version string (static). */
+const char *jacc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JACC_H */

@@ -1,0 +1,83 @@
+// Loop-kind dispatch, default launch configurations and their validation.
+#include "jacc.h"
+#include "kernels.h"
+
+namespace jk {
+
+static int64_t inner_extent(const Launch &L) {
+    // length of the contiguous (innermost) dimension of the first argument
+    int nd = 1;
+    for (int i = 1; i < 4; ++i)
+        if (L.ext[i] > 0) nd = i + 1;
+    return L.ext[nd - 1];
+}
+
+Cfg default_config(int kind, const Launch &L, Cfg c) {
+    const bool even = (inner_extent(L) % 2) == 0;
+    switch (kind) {
+        case JACC_LOOP_JACOBI2D:
+            if (!c.bx) c.bx = 256;
+            if (!c.by) c.by = 1;
+            if (!c.tile) c.tile = 32;
+            if (!c.vec) c.vec = even ? 2 : 1;
+            break;
+        case JACC_LOOP_HEAT3D:
+            if (!c.bx) c.bx = 128;
+            if (!c.by) c.by = 2;
+            if (!c.tile) c.tile = 16;
+            if (!c.vec) c.vec = even ? 2 : 1;
+            break;
+        default:
+            if (!c.bx) c.bx = 256;
+            if (!c.by) c.by = 1;
+            if (!c.tile) c.tile = 1;
+            if (!c.vec) c.vec = 1;
+            break;
+    }
+    return c;
+}
+
+int check_config(const Launch &L) {
+    const Cfg &c = L.cfg;
+    if (c.persistent) return 1;  // persistent execution only inside a batch
+    switch (L.kind) {
+        case JACC_LOOP_JACOBI2D:
+        case JACC_LOOP_HEAT3D:
+            if (c.bx < 64 || c.bx % 64 || c.by < 1 || c.bx * c.by > 1024) return 1;
+            if (c.tile < 1 || c.tile > 65536) return 1;
+            if (c.vec != 1 && c.vec != 2) return 1;
+            if (c.vec == 2 && inner_extent(L) % 2) return 1;
+            return 0;
+        case JACC_LOOP_SUM:
+        case JACC_LOOP_GEMM:
+        case JACC_LOOP_SPMV_CSR:
+            return 0;  // fixed internal configurations; fields are ignored
+        default:
+            return 1;
+    }
+}
+
+int64_t reduction_workgroups(const Launch &L) {
+    switch (L.kind) {
+        case JACC_LOOP_HEAT3D: return heat3d_workgroups(L);
+        case JACC_LOOP_SUM: return sum_workgroups(L);
+        default: return 0;
+    }
+}
+
+hipError_t launch_loop(const Launch &L, hipStream_t s) {
+    switch (L.kind) {
+        case JACC_LOOP_JACOBI2D: return launch_jacobi2d(L, s);
+        case JACC_LOOP_HEAT3D: {
+            hipError_t e = launch_heat3d(L, s);
+            if (e != hipSuccess || !L.wg_partials) return e;
+            return launch_finalise(L.wg_partials, heat3d_workgroups(L), L.part_out, s);
+        }
+        case JACC_LOOP_SUM: return launch_sum(L, s);
+        case JACC_LOOP_GEMM: return launch_gemm(L, s);
+        case JACC_LOOP_SPMV_CSR: return launch_spmv(L, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace jk

@@ -1,0 +1,144 @@
+// Dense FP64 contraction C = A*B on the gfx950 matrix cores
+// (v_mfma_f64_16x16x4f64).
+//
+// Workgroup: 256 threads (4 waves) computing a 128x128 tile of C; each wave
+// owns a 64x64 sub-tile as 4x4 MFMA blocks of 16x16 (64 FP64 accumulators
+// per lane).  The k dimension is walked in slabs of 16 in increasing order
+// (no split-k, so every element's accumulation order is the same for every
+// partition count), staged through LDS with double buffering: the next
+// slab's global loads are in flight while the current slab feeds the
+// matrix cores.
+//
+// MFMA operand layout (16x16x4, FP64, wave64): lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; accumulator element r of lane l is D[4*(l/16)+r][l%16].
+#include "k_common.h"
+#include "kernels.h"
+
+namespace jk {
+
+namespace {
+
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int kGemmThreads = 256;
+constexpr int SA = BK + 2;   // LDS row stride of A (doubles): conflict-free fragment reads
+constexpr int SB = BN + 16;  // LDS row stride of B (doubles)
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(kGemmThreads)
+gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *__restrict__ C, int64_t m_lo,
+            int64_t m_hi, int64_t N, int64_t L, int64_t lda, int64_t ldb, int64_t ldc, int64_t n_lo, int64_t n_hi,
+            int tiles_n) {
+    __shared__ double As[2][BM * SA];
+    __shared__ double Bs[2][BK * SB];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t tile = blockIdx.x;
+    const int64_t row0 = m_lo + (tile / tiles_n) * BM;
+    const int64_t col0 = n_lo + (tile % tiles_n) * BN;
+
+    // global -> register staging: A tile 128x16 and B tile 16x128 are 1024
+    // double2 each, 4 per thread
+    double2 ra[4], rb[4];
+    auto load_tiles = [&](int64_t k0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int idx = tid + u * kGemmThreads;
+            {   // A: row = idx / 8, k pair = idx % 8
+                const int r = idx >> 3, kp = (idx & 7) * 2;
+                const int64_t gi = row0 + r, gk = k0 + kp;
+                double2 v;
+                v.x = (gi < m_hi && gk < L) ? A[gi * lda + gk] : 0.0;
+                v.y = (gi < m_hi && gk + 1 < L) ? A[gi * lda + gk + 1] : 0.0;
+                ra[u] = v;
+            }
+            {   // B: k = idx / 64, column pair = idx % 64
+                const int kr = idx >> 6, cp = (idx & 63) * 2;
+                const int64_t gk = k0 + kr, gj = col0 + cp;
+                double2 v;
+                v.x = (gk < L && gj < n_hi) ? B[gk * ldb + gj] : 0.0;
+                v.y = (gk < L && gj + 1 < n_hi) ? B[gk * ldb + gj + 1] : 0.0;
+                rb[u] = v;
+            }
+        }
+    };
+    auto store_tiles = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int idx = tid + u * kGemmThreads;
+            const int r = idx >> 3, kp = (idx & 7) * 2;
+            As[buf][r * SA + kp] = ra[u].x;
+            As[buf][r * SA + kp + 1] = ra[u].y;
+            const int kr = idx >> 6, cp = (idx & 63) * 2;
+            Bs[buf][kr * SB + cp] = rb[u].x;
+            Bs[buf][kr * SB + cp + 1] = rb[u].y;
+        }
+    };
+
+    d4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const int nk = (int)((L + BK - 1) / BK);
+    load_tiles(0);
+    store_tiles(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load_tiles((int64_t)(kt + 1) * BK);
+        const double *as = As[buf];
+        const double *bs = Bs[buf];
+#pragma unroll
+        for (int kk = 0; kk < BK / 4; ++kk) {
+            double a[4], b[4];
+            const int kq = kk * 4 + (lane >> 4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = as[(wm * 64 + i * 16 + (lane & 15)) * SA + kq];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = bs[kq * SB + wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (kt + 1 < nk) {
+            store_tiles(buf ^ 1);
+        }
+        __syncthreads();
+    }
+    // write back: acc[i][j][r] -> C[row0 + wm*64 + i*16 + 4*(lane/16) + r][col0 + wn*64 + j*16 + lane%16]
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t gi = row0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+            if (gi >= m_hi) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t gj = col0 + wn * 64 + j * 16 + (lane & 15);
+                if (gj < n_hi) C[gi * ldc + gj] = acc[i][j][r];
+            }
+        }
+}
+
+}  // namespace
+
+hipError_t launch_gemm(const Launch &L, hipStream_t s) {
+    // arguments: A (M x Lk), B (Lk x N), C (M x N); iteration box rows
+    // [lo0, hi0) of C, columns [lo1, hi1)
+    const int64_t m = L.hi[0] - L.lo[0], n = L.hi[1] - L.lo[1];
+    if (m <= 0 || n <= 0) return hipSuccess;
+    const int64_t Lk = L.a[0].row_elems;
+    const int64_t N = L.a[2].row_elems;
+    const int tiles_m = (int)((m + BM - 1) / BM), tiles_n = (int)((n + BN - 1) / BN);
+    hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)tiles_m * tiles_n), dim3(kGemmThreads), 0, s,
+                       (const double *)L.a[0].ptr, (const double *)L.a[1].ptr, (double *)L.a[2].ptr, L.lo[0], L.hi[0],
+                       N, Lk, Lk, L.a[1].row_elems, N, L.lo[1], L.hi[1], tiles_n);
+    return hipGetLastError();
+}
+
+}  // namespace jk

@@ -1,0 +1,99 @@
+// Reduction loop body (sum / sum of squares), per-partition finaliser and
+// the cross-partition combine, for gfx950.
+//
+// Order of additions (fixed for a given configuration and partition): each
+// lane keeps 8 running sums over a grid-stride walk, adds them pairwise,
+// the wave adds its lanes by a butterfly, the workgroup adds its waves in
+// order, the finaliser adds workgroup partials with a fixed tree, and the
+// combine adds the partitions' results in partition order (the paper filters
+// a reduction by the range of the outer iterator on each device and then
+// combines the per-device values, Sec. "Predicate-Based Filtering").
+#include "k_common.h"
+#include "kernels.h"
+
+namespace jk {
+
+namespace {
+
+constexpr int kSumThreads = 256;
+constexpr int kSumUnroll = 8;
+constexpr int kSumMaxBlocks = 2048;
+
+template <bool SQ>
+__global__ void __launch_bounds__(kSumThreads)
+sum_kernel(const double *__restrict__ x, int64_t begin, int64_t n, double *__restrict__ wg_partials) {
+    __shared__ double sh[kSumThreads / kWave];
+    const int64_t chunk = (int64_t)kSumThreads * kSumUnroll;
+    const int64_t stride = chunk * gridDim.x;
+    double a[kSumUnroll];
+#pragma unroll
+    for (int u = 0; u < kSumUnroll; ++u) a[u] = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * chunk; base < n; base += stride) {
+        double v[kSumUnroll];
+#pragma unroll
+        for (int u = 0; u < kSumUnroll; ++u) {
+            const int64_t e = base + threadIdx.x + (int64_t)u * kSumThreads;
+            v[u] = e < n ? x[begin + e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSumUnroll; ++u) a[u] += SQ ? v[u] * v[u] : v[u];
+    }
+    const double t = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    const double s = block_sum(t, sh);
+    if (threadIdx.x == 0) wg_partials[blockIdx.x] = s;
+}
+
+// out = ordered sum of p[0..n): thread t adds p[t], p[t+256], ... then the
+// workgroup sum.
+__global__ void __launch_bounds__(256)
+finalise_kernel(const double *__restrict__ p, int64_t n, double *__restrict__ out) {
+    __shared__ double sh[256 / kWave];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) a += p[i];
+    const double s = block_sum(a, sh);
+    if (threadIdx.x == 0) *out = s;
+}
+
+__global__ void combine_kernel(const double *__restrict__ partials, uint64_t mask, double *__restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int p = 0; p < 64; ++p)
+            if (mask >> p & 1) s += partials[p];
+        *out = s;
+    }
+}
+
+}  // namespace
+
+int64_t sum_workgroups(const Launch &L) {
+    const int64_t n = (L.hi[0] - L.lo[0]) * L.a[0].row_elems;
+    int64_t nb = (n + (int64_t)kSumThreads * kSumUnroll - 1) / ((int64_t)kSumThreads * kSumUnroll);
+    if (nb > kSumMaxBlocks) nb = kSumMaxBlocks;
+    return nb < 1 ? 1 : nb;
+}
+
+hipError_t launch_sum(const Launch &L, hipStream_t s) {
+    const int64_t n = (L.hi[0] - L.lo[0]) * L.a[0].row_elems;
+    const int64_t begin = L.lo[0] * L.a[0].row_elems;
+    const int64_t nb = sum_workgroups(L);
+    const double *x = (const double *)L.a[0].ptr;
+    if (L.scalars[0] != 0.0)
+        hipLaunchKernelGGL(sum_kernel<true>, dim3((unsigned)nb), dim3(kSumThreads), 0, s, x, begin, n, L.wg_partials);
+    else
+        hipLaunchKernelGGL(sum_kernel<false>, dim3((unsigned)nb), dim3(kSumThreads), 0, s, x, begin, n, L.wg_partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalise(L.wg_partials, nb, L.part_out, s);
+}
+
+hipError_t launch_finalise(const double *partials, int64_t n, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(finalise_kernel, dim3(1), dim3(256), 0, s, partials, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const double *partials, uint64_t mask, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, s, partials, mask, out);
+    return hipGetLastError();
+}
+
+}  // namespace jk

@@ -1,0 +1,70 @@
+// Internal interface between the runtime (runtime.cpp) and the HIP loop
+// bodies (k_*.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace jk {
+
+// One argument as a kernel sees it: `ptr` is the device address of global
+// row 0 of the array *as if* the slab started there (slab pointer minus
+// slab_lo rows), so kernels index with global row numbers; only rows
+// [slab_lo, slab_hi) may be touched.
+struct Arg {
+    const void *ptr;       // biased pointer (see above)
+    int64_t slab_lo, slab_hi;
+    int64_t row_elems;     // elements per row of dim 0
+};
+
+struct Cfg {
+    int bx, by, tile, vec, persistent;
+};
+
+// One partition's launch of one loop nest.
+struct Launch {
+    int kind;
+    int ndim;
+    int64_t lo[3], hi[3];       // iteration box (dim 0 already clipped to the partition)
+    int64_t ext[4];             // extents of the first argument's array
+    Arg a[6];
+    int nargs;
+    double scalars[4];
+    Cfg cfg;
+    // reductions: workgroup partials go to `wg_partials` (capacity
+    // `wg_capacity` doubles); the finaliser writes their ordered sum to
+    // `part_out`.  Both null when the loop reduces nothing.
+    double *wg_partials;
+    int64_t wg_capacity;
+    double *part_out;
+};
+
+// Launches the loop body (and, for reductions, the per-partition
+// finaliser) on `s`.  Returns hipErrorInvalidValue for a configuration the
+// body does not support; the runtime validates shapes before calling.
+hipError_t launch_loop(const Launch &L, hipStream_t s);
+
+// Checks a configuration for a loop without launching; returns 0 if legal.
+int check_config(const Launch &L);
+
+// Fills in defaults for zero fields of a configuration.
+Cfg default_config(int kind, const Launch &L, Cfg c);
+
+// Reduction combine: out[0] = sum of partials[p] over the partitions p whose
+// bit is set in `mask`, added in increasing p (p < 64).
+hipError_t launch_combine(const double *partials, uint64_t mask, double *out, hipStream_t s);
+
+// Number of workgroups the loop's reduction writes partials for (for
+// sizing; <= wg_capacity is required).
+int64_t reduction_workgroups(const Launch &L);
+
+// ---- per-kind launchers (k_*.hip) -----------------------------------------
+hipError_t launch_jacobi2d(const Launch &L, hipStream_t s);
+hipError_t launch_heat3d(const Launch &L, hipStream_t s);
+int64_t heat3d_workgroups(const Launch &L);
+hipError_t launch_sum(const Launch &L, hipStream_t s);
+int64_t sum_workgroups(const Launch &L);
+hipError_t launch_finalise(const double *partials, int64_t n, double *out, hipStream_t s);
+hipError_t launch_gemm(const Launch &L, hipStream_t s);
+hipError_t launch_spmv(const Launch &L, hipStream_t s);
+
+}  // namespace jk

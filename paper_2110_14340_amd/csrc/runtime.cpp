@@ -1,0 +1,1142 @@
+// Runtime core of the K-partitioned loop-nest library: present table,
+// partition planner (owner blocks, iteration sub-ranges, access ranges),
+// coherence tracker and copy planner, stream/event scheduler with hazard
+// tracking, reduction combine, and the C ABI declared in jacc.h.
+//
+// Paper: JACC (Matsumura, Garcia De Gonzalo, Pena; HiPC 2021).  The data
+// model follows its data-region routines and present table (Sec. "JACC",
+// Sec. "Automated Asynchronous Execution"); the split follows the equal
+// division of the parallel dimension and the per-device write ranges of
+// predicate-based filtering (Sec. "Predicate-Based Filtering", Sec.
+// "Division of Multidimensional Arrays"); cross-queue synchronisation only
+// where a data dependency exists, skipping dependencies already solved by an
+// earlier synchronisation, follows Sec. "Automated Asynchronous Execution".
+#include "jacc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace {
+
+constexpr int kMaxK = 64;
+constexpr int kSlots = 4096;
+constexpr int kEventRing = 16;
+constexpr int64_t kWgCapacity = 1 << 16;  // workgroup partials per partition
+
+struct Range {
+    int64_t lo = 0, hi = 0;
+    bool empty() const { return hi <= lo; }
+};
+inline Range isect(Range a, Range b) { return {std::max(a.lo, b.lo), std::min(a.hi, b.hi)}; }
+inline Range hull(Range a, Range b) {
+    if (a.empty()) return b;
+    if (b.empty()) return a;
+    return {std::min(a.lo, b.lo), std::max(a.hi, b.hi)};
+}
+
+// Sorted set of disjoint half-open intervals.
+struct IntervalSet {
+    std::vector<Range> v;
+    void add(Range r) {
+        if (r.empty()) return;
+        std::vector<Range> out;
+        bool placed = false;
+        for (const Range &x : v) {
+            if (x.hi < r.lo) {
+                out.push_back(x);
+            } else if (r.hi < x.lo) {
+                if (!placed) { out.push_back(r); placed = true; }
+                out.push_back(x);
+            } else {
+                r = {std::min(r.lo, x.lo), std::max(r.hi, x.hi)};
+            }
+        }
+        if (!placed) out.push_back(r);
+        v.swap(out);
+    }
+    void sub(Range r) {
+        if (r.empty()) return;
+        std::vector<Range> out;
+        for (const Range &x : v) {
+            if (x.hi <= r.lo || r.hi <= x.lo) {
+                out.push_back(x);
+                continue;
+            }
+            if (x.lo < r.lo) out.push_back({x.lo, r.lo});
+            if (r.hi < x.hi) out.push_back({r.hi, x.hi});
+        }
+        v.swap(out);
+    }
+    // r minus the set
+    std::vector<Range> missing(Range r) const {
+        std::vector<Range> out;
+        int64_t cur = r.lo;
+        for (const Range &x : v) {
+            if (x.hi <= cur) continue;
+            if (x.lo >= r.hi) break;
+            if (x.lo > cur) out.push_back({cur, std::min(x.lo, r.hi)});
+            cur = std::max(cur, x.hi);
+            if (cur >= r.hi) break;
+        }
+        if (cur < r.hi) out.push_back({cur, r.hi});
+        return out;
+    }
+};
+
+// Piecewise-constant map over [0, E).
+template <class T>
+struct IntervalMap {
+    struct Piece {
+        int64_t lo, hi;
+        T val;
+    };
+    std::vector<Piece> v;
+    void init(int64_t lo, int64_t hi, const T &val) { v.assign(1, Piece{lo, hi, val}); }
+    size_t split(int64_t x) {  // index of the piece starting at x (v.size() if x == end)
+        for (size_t i = 0; i < v.size(); ++i) {
+            if (v[i].lo == x) return i;
+            if (v[i].lo < x && x < v[i].hi) {
+                Piece right = v[i];
+                right.lo = x;
+                v[i].hi = x;
+                v.insert(v.begin() + (long)i + 1, right);
+                return i + 1;
+            }
+        }
+        return v.size();
+    }
+    template <class F>
+    void for_range(Range r, F f) {  // f(Piece&) over the pieces inside r (split at its ends)
+        if (r.empty() || v.empty()) return;
+        r = isect(r, Range{v.front().lo, v.back().hi});
+        if (r.empty()) return;
+        size_t a = split(r.lo);
+        size_t b = split(r.hi);
+        for (size_t i = a; i < b; ++i) f(v[i]);
+    }
+    void assign(Range r, const T &val) {
+        for_range(r, [&](Piece &p) { p.val = val; });
+        coalesce();
+    }
+    void coalesce() {
+        std::vector<Piece> out;
+        for (const Piece &p : v) {
+            if (!out.empty() && out.back().hi == p.lo && out.back().val == p.val)
+                out.back().hi = p.hi;
+            else
+                out.push_back(p);
+        }
+        v.swap(out);
+    }
+};
+
+// Access history of a row interval of one slab: last writer (stream, seq)
+// and, per other stream, the latest read since that write.
+struct Access {
+    int32_t ws = -1;
+    int64_t wseq = 0;
+    std::vector<std::pair<int32_t, int64_t>> reads;
+    bool operator==(const Access &o) const { return ws == o.ws && wseq == o.wseq && reads == o.reads; }
+};
+
+struct Slab {
+    void *dev = nullptr;
+    Range rows;
+    IntervalMap<Access> acc;
+};
+
+struct Array {
+    int id = 0;
+    uintptr_t host = 0;
+    size_t bytes = 0;
+    jacc_array_desc d{};
+    int K = 1;
+    int64_t E = 0, row_elems = 1;
+    size_t esize = 8, row_bytes = 8;
+    int refs = 1;
+    bool whole = false;
+    std::vector<Slab> slabs;
+    IntervalMap<int32_t> writer;  // -1: host data, valid in every holder
+    std::vector<IntervalSet> valid;
+    Range block(int p) const {
+        return {(int64_t)((__int128)p * E / K), (int64_t)((__int128)(p + 1) * E / K)};
+    }
+};
+
+struct EvEntry {
+    hipEvent_t ev = nullptr;
+    int64_t covers = -1;
+    std::vector<int64_t> waited;  // snapshot of the stream's waited[] at record time
+};
+
+struct StreamState {
+    hipStream_t s = nullptr;
+    int64_t seq = 0;
+    int64_t recorded = 0;
+    std::vector<EvEntry> ring;
+    int ring_next = 0;
+    std::vector<int64_t> waited;  // waited[q]: ops of stream q known complete before our next op
+};
+
+size_t dtype_size(int dt) {
+    switch (dt) {
+        case JACC_F64: return 8;
+        case JACC_F32: return 4;
+        case JACC_I32: return 4;
+        case JACC_I64: return 8;
+        default: return 0;
+    }
+}
+
+}  // namespace
+
+struct jacc_ctx {
+    int K = 1;
+    unsigned flags = 0;
+    bool dry = false, tracing = false, serialize = false;
+    jacc_allocator alloc{};
+    bool use_hipmalloc = true;
+    bool own_streams = false;
+    std::vector<StreamState> st;
+    std::map<uintptr_t, Array *> present;
+    int next_id = 0;
+    int status = JACC_OK;
+    std::string err;
+    std::vector<jacc_trace_op> trace;
+    uintptr_t fake_next = (uintptr_t)1 << 44;
+    // reductions
+    double *slots = nullptr;        // kSlots doubles
+    double *partials = nullptr;     // kMaxK doubles
+    double *wg = nullptr;           // K * kWgCapacity doubles
+    int64_t combine_seq = 0;        // seq (on stream 0) of the last combine (readers of partials)
+    std::vector<int64_t> slot_seq;  // seq on stream 0 that produced each slot
+    // fault injection (tests): fail the n-th op of a kind
+    int fault_kind = 0;  // 1 copy, 2 launch
+    int64_t fault_n = -1, fault_count = 0;
+};
+
+namespace {
+
+int set_err(jacc_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+    return code;
+}
+
+int dev_fail(jacc_ctx *c, hipError_t e, const char *what) {
+    c->status = JACC_ERR_DEVICE;
+    return set_err(c, JACC_ERR_DEVICE, "%s failed: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+#define HIPCHK(c, expr, what)                          \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return dev_fail(c, e_, what); \
+    } while (0)
+
+void trace(jacc_ctx *c, int op, int stream, int array, int src, int dst, int kind, int64_t lo,
+           int64_t hi, int64_t seq) {
+    if (!c->tracing) return;
+    jacc_trace_op t;
+    t.op = op;
+    t.stream = stream;
+    t.array = array;
+    t.src = src;
+    t.dst = dst;
+    t.kind = kind;
+    t.lo = lo;
+    t.hi = hi;
+    t.seq = seq;
+    c->trace.push_back(t);
+}
+
+int stream_of(const jacc_ctx *c, int p) { return c->serialize ? 0 : p; }
+
+// ---- device memory ------------------------------------------------------
+int dev_alloc(jacc_ctx *c, size_t bytes, void **out) {
+    if (bytes == 0) bytes = 256;
+    if (c->dry && c->use_hipmalloc) {
+        *out = (void *)c->fake_next;
+        c->fake_next += (bytes + 4095) & ~(size_t)4095;
+        return JACC_OK;
+    }
+    void *p = nullptr;
+    if (c->use_hipmalloc) {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_err(c, JACC_ERR_ALLOC, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        }
+    } else {
+        p = c->alloc.alloc(bytes, c->alloc.user);
+        if (!p) return set_err(c, JACC_ERR_ALLOC, "allocator returned NULL for %zu bytes", bytes);
+    }
+    *out = p;
+    return JACC_OK;
+}
+
+void dev_free(jacc_ctx *c, void *p) {
+    if (!p || (c->dry && c->use_hipmalloc)) return;
+    if (c->use_hipmalloc)
+        (void)hipFree(p);
+    else
+        c->alloc.free(p, c->alloc.user);
+}
+
+// ---- streams, events, waits ----------------------------------------------
+int post_op(jacc_ctx *c, int s) {  // after an op has been enqueued on stream s
+    if (c->serialize && !c->dry) HIPCHK(c, hipDeviceSynchronize(), "hipDeviceSynchronize");
+    (void)s;
+    return JACC_OK;
+}
+
+// Make sure an event on stream q covers its op `n`; returns the ring index.
+int ensure_event(jacc_ctx *c, int q, int64_t n, int *idx) {
+    StreamState &S = c->st[q];
+    if (S.recorded < n) {
+        EvEntry &E = S.ring[S.ring_next];
+        if (!c->dry) HIPCHK(c, hipEventRecord(E.ev, S.s), "hipEventRecord");
+        E.covers = S.seq;
+        E.waited = S.waited;
+        S.recorded = S.seq;
+        trace(c, JACC_OP_RECORD, q, -1, -1, -1, 0, 0, 0, S.seq);
+        S.ring_next = (S.ring_next + 1) % kEventRing;
+    }
+    int best = -1;
+    for (int i = 0; i < kEventRing; ++i) {
+        const EvEntry &E = S.ring[i];
+        if (E.covers >= n && (best < 0 || E.covers < S.ring[best].covers)) best = i;
+    }
+    *idx = best;
+    return JACC_OK;
+}
+
+// Stream d must not run its next op before op n of stream q completed.
+int ensure_wait(jacc_ctx *c, int d, int q, int64_t n) {
+    if (d == q || n <= 0) return JACC_OK;
+    StreamState &D = c->st[d];
+    if (D.waited[q] >= n) return JACC_OK;
+    int idx = -1;
+    int rc = ensure_event(c, q, n, &idx);
+    if (rc) return rc;
+    const EvEntry &E = c->st[q].ring[idx];
+    if (!c->dry) HIPCHK(c, hipStreamWaitEvent(D.s, E.ev, 0), "hipStreamWaitEvent");
+    trace(c, JACC_OP_WAIT, d, -1, q, -1, 0, 0, 0, E.covers);
+    D.waited[q] = std::max(D.waited[q], E.covers);
+    for (size_t k = 0; k < E.waited.size(); ++k) D.waited[k] = std::max(D.waited[k], E.waited[k]);
+    return JACC_OK;
+}
+
+// Hazard bookkeeping for an access by stream s (its next op, seq+1) to rows r
+// of slab p of array A.  write: RAW+WAW+WAR waits, then becomes last writer.
+int hazard(jacc_ctx *c, Array *A, int p, Range r, bool write, int s) {
+    if (r.empty()) return JACC_OK;
+    Slab &sl = A->slabs[p];
+    int rc = JACC_OK;
+    std::vector<std::pair<int, int64_t>> need;
+    sl.acc.for_range(r, [&](IntervalMap<Access>::Piece &pc) {
+        if (pc.val.ws >= 0 && pc.val.ws != s) need.push_back({pc.val.ws, pc.val.wseq});
+        if (write)
+            for (auto &rd : pc.val.reads)
+                if (rd.first != s) need.push_back({rd.first, rd.second});
+    });
+    for (auto &w : need) {
+        rc = ensure_wait(c, s, w.first, w.second);
+        if (rc) return rc;
+    }
+    const int64_t next = c->st[s].seq + 1;
+    sl.acc.for_range(r, [&](IntervalMap<Access>::Piece &pc) {
+        if (write) {
+            pc.val.ws = s;
+            pc.val.wseq = next;
+            pc.val.reads.clear();
+        } else if (pc.val.ws != s) {
+            bool found = false;
+            for (auto &rd : pc.val.reads)
+                if (rd.first == s) { rd.second = next; found = true; }
+            if (!found) pc.val.reads.push_back({s, next});
+        }
+    });
+    sl.acc.coalesce();
+    trace(c, JACC_OP_ACCESS, s, A->id, -1, p, write ? 2 : 1, r.lo, r.hi, next);
+    return JACC_OK;
+}
+
+bool inject_fault(jacc_ctx *c, int kind) {
+    if (c->fault_kind != kind) return false;
+    return ++c->fault_count == c->fault_n;
+}
+
+// ---- present table --------------------------------------------------------
+Array *lookup(jacc_ctx *c, const void *host) {
+    uintptr_t a = (uintptr_t)host;
+    auto it = c->present.upper_bound(a);
+    if (it == c->present.begin()) return nullptr;
+    --it;
+    Array *A = it->second;
+    return (a >= A->host && a < A->host + A->bytes) ? A : nullptr;
+}
+
+// ---- copies ------------------------------------------------------------
+// Copy rows r of array A from slab q to slab p, on p's stream.
+int issue_copy(jacc_ctx *c, Array *A, int q, int p, Range r) {
+    const int s = stream_of(c, p);
+    int rc = hazard(c, A, q, r, false, s);
+    if (rc) return rc;
+    rc = hazard(c, A, p, r, true, s);
+    if (rc) return rc;
+    if (inject_fault(c, 1)) {
+        c->status = JACC_ERR_DEVICE;
+        return set_err(c, JACC_ERR_DEVICE, "injected fault in copy %lld", (long long)c->fault_count);
+    }
+    const Slab &src = A->slabs[q];
+    const Slab &dst = A->slabs[p];
+    size_t bytes = (size_t)(r.hi - r.lo) * A->row_bytes;
+    if (!c->dry) {
+        char *sp = (char *)src.dev + (size_t)(r.lo - src.rows.lo) * A->row_bytes;
+        char *dp = (char *)dst.dev + (size_t)(r.lo - dst.rows.lo) * A->row_bytes;
+        HIPCHK(c, hipMemcpyAsync(dp, sp, bytes, hipMemcpyDeviceToDevice, c->st[s].s), "hipMemcpyAsync(D2D)");
+    }
+    c->st[s].seq++;
+    trace(c, JACC_OP_COPY, s, A->id, q, p, 0, r.lo, r.hi, c->st[s].seq);
+    return post_op(c, s);
+}
+
+// Pull into slab p every row of `need` that it does not hold fresh.
+int make_fresh(jacc_ctx *c, Array *A, int p, Range need) {
+    if (need.empty()) return JACC_OK;
+    std::vector<Range> miss = A->valid[p].missing(need);
+    for (const Range &m : miss) {
+        std::vector<std::pair<int, Range>> pieces;
+        A->writer.for_range(m, [&](IntervalMap<int32_t>::Piece &pc) { pieces.push_back({pc.val, {pc.lo, pc.hi}}); });
+        A->writer.coalesce();
+        for (auto &pc : pieces) {
+            int q = pc.first;
+            if (q < 0 || q == p)
+                return set_err(c, JACC_ERR_INVALID, "internal: rows [%lld,%lld) of array %d stale with no writer",
+                               (long long)pc.second.lo, (long long)pc.second.hi, A->id);
+            int rc = issue_copy(c, A, q, p, pc.second);
+            if (rc) return rc;
+        }
+        A->valid[p].add(m);
+    }
+    return JACC_OK;
+}
+
+void note_write(Array *A, int p, Range w) {
+    if (w.empty()) return;
+    A->writer.assign(w, p);
+    for (int q = 0; q < A->K; ++q) {
+        if (q == p) A->valid[q].add(w);
+        else A->valid[q].sub(w);
+    }
+}
+
+// Owner of each row for gathers: the last writer, else the block owner.
+template <class F>
+void for_owner_pieces(Array *A, Range r, F f) {
+    std::vector<std::pair<int, Range>> pieces;
+    A->writer.for_range(r, [&](IntervalMap<int32_t>::Piece &pc) { pieces.push_back({pc.val, {pc.lo, pc.hi}}); });
+    A->writer.coalesce();
+    for (auto &pc : pieces) {
+        if (pc.first >= 0) {
+            f(pc.first, pc.second);
+            continue;
+        }
+        if (A->whole) {
+            f(0, pc.second);
+            continue;
+        }
+        for (int p = 0; p < A->K; ++p) {
+            Range x = isect(pc.second, A->block(p));
+            if (!x.empty()) f(p, x);
+        }
+    }
+}
+
+int sync_stream(jacc_ctx *c, int s) {
+    if (!c->dry) HIPCHK(c, hipStreamSynchronize(c->st[s].s), "hipStreamSynchronize");
+    trace(c, JACC_OP_SYNC, s, -1, -1, -1, 0, 0, 0, c->st[s].seq);
+    return JACC_OK;
+}
+
+int sync_all(jacc_ctx *c) {
+    for (size_t s = 0; s < c->st.size(); ++s) {
+        int rc = sync_stream(c, (int)s);
+        if (rc) return rc;
+    }
+    return JACC_OK;
+}
+
+int h2d_rows(jacc_ctx *c, Array *A, int p, Range r) {
+    const int s = stream_of(c, p);
+    int rc = hazard(c, A, p, r, true, s);
+    if (rc) return rc;
+    const Slab &sl = A->slabs[p];
+    if (!c->dry) {
+        char *dp = (char *)sl.dev + (size_t)(r.lo - sl.rows.lo) * A->row_bytes;
+        const char *hp = (const char *)A->host + (size_t)r.lo * A->row_bytes;
+        HIPCHK(c, hipMemcpyAsync(dp, hp, (size_t)(r.hi - r.lo) * A->row_bytes, hipMemcpyHostToDevice, c->st[s].s),
+               "hipMemcpyAsync(H2D)");
+    }
+    c->st[s].seq++;
+    trace(c, JACC_OP_H2D, s, A->id, -1, p, 0, r.lo, r.hi, c->st[s].seq);
+    return post_op(c, s);
+}
+
+int d2h_rows(jacc_ctx *c, Array *A, int p, Range r) {
+    const int s = stream_of(c, p);
+    int rc = hazard(c, A, p, r, false, s);
+    if (rc) return rc;
+    const Slab &sl = A->slabs[p];
+    if (!c->dry) {
+        const char *sp = (const char *)sl.dev + (size_t)(r.lo - sl.rows.lo) * A->row_bytes;
+        char *hp = (char *)A->host + (size_t)r.lo * A->row_bytes;
+        HIPCHK(c, hipMemcpyAsync(hp, sp, (size_t)(r.hi - r.lo) * A->row_bytes, hipMemcpyDeviceToHost, c->st[s].s),
+               "hipMemcpyAsync(D2H)");
+    }
+    c->st[s].seq++;
+    trace(c, JACC_OP_D2H, s, A->id, p, -1, 0, r.lo, r.hi, c->st[s].seq);
+    return post_op(c, s);
+}
+
+int gather(jacc_ctx *c, Array *A, Range r) {
+    std::vector<char> used(c->st.size(), 0);
+    int rc = JACC_OK;
+    for_owner_pieces(A, r, [&](int p, Range x) {
+        if (rc) return;
+        rc = d2h_rows(c, A, p, x);
+        used[stream_of(c, p)] = 1;
+    });
+    if (rc) return rc;
+    for (size_t s = 0; s < used.size(); ++s)
+        if (used[s]) {
+            rc = sync_stream(c, (int)s);
+            if (rc) return rc;
+        }
+    return JACC_OK;
+}
+
+void free_array(jacc_ctx *c, Array *A) {
+    for (int p = 0; p < A->K; ++p) {
+        trace(c, JACC_OP_FREE, -1, A->id, -1, p, 0, A->slabs[p].rows.lo, A->slabs[p].rows.hi, 0);
+        dev_free(c, A->slabs[p].dev);
+    }
+    delete A;
+}
+
+bool desc_equal(const jacc_array_desc &a, const jacc_array_desc &b) {
+    if (a.dtype != b.dtype || a.ndim != b.ndim || a.halo_lo != b.halo_lo || a.halo_hi != b.halo_hi ||
+        a.whole != b.whole || a.num_partitions != b.num_partitions)
+        return false;
+    for (int i = 0; i < a.ndim; ++i)
+        if (a.extent[i] != b.extent[i]) return false;
+    return true;
+}
+
+// ---- loop kinds: argument tables --------------------------------------------
+struct KindInfo {
+    int nargs;
+    int ndim;
+    int red;  // 0 none, 1 optional, 2 required
+};
+
+bool kind_info(int kind, KindInfo *k) {
+    switch (kind) {
+        case JACC_LOOP_JACOBI2D: *k = {2, 2, 0}; return true;
+        case JACC_LOOP_HEAT3D: *k = {2, 3, 1}; return true;
+        case JACC_LOOP_SUM: *k = {1, 1, 2}; return true;
+        case JACC_LOOP_GEMM: *k = {3, 2, 0}; return true;
+        case JACC_LOOP_SPMV_CSR: *k = {5, 1, 0}; return true;
+        default: return false;
+    }
+}
+
+struct PartPlan {
+    Range iters;
+    std::vector<Range> rng;  // per argument
+};
+
+#define GUARD(c)                                   \
+    do {                                           \
+        if (!(c)) return JACC_ERR_INVALID;         \
+        if ((c)->status) {                         \
+            return JACC_ERR_DEVICE;                \
+        }                                          \
+    } while (0)
+
+int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc_arg *args,
+              const double *scalars, int nscalars, int slot, double *red_host, const jacc_config *cfg) {
+    KindInfo ki;
+    if (!kind_info(kind, &ki)) return set_err(c, JACC_ERR_INVALID, "unknown loop kind %d", kind);
+    if (!b || nargs != ki.nargs || !args)
+        return set_err(c, JACC_ERR_INVALID, "loop kind %d takes %d arguments and bounds", kind, ki.nargs);
+    if (b->ndim != ki.ndim) return set_err(c, JACC_ERR_INVALID, "loop kind %d takes %d-D bounds", kind, ki.ndim);
+    for (int d = 0; d < b->ndim; ++d)
+        if (b->lo[d] < 0 || b->hi[d] < b->lo[d]) return set_err(c, JACC_ERR_INVALID, "bad bounds in dim %d", d);
+    if (nscalars < 0 || nscalars > 4 || (nscalars > 0 && !scalars))
+        return set_err(c, JACC_ERR_INVALID, "bad scalars");
+    const bool want_red = slot >= 0 || red_host;
+    if (ki.red == 0 && want_red) return set_err(c, JACC_ERR_INVALID, "loop kind %d has no reduction", kind);
+    if (ki.red == 2 && !want_red) return set_err(c, JACC_ERR_INVALID, "loop kind %d needs a reduction target", kind);
+    if (slot >= kSlots) return set_err(c, JACC_ERR_INVALID, "reduction slot %d out of range", slot);
+    if (kind == JACC_LOOP_HEAT3D && nscalars < 1) return set_err(c, JACC_ERR_INVALID, "HEAT3D needs alpha");
+
+    // resolve arguments
+    Array *arr[8];
+    int K = -1;
+    for (int i = 0; i < nargs; ++i) {
+        if (args[i].mode < JACC_READ || args[i].mode > JACC_READWRITE)
+            return set_err(c, JACC_ERR_INVALID, "argument %d: bad mode", i);
+        if (args[i].off_lo > args[i].off_hi) return set_err(c, JACC_ERR_INVALID, "argument %d: off_lo > off_hi", i);
+        Array *A = lookup(c, args[i].host);
+        if (!A) return set_err(c, JACC_ERR_NOT_PRESENT, "argument %d (%p) is not present", i, args[i].host);
+        if ((uintptr_t)args[i].host != A->host)
+            return set_err(c, JACC_ERR_UNSUPPORTED, "argument %d is an interior pointer of array %d", i, A->id);
+        if (K < 0) K = A->K;
+        if (A->K != K) return set_err(c, JACC_ERR_UNSUPPORTED, "arguments are partitioned with different K");
+        arr[i] = A;
+    }
+    // dtype / shape checks per kind
+    auto is = [&](int i, int dt, int nd) { return arr[i]->d.dtype == dt && arr[i]->d.ndim == nd; };
+    jk::Launch L{};
+    L.kind = kind;
+    L.ndim = b->ndim;
+    L.nargs = nargs;
+    for (int i = 0; i < nscalars; ++i) L.scalars[i] = scalars[i];
+    for (int i = 0; i < 4; ++i) L.ext[i] = arr[0]->d.extent[i];
+    int primary = -1;  // the argument whose owner blocks split the iterations
+    switch (kind) {
+        case JACC_LOOP_JACOBI2D:
+            if (!is(0, JACC_F64, 2) || !is(1, JACC_F64, 2) || arr[0]->d.extent[0] != arr[1]->d.extent[0] ||
+                arr[0]->d.extent[1] != arr[1]->d.extent[1])
+                return set_err(c, JACC_ERR_INVALID, "JACOBI2D takes two FP64 2-D arrays of equal shape");
+            if (b->hi[0] > arr[0]->E - 1 || b->lo[0] < 1 || b->lo[1] < 1 || b->hi[1] > arr[0]->d.extent[1] - 1)
+                return set_err(c, JACC_ERR_RANGE, "JACOBI2D bounds must lie inside the interior");
+            primary = 1;
+            break;
+        case JACC_LOOP_HEAT3D:
+            if (!is(0, JACC_F64, 3) || !is(1, JACC_F64, 3))
+                return set_err(c, JACC_ERR_INVALID, "HEAT3D takes two FP64 3-D arrays");
+            for (int d = 0; d < 3; ++d)
+                if (arr[0]->d.extent[d] != arr[1]->d.extent[d])
+                    return set_err(c, JACC_ERR_INVALID, "HEAT3D arrays differ in shape");
+            for (int d = 0; d < 3; ++d)
+                if (b->lo[d] < 1 || b->hi[d] > arr[0]->d.extent[d] - 1)
+                    return set_err(c, JACC_ERR_RANGE, "HEAT3D bounds must lie inside the interior");
+            primary = 1;
+            break;
+        case JACC_LOOP_SUM:
+            if (arr[0]->d.dtype != JACC_F64) return set_err(c, JACC_ERR_INVALID, "SUM takes an FP64 array");
+            if (b->hi[0] > arr[0]->E) return set_err(c, JACC_ERR_RANGE, "SUM bounds exceed the array");
+            primary = 0;
+            break;
+        case JACC_LOOP_GEMM:
+            if (!is(0, JACC_F64, 2) || !is(1, JACC_F64, 2) || !is(2, JACC_F64, 2))
+                return set_err(c, JACC_ERR_INVALID, "GEMM takes three FP64 2-D arrays");
+            if (arr[0]->d.extent[1] != arr[1]->d.extent[0] || arr[0]->d.extent[0] != arr[2]->d.extent[0] ||
+                arr[1]->d.extent[1] != arr[2]->d.extent[1])
+                return set_err(c, JACC_ERR_INVALID, "GEMM shapes do not conform");
+            if (b->hi[0] > arr[2]->d.extent[0] || b->hi[1] > arr[2]->d.extent[1])
+                return set_err(c, JACC_ERR_RANGE, "GEMM bounds exceed C");
+            primary = 2;
+            break;
+        case JACC_LOOP_SPMV_CSR:
+            if (!is(0, JACC_I32, 1) || !is(1, JACC_I32, 1) || !is(2, JACC_F64, 1) || !is(3, JACC_F64, 1) ||
+                !is(4, JACC_F64, 1))
+                return set_err(c, JACC_ERR_INVALID, "SPMV_CSR takes int32 row_ptr, int32 col, f64 val, x, y");
+            if (arr[0]->E != arr[4]->E + 1 || arr[1]->E != arr[2]->E)
+                return set_err(c, JACC_ERR_INVALID, "SPMV_CSR: row_ptr must have n+1 entries and col/val match");
+            if (b->hi[0] > arr[4]->E) return set_err(c, JACC_ERR_RANGE, "SPMV_CSR bounds exceed y");
+            primary = 4;
+            break;
+    }
+    if (!(args[primary].mode & JACC_WRITE) && kind != JACC_LOOP_SUM)
+        return set_err(c, JACC_ERR_INVALID, "the output argument must be declared writable");
+
+    // plan: iteration sub-range and per-argument rows for every partition
+    Array *P = arr[primary];
+    std::vector<PartPlan> plan(K);
+    for (int p = 0; p < K; ++p) {
+        Range own = P->whole ? Range{p == 0 ? 0 : 0, p == 0 ? P->E : 0} : P->block(p);
+        plan[p].iters = isect({b->lo[0], b->hi[0]}, own);
+        plan[p].rng.resize(nargs);
+        for (int i = 0; i < nargs; ++i) {
+            Range r{};
+            if (!plan[p].iters.empty()) {
+                if (args[i].whole)
+                    r = {0, arr[i]->E};
+                else
+                    r = isect({plan[p].iters.lo + args[i].off_lo, plan[p].iters.hi - 1 + args[i].off_hi + 1},
+                              {0, arr[i]->E});
+            }
+            plan[p].rng[i] = r;
+            if (r.empty()) continue;
+            const Range sl = arr[i]->slabs[p].rows;
+            if (r.lo < sl.lo || r.hi > sl.hi)
+                return set_err(c, JACC_ERR_RANGE,
+                               "partition %d: argument %d touches rows [%lld,%lld) outside its slab [%lld,%lld)", p, i,
+                               (long long)r.lo, (long long)r.hi, (long long)sl.lo, (long long)sl.hi);
+            if ((args[i].mode & JACC_WRITE) && !arr[i]->whole) {
+                Range own_i = arr[i]->block(p);
+                if (r.lo < own_i.lo || r.hi > own_i.hi)
+                    return set_err(c, JACC_ERR_RANGE,
+                                   "partition %d: argument %d writes rows [%lld,%lld) outside its owner block", p, i,
+                                   (long long)r.lo, (long long)r.hi);
+            }
+        }
+    }
+    // writes of one array by two partitions, or a read of rows another
+    // partition writes in the same loop (the paper duplicates such loops)
+    for (int i = 0; i < nargs; ++i) {
+        if (!(args[i].mode & JACC_WRITE)) continue;
+        for (int j = 0; j < nargs; ++j) {
+            if (arr[j] != arr[i]) continue;
+            for (int p = 0; p < K; ++p)
+                for (int q = 0; q < K; ++q) {
+                    if (p == q) continue;
+                    if (!isect(plan[p].rng[i], plan[q].rng[j]).empty())
+                        return set_err(c, JACC_ERR_RANGE,
+                                       "partitions %d and %d overlap on array %d (aliased write ranges)", p, q,
+                                       arr[i]->id);
+                }
+        }
+    }
+    // configuration
+    jk::Cfg cf{0, 0, 0, 0, 0};
+    if (cfg) cf = {cfg->bx, cfg->by, cfg->tile, cfg->vec, cfg->persistent};
+    L.cfg = jk::default_config(kind, L, cf);
+    if (jk::check_config(L) != 0)
+        return set_err(c, JACC_ERR_INVALID, "configuration bx=%d by=%d tile=%d vec=%d not valid for kind %d", L.cfg.bx,
+                       L.cfg.by, L.cfg.tile, L.cfg.vec, kind);
+
+    // issue
+    uint64_t active = 0;
+    for (int p = 0; p < K; ++p) {
+        const PartPlan &pp = plan[p];
+        if (pp.iters.empty()) continue;
+        const int s = stream_of(c, p);
+        int rc;
+        // bring every read row up to date
+        for (int i = 0; i < nargs; ++i)
+            if (args[i].mode & JACC_READ) {
+                rc = make_fresh(c, arr[i], p, pp.rng[i]);
+                if (rc) return rc;
+            }
+        // hazards of the kernel's own accesses
+        for (int i = 0; i < nargs; ++i) {
+            if (args[i].mode & JACC_READ) {
+                rc = hazard(c, arr[i], p, pp.rng[i], false, s);
+                if (rc) return rc;
+            }
+            if (args[i].mode & JACC_WRITE) {
+                rc = hazard(c, arr[i], p, pp.rng[i], true, s);
+                if (rc) return rc;
+            }
+        }
+        if (want_red) {  // partials[p] is read by the previous combine on stream 0
+            rc = ensure_wait(c, s, stream_of(c, 0), c->combine_seq);
+            if (rc) return rc;
+        }
+        jk::Launch LP = L;
+        LP.lo[0] = pp.iters.lo;
+        LP.hi[0] = pp.iters.hi;
+        for (int d = 1; d < b->ndim; ++d) {
+            LP.lo[d] = b->lo[d];
+            LP.hi[d] = b->hi[d];
+        }
+        for (int i = 0; i < nargs; ++i) {
+            const Slab &sl = arr[i]->slabs[p];
+            LP.a[i].ptr = (const char *)sl.dev - (intptr_t)((size_t)sl.rows.lo * arr[i]->row_bytes);
+            LP.a[i].slab_lo = sl.rows.lo;
+            LP.a[i].slab_hi = sl.rows.hi;
+            LP.a[i].row_elems = arr[i]->row_elems;
+        }
+        if (want_red) {
+            LP.wg_partials = c->wg + (size_t)p * kWgCapacity;
+            LP.wg_capacity = kWgCapacity;
+            LP.part_out = c->partials + p;
+            if (jk::reduction_workgroups(LP) > kWgCapacity)
+                return set_err(c, JACC_ERR_UNSUPPORTED, "reduction needs more than %lld workgroups",
+                               (long long)kWgCapacity);
+            active |= (uint64_t)1 << p;
+        }
+        if (inject_fault(c, 2)) {
+            c->status = JACC_ERR_DEVICE;
+            return set_err(c, JACC_ERR_DEVICE, "injected fault in launch %lld", (long long)c->fault_count);
+        }
+        if (!c->dry) HIPCHK(c, jk::launch_loop(LP, c->st[s].s), "kernel launch");
+        c->st[s].seq++;
+        trace(c, JACC_OP_KERNEL, s, -1, -1, p, kind, pp.iters.lo, pp.iters.hi, c->st[s].seq);
+        rc = post_op(c, s);
+        if (rc) return rc;
+        if (c->st.size() > 1) {  // precise event for the partitions that will read these rows
+            int idx;
+            rc = ensure_event(c, s, c->st[s].seq, &idx);
+            if (rc) return rc;
+        }
+        for (int i = 0; i < nargs; ++i)
+            if (args[i].mode & JACC_WRITE) note_write(arr[i], p, pp.rng[i]);
+    }
+    if (want_red) {
+        const int s0 = stream_of(c, 0);
+        for (int p = 0; p < K; ++p)
+            if (active >> p & 1) {
+                int rc = ensure_wait(c, s0, stream_of(c, p), c->st[stream_of(c, p)].seq);
+                if (rc) return rc;
+            }
+        int sl = slot >= 0 ? slot : kSlots - 1;  // a synchronous-only reduction uses the last slot
+        if (!c->dry) {
+            if (active == 0)
+                HIPCHK(c, hipMemsetAsync(c->slots + sl, 0, sizeof(double), c->st[s0].s), "hipMemsetAsync");
+            else
+                HIPCHK(c, jk::launch_combine(c->partials, active, c->slots + sl, c->st[s0].s), "combine launch");
+        }
+        c->st[s0].seq++;
+        c->combine_seq = c->st[s0].seq;
+        c->slot_seq[sl] = c->st[s0].seq;
+        trace(c, JACC_OP_COMBINE, s0, -1, -1, -1, sl, 0, 0, c->st[s0].seq);
+        int rc = post_op(c, s0);
+        if (rc) return rc;
+        if (red_host) {
+            rc = sync_stream(c, s0);
+            if (rc) return rc;
+            if (!c->dry)
+                HIPCHK(c, hipMemcpy(red_host, c->slots + sl, sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy(D2H)");
+            else
+                *red_host = 0.0;
+        }
+    }
+    return JACC_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char *jacc_version(void) { return "jacc-mi355x 0.1 (gfx950)"; }
+
+int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator *alloc, unsigned flags) {
+    if (!out) return JACC_ERR_INVALID;
+    *out = nullptr;
+    if (K < 1 || K > kMaxK) return JACC_ERR_INVALID;
+    if (alloc && (!alloc->alloc || !alloc->free)) return JACC_ERR_INVALID;
+    jacc_ctx *c = nullptr;
+    try {
+        c = new jacc_ctx();
+        c->K = K;
+        c->flags = flags;
+        c->dry = (flags & JACC_INIT_DRYRUN) != 0;
+        c->tracing = (flags & JACC_INIT_TRACE) != 0;
+        c->serialize = (flags & JACC_INIT_SERIALIZE) != 0;
+        if (alloc) {
+            c->alloc = *alloc;
+            c->use_hipmalloc = false;
+        }
+        if (const char *f = getenv("JACC_FAULT_INJECT")) {
+            // "<copy|launch>:<n>"
+            const char *colon = strchr(f, ':');
+            if (colon) {
+                if (!strncmp(f, "copy", 4)) c->fault_kind = 1;
+                if (!strncmp(f, "launch", 6)) c->fault_kind = 2;
+                c->fault_n = atoll(colon + 1);
+            }
+        }
+        const int nstreams = c->serialize ? 1 : K;
+        c->st.resize(nstreams);
+        c->own_streams = (streams == nullptr);
+        for (int s = 0; s < nstreams; ++s) {
+            StreamState &S = c->st[s];
+            S.waited.assign(nstreams, 0);
+            S.ring.resize(kEventRing);
+            if (c->dry) continue;
+            if (streams)
+                S.s = (hipStream_t)streams[s];
+            else {
+                hipError_t e = hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking);
+                if (e != hipSuccess) {
+                    int rc = dev_fail(c, e, "hipStreamCreateWithFlags");
+                    jacc_finalize(c);
+                    return rc;
+                }
+            }
+            for (auto &E : S.ring) {
+                hipError_t e = hipEventCreateWithFlags(&E.ev, hipEventDisableTiming);
+                if (e != hipSuccess) {
+                    int rc = dev_fail(c, e, "hipEventCreateWithFlags");
+                    jacc_finalize(c);
+                    return rc;
+                }
+            }
+        }
+        c->slot_seq.assign(kSlots, 0);
+        int rc = dev_alloc(c, kSlots * sizeof(double), (void **)&c->slots);
+        if (!rc) rc = dev_alloc(c, kMaxK * sizeof(double), (void **)&c->partials);
+        if (!rc) rc = dev_alloc(c, (size_t)K * kWgCapacity * sizeof(double), (void **)&c->wg);
+        if (rc) {
+            jacc_finalize(c);
+            return rc;
+        }
+        if (!c->dry) {
+            hipError_t e = hipMemset(c->slots, 0, kSlots * sizeof(double));
+            if (e != hipSuccess) {
+                int rc2 = dev_fail(c, e, "hipMemset");
+                jacc_finalize(c);
+                return rc2;
+            }
+        }
+    } catch (const std::bad_alloc &) {
+        delete c;
+        return JACC_ERR_ALLOC;
+    } catch (...) {
+        delete c;
+        return JACC_ERR_INVALID;
+    }
+    *out = c;
+    return JACC_OK;
+}
+
+int jacc_finalize(jacc_ctx *c) {
+    if (!c) return JACC_ERR_INVALID;
+    int status = c->status;
+    try {
+        if (!c->dry)
+            for (auto &S : c->st)
+                if (S.s) (void)hipStreamSynchronize(S.s);
+        for (auto &kv : c->present) free_array(c, kv.second);
+        c->present.clear();
+        dev_free(c, c->slots);
+        dev_free(c, c->partials);
+        dev_free(c, c->wg);
+        if (!c->dry) {
+            for (auto &S : c->st) {
+                for (auto &E : S.ring)
+                    if (E.ev) (void)hipEventDestroy(E.ev);
+                if (c->own_streams && S.s) (void)hipStreamDestroy(S.s);
+            }
+        }
+    } catch (...) {
+    }
+    delete c;
+    return status;
+}
+
+int jacc_data_enter(jacc_ctx *c, void *host, const jacc_array_desc *d, int clause) {
+    GUARD(c);
+    try {
+        if (!host || !d) return set_err(c, JACC_ERR_INVALID, "NULL host pointer or descriptor");
+        if (clause != JACC_COPYIN && clause != JACC_CREATE && clause != JACC_COPY)
+            return set_err(c, JACC_ERR_INVALID, "bad clause %d", clause);
+        size_t es = dtype_size(d->dtype);
+        if (!es || d->ndim < 1 || d->ndim > 4) return set_err(c, JACC_ERR_INVALID, "bad dtype or ndim");
+        int64_t row = 1;
+        for (int i = 0; i < d->ndim; ++i) {
+            if (d->extent[i] < 1) return set_err(c, JACC_ERR_INVALID, "extent[%d] < 1", i);
+            if (i > 0) row *= d->extent[i];
+        }
+        if (d->halo_lo < 0 || d->halo_hi < 0) return set_err(c, JACC_ERR_INVALID, "negative halo");
+        int K = d->num_partitions ? d->num_partitions : c->K;
+        if (K < 1 || K > c->K) return set_err(c, JACC_ERR_INVALID, "num_partitions %d not in [1,%d]", K, c->K);
+        if (!d->whole && K > d->extent[0])
+            return set_err(c, JACC_ERR_INVALID, "K=%d exceeds the %lld rows of dim 0", K, (long long)d->extent[0]);
+        size_t bytes = (size_t)d->extent[0] * (size_t)row * es;
+        if (Array *A = lookup(c, host)) {
+            if (A->host == (uintptr_t)host && A->bytes == bytes && desc_equal(A->d, *d)) {
+                A->refs++;
+                return JACC_OK;
+            }
+            return set_err(c, JACC_ERR_ALREADY_PRESENT, "host range overlaps array %d with another descriptor", A->id);
+        }
+        {  // a new range must not overlap a later array either
+            auto it = c->present.lower_bound((uintptr_t)host);
+            if (it != c->present.end() && it->first < (uintptr_t)host + bytes)
+                return set_err(c, JACC_ERR_ALREADY_PRESENT, "host range overlaps array %d", it->second->id);
+        }
+        Array *A = new Array();
+        A->id = c->next_id++;
+        A->host = (uintptr_t)host;
+        A->bytes = bytes;
+        A->d = *d;
+        A->K = K;
+        A->E = d->extent[0];
+        A->row_elems = row;
+        A->esize = es;
+        A->row_bytes = (size_t)row * es;
+        A->whole = d->whole != 0;
+        A->slabs.resize(K);
+        A->valid.resize(K);
+        A->writer.init(0, A->E, -1);
+        int rc = JACC_OK;
+        for (int p = 0; p < K && !rc; ++p) {
+            Range sl{0, A->E};
+            if (!A->whole) {
+                Range bl = A->block(p);
+                sl = {std::max<int64_t>(0, bl.lo - d->halo_lo), std::min<int64_t>(A->E, bl.hi + d->halo_hi)};
+            }
+            A->slabs[p].rows = sl;
+            A->slabs[p].acc.init(sl.lo, sl.hi, Access{});
+            A->valid[p].add(sl);
+            rc = dev_alloc(c, (size_t)(sl.hi - sl.lo) * A->row_bytes, &A->slabs[p].dev);
+            if (!rc) trace(c, JACC_OP_ALLOC, -1, A->id, -1, p, 0, sl.lo, sl.hi, 0);
+        }
+        if (rc) {
+            for (int p = 0; p < K; ++p) dev_free(c, A->slabs[p].dev);
+            delete A;
+            return rc;
+        }
+        c->present[A->host] = A;
+        if (clause == JACC_COPYIN || clause == JACC_COPY) {
+            for (int p = 0; p < K; ++p) {
+                rc = h2d_rows(c, A, p, A->slabs[p].rows);
+                if (rc) return rc;
+            }
+        }
+        return JACC_OK;
+    } catch (const std::bad_alloc &) {
+        return set_err(c, JACC_ERR_ALLOC, "host allocation failed");
+    } catch (...) {
+        return set_err(c, JACC_ERR_INVALID, "internal error");
+    }
+}
+
+int jacc_data_exit(jacc_ctx *c, void *host, int clause) {
+    GUARD(c);
+    try {
+        if (clause != JACC_COPYOUT && clause != JACC_DELETE) return set_err(c, JACC_ERR_INVALID, "bad clause %d", clause);
+        Array *A = lookup(c, host);
+        if (!A) return set_err(c, JACC_ERR_NOT_PRESENT, "%p is not present", host);
+        int rc = JACC_OK;
+        if (clause == JACC_COPYOUT) {
+            rc = gather(c, A, {0, A->E});
+            if (rc) return rc;
+        }
+        if (--A->refs > 0) return JACC_OK;
+        rc = sync_all(c);
+        if (rc) return rc;
+        c->present.erase(A->host);
+        free_array(c, A);
+        return JACC_OK;
+    } catch (...) {
+        return set_err(c, JACC_ERR_INVALID, "internal error");
+    }
+}
+
+int jacc_update(jacc_ctx *c, void *host, int dir, int64_t row_lo, int64_t row_hi) {
+    GUARD(c);
+    try {
+        Array *A = lookup(c, host);
+        if (!A) return set_err(c, JACC_ERR_NOT_PRESENT, "%p is not present", host);
+        if (row_hi < 0) row_hi = A->E;
+        if (row_lo < 0 || row_lo > row_hi || row_hi > A->E)
+            return set_err(c, JACC_ERR_INVALID, "bad row range [%lld,%lld)", (long long)row_lo, (long long)row_hi);
+        Range r{row_lo, row_hi};
+        if (r.empty()) return JACC_OK;
+        if (dir == JACC_UPDATE_HOST) return gather(c, A, r);
+        if (dir != JACC_UPDATE_DEVICE) return set_err(c, JACC_ERR_INVALID, "bad direction %d", dir);
+        for (int p = 0; p < A->K; ++p) {
+            Range x = isect(r, A->slabs[p].rows);
+            if (x.empty()) continue;
+            int rc = h2d_rows(c, A, p, x);
+            if (rc) return rc;
+            A->valid[p].add(x);
+        }
+        A->writer.assign(r, -1);
+        return JACC_OK;
+    } catch (...) {
+        return set_err(c, JACC_ERR_INVALID, "internal error");
+    }
+}
+
+int jacc_parallel_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc_arg *args,
+                       const double *scalars, int nscalars, int reduce_slot, double *reduce_host,
+                       const jacc_config *cfg) {
+    GUARD(c);
+    try {
+        return loop_impl(c, kind, b, nargs, args, scalars, nscalars, reduce_slot, reduce_host, cfg);
+    } catch (const std::bad_alloc &) {
+        return set_err(c, JACC_ERR_ALLOC, "host allocation failed");
+    } catch (...) {
+        return set_err(c, JACC_ERR_INVALID, "internal error");
+    }
+}
+
+int jacc_wait(jacc_ctx *c) {
+    GUARD(c);
+    return sync_all(c);
+}
+
+int jacc_reduction_get(jacc_ctx *c, int slot, double *out) {
+    GUARD(c);
+    if (slot < 0 || slot >= kSlots || !out) return set_err(c, JACC_ERR_INVALID, "bad slot or output");
+    int rc = sync_stream(c, 0);
+    if (rc) return rc;
+    if (c->dry) {
+        *out = 0.0;
+        return JACC_OK;
+    }
+    HIPCHK(c, hipMemcpy(out, c->slots + slot, sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy(D2H)");
+    return JACC_OK;
+}
+
+int jacc_reduction_read(jacc_ctx *c, int first, int count, double *out) {
+    GUARD(c);
+    if (first < 0 || count < 0 || first + count > kSlots || (count && !out))
+        return set_err(c, JACC_ERR_INVALID, "bad slot range");
+    int rc = sync_all(c);
+    if (rc) return rc;
+    if (!count) return JACC_OK;
+    if (c->dry) {
+        memset(out, 0, (size_t)count * sizeof(double));
+        return JACC_OK;
+    }
+    HIPCHK(c, hipMemcpy(out, c->slots + first, (size_t)count * sizeof(double), hipMemcpyDeviceToHost),
+           "hipMemcpy(D2H)");
+    return JACC_OK;
+}
+
+const char *jacc_last_error(const jacc_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+
+int jacc_slab_info(jacc_ctx *c, void *host, int p, void **dev, int64_t *row_lo, int64_t *row_hi) {
+    if (!c) return JACC_ERR_INVALID;
+    Array *A = lookup(c, host);
+    if (!A) return set_err(c, JACC_ERR_NOT_PRESENT, "%p is not present", host);
+    if (p < 0 || p >= A->K) return set_err(c, JACC_ERR_INVALID, "bad partition %d", p);
+    if (dev) *dev = A->slabs[p].dev;
+    if (row_lo) *row_lo = A->slabs[p].rows.lo;
+    if (row_hi) *row_hi = A->slabs[p].rows.hi;
+    return JACC_OK;
+}
+
+int jacc_trace_len(const jacc_ctx *c) { return c ? (int)c->trace.size() : 0; }
+
+int jacc_trace_get(const jacc_ctx *c, int i, jacc_trace_op *out) {
+    if (!c || !out || i < 0 || i >= (int)c->trace.size()) return JACC_ERR_INVALID;
+    *out = c->trace[(size_t)i];
+    return JACC_OK;
+}
+
+int jacc_trace_clear(jacc_ctx *c) {
+    if (!c) return JACC_ERR_INVALID;
+    c->trace.clear();
+    return JACC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,324 @@
+"""ctypes binding of libjacc.so (the C ABI in include/jacc.h).
+
+Argument marshalling only: every step of every loop runs in the library's
+HIP kernels and C++ runtime.  PyTorch supplies device memory (through the
+allocator callback) and the K HIP streams.  The library must be built
+in-tree (``python -m paper_2110_14340_amd.build``); loading fails loudly
+when it is missing — there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjacc.so")
+
+# ---- constants mirrored from jacc.h --------------------------------------
+OK, ERR_INVALID, ERR_NOT_PRESENT, ERR_ALREADY_PRESENT, ERR_RANGE, ERR_ALLOC, ERR_DEVICE, ERR_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6, -7
+F64, F32, I32, I64 = 0, 1, 2, 3
+COPYIN, CREATE, COPY = 1, 2, 3
+COPYOUT, DELETE = 1, 2
+UPDATE_HOST, UPDATE_DEVICE = 1, 2
+READ, WRITE, READWRITE = 1, 2, 3
+JACOBI2D, HEAT3D, SUM, GEMM, SPMV_CSR = 1, 2, 3, 4, 5
+INIT_DRYRUN, INIT_TRACE, INIT_SERIALIZE = 1, 2, 4
+OP_NAMES = {1: "ALLOC", 2: "FREE", 3: "H2D", 4: "D2H", 5: "COPY", 6: "KERNEL", 7: "RECORD", 8: "WAIT",
+            9: "SYNC", 10: "COMBINE", 11: "ACCESS"}
+STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOT_PRESENT", -3: "ALREADY_PRESENT", -4: "RANGE", -5: "ALLOC",
+                -6: "DEVICE", -7: "UNSUPPORTED"}
+
+_DTYPES = {np.dtype(np.float64): F64, np.dtype(np.float32): F32, np.dtype(np.int32): I32,
+           np.dtype(np.int64): I64}
+
+
+class ArrayDesc(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("ndim", ctypes.c_int32), ("extent", ctypes.c_int64 * 4),
+                ("halo_lo", ctypes.c_int32), ("halo_hi", ctypes.c_int32), ("whole", ctypes.c_int32),
+                ("num_partitions", ctypes.c_int32)]
+
+
+class Arg(ctypes.Structure):
+    _fields_ = [("host", ctypes.c_void_p), ("mode", ctypes.c_int32), ("off_lo", ctypes.c_int32),
+                ("off_hi", ctypes.c_int32), ("whole", ctypes.c_int32)]
+
+
+class Bounds(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("pad_", ctypes.c_int32), ("lo", ctypes.c_int64 * 3),
+                ("hi", ctypes.c_int64 * 3)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("vec", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+
+
+class Allocator(ctypes.Structure):
+    ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+    FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+    _fields_ = [("alloc", ALLOC), ("free", FREE), ("user", ctypes.c_void_p)]
+
+
+class TraceOp(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("stream", ctypes.c_int32), ("array", ctypes.c_int32),
+                ("src", ctypes.c_int32), ("dst", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("lo", ctypes.c_int64), ("hi", ctypes.c_int64), ("seq", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libjacc.so and declare its signatures; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2110_14340_amd.build` "
+                           "(there is no non-HIP fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    L.jacc_version.restype = ctypes.c_char_p
+    L.jacc_init.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(Allocator), ctypes.c_uint]
+    L.jacc_finalize.argtypes = [vp]
+    L.jacc_data_enter.argtypes = [vp, vp, ctypes.POINTER(ArrayDesc), i32]
+    L.jacc_data_exit.argtypes = [vp, vp, i32]
+    L.jacc_update.argtypes = [vp, vp, i32, i64, i64]
+    L.jacc_parallel_loop.argtypes = [vp, i32, ctypes.POINTER(Bounds), i32, ctypes.POINTER(Arg),
+                                     ctypes.POINTER(ctypes.c_double), i32, i32, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(Config)]
+    L.jacc_wait.argtypes = [vp]
+    L.jacc_reduction_get.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
+    L.jacc_reduction_read.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
+    L.jacc_last_error.argtypes = [vp]
+    L.jacc_last_error.restype = ctypes.c_char_p
+    L.jacc_slab_info.argtypes = [vp, vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.jacc_trace_len.argtypes = [vp]
+    L.jacc_trace_get.argtypes = [vp, i32, ctypes.POINTER(TraceOp)]
+    L.jacc_trace_clear.argtypes = [vp]
+    _lib = L
+    return L
+
+
+class JaccError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def config(bx=0, by=0, tile=0, vec=0, persistent=0):
+    return Config(bx, by, tile, vec, persistent)
+
+
+def bounds(*pairs):
+    b = Bounds()
+    b.ndim = len(pairs)
+    for d, (lo, hi) in enumerate(pairs):
+        b.lo[d] = lo
+        b.hi[d] = hi
+    return b
+
+
+class TorchAllocator:
+    """Device memory from PyTorch's caching allocator (uint8 tensors kept
+    alive until the library frees them)."""
+
+    def __init__(self, device="cuda"):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.live = {}
+        self._a = Allocator.ALLOC(self._alloc)
+        self._f = Allocator.FREE(self._free)
+        self.struct = Allocator(self._a, self._f, None)
+
+    def _alloc(self, nbytes, user):
+        try:
+            t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device=self.device)
+        except Exception:
+            return None
+        self.live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _free(self, ptr, user):
+        self.live.pop(ptr, None)
+
+
+class Context:
+    """One runtime context with K partitions.
+
+    streams: None (library-created streams), "torch" (K new torch streams,
+    default priority) or a list of K torch streams.
+    allocator: "torch" (PyTorch caching allocator) or "hip" (hipMalloc).
+    """
+
+    def __init__(self, K, streams="torch", allocator="torch", flags=0):
+        self.L = lib()
+        self.K = K
+        self.flags = flags
+        self._keep = []
+        self.streams = None
+        sp = None
+        if flags & INIT_DRYRUN:
+            streams = None
+            if allocator == "torch":
+                allocator = "hip"
+        if streams == "torch":
+            import torch
+            self.streams = [torch.cuda.Stream() for _ in range(K)]
+        elif streams is not None:
+            self.streams = list(streams)
+        if self.streams is not None:
+            arr = (ctypes.c_void_p * K)(*[s.cuda_stream for s in self.streams])
+            self._keep.append(arr)
+            sp = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+        ap = None
+        if allocator == "torch":
+            self.allocator = TorchAllocator()
+            ap = ctypes.byref(self.allocator.struct)
+        elif allocator != "hip":  # any object with a ctypes Allocator in .struct
+            self.allocator = allocator
+            ap = ctypes.byref(allocator.struct)
+        self.ctx = ctypes.c_void_p()
+        st = self.L.jacc_init(ctypes.byref(self.ctx), K, sp, ap, flags)
+        if st != OK:
+            raise JaccError(st, "jacc_init failed")
+        self.arrays = {}
+
+    # -- helpers ---------------------------------------------------------
+    def _check(self, st):
+        if st != OK:
+            raise JaccError(st, self.L.jacc_last_error(self.ctx).decode())
+        return st
+
+    def status(self, st):
+        """Status name of a raw return code (for tests of error paths)."""
+        return STATUS_NAMES.get(st, st)
+
+    @staticmethod
+    def _ptr(a):
+        return a.ctypes.data
+
+    def close(self):
+        if self.ctx:
+            st = self.L.jacc_finalize(self.ctx)
+            self.ctx = ctypes.c_void_p()
+            self.arrays.clear()
+            return st
+        return OK
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- data ----------------------------------------------------------------
+    def enter(self, a, halo=(0, 0), whole=False, K=0, clause=COPYIN, raw=False):
+        assert a.flags.c_contiguous
+        d = ArrayDesc()
+        d.dtype = _DTYPES[a.dtype]
+        d.ndim = a.ndim
+        for i, e in enumerate(a.shape):
+            d.extent[i] = e
+        d.halo_lo, d.halo_hi = halo
+        d.whole = int(whole)
+        d.num_partitions = K
+        st = self.L.jacc_data_enter(self.ctx, self._ptr(a), ctypes.byref(d), clause)
+        if raw:
+            return st
+        self._check(st)
+        self.arrays[self._ptr(a)] = a
+        return st
+
+    def exit(self, a, clause=COPYOUT, raw=False):
+        st = self.L.jacc_data_exit(self.ctx, self._ptr(a), clause)
+        return st if raw else self._check(st)
+
+    def update(self, a, direction, lo=0, hi=-1, raw=False):
+        st = self.L.jacc_update(self.ctx, self._ptr(a), direction, lo, hi)
+        return st if raw else self._check(st)
+
+    # -- loops ---------------------------------------------------------------
+    def loop(self, kind, bnds, args, scalars=(), slot=-1, sync=False, cfg=None, raw=False):
+        """args: list of (array, mode, off_lo, off_hi, whole)."""
+        n = len(args)
+        A = (Arg * n)()
+        for i, (a, mode, lo, hi, whole) in enumerate(args):
+            A[i] = Arg(self._ptr(a) if isinstance(a, np.ndarray) else a, mode, lo, hi, int(whole))
+        S = (ctypes.c_double * max(1, len(scalars)))(*scalars)
+        out = ctypes.c_double(0.0)
+        st = self.L.jacc_parallel_loop(self.ctx, kind, ctypes.byref(bnds), n, A, S, len(scalars), slot,
+                                       ctypes.byref(out) if sync else None,
+                                       ctypes.byref(cfg) if cfg is not None else None)
+        if raw:
+            return st
+        self._check(st)
+        return out.value if sync else None
+
+    # convenience wrappers for the loop kinds (declared access ranges)
+    def jacobi2d(self, u_in, u_out, rows=None, cols=None, cfg=None, raw=False):
+        ny, nx = u_in.shape
+        b = bounds(rows or (1, ny - 1), cols or (1, nx - 1))
+        return self.loop(JACOBI2D, b, [(u_in, READ, -1, 1, 0), (u_out, WRITE, 0, 0, 0)], cfg=cfg, raw=raw)
+
+    def heat3d(self, u_in, u_out, alpha, slot=-1, sync=False, cfg=None, raw=False):
+        nz, ny, nx = u_in.shape
+        b = bounds((1, nz - 1), (1, ny - 1), (1, nx - 1))
+        return self.loop(HEAT3D, b, [(u_in, READ, -1, 1, 0), (u_out, WRITE, 0, 0, 0)], scalars=(alpha,),
+                         slot=slot, sync=sync, cfg=cfg, raw=raw)
+
+    def sum(self, x, squares=False, slot=-1, sync=True, rows=None, raw=False):
+        b = bounds(rows or (0, x.shape[0]))
+        return self.loop(SUM, b, [(x, READ, 0, 0, 0)], scalars=(1.0 if squares else 0.0,), slot=slot,
+                         sync=sync, raw=raw)
+
+    def gemm(self, A, B, C, raw=False):
+        b = bounds((0, C.shape[0]), (0, C.shape[1]))
+        return self.loop(GEMM, b, [(A, READ, 0, 0, 0), (B, READ, 0, 0, 1), (C, WRITE, 0, 0, 0)], raw=raw)
+
+    def spmv(self, rp, col, val, x, y, raw=False):
+        b = bounds((0, y.shape[0]))
+        return self.loop(SPMV_CSR, b, [(rp, READ, 0, 1, 0), (col, READ, 0, 0, 1), (val, READ, 0, 0, 1),
+                                       (x, READ, 0, 0, 1), (y, WRITE, 0, 0, 0)], raw=raw)
+
+    # -- sync / reductions -----------------------------------------------------
+    def wait(self):
+        return self._check(self.L.jacc_wait(self.ctx))
+
+    def reduction(self, slot):
+        out = ctypes.c_double()
+        self._check(self.L.jacc_reduction_get(self.ctx, slot, ctypes.byref(out)))
+        return out.value
+
+    def reductions(self, first, count):
+        out = np.zeros(count, dtype=np.float64)
+        self._check(self.L.jacc_reduction_read(self.ctx, first, count,
+                                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def slab(self, a, p):
+        dev = ctypes.c_void_p()
+        lo = ctypes.c_int64()
+        hi = ctypes.c_int64()
+        self._check(self.L.jacc_slab_info(self.ctx, self._ptr(a), p, ctypes.byref(dev), ctypes.byref(lo),
+                                          ctypes.byref(hi)))
+        return dev.value, lo.value, hi.value
+
+    def last_error(self):
+        return self.L.jacc_last_error(self.ctx).decode()
+
+    # -- trace -----------------------------------------------------------------
+    def trace(self):
+        n = self.L.jacc_trace_len(self.ctx)
+        out = []
+        t = TraceOp()
+        for i in range(n):
+            self.L.jacc_trace_get(self.ctx, i, ctypes.byref(t))
+            out.append({"op": OP_NAMES[t.op], "stream": t.stream, "array": t.array, "src": t.src, "dst": t.dst,
+                        "kind": t.kind, "lo": t.lo, "hi": t.hi, "seq": t.seq})
+        return out
+
+    def trace_clear(self):
+        self.L.jacc_trace_clear(self.ctx)

@@ -1,0 +1,139 @@
+"""GPU parity of the reduction, contraction and SpMV loop bodies against the
+CPU oracle, at the stated tolerances (sum: 1e-13 relative to the sum of
+magnitudes; GEMM: 1e-12 * ||A||_F ||B||_F in Frobenius norm, exact for
+integer-valued inputs; SpMV: 1e-13 relative to each row's sum of
+magnitudes)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_14340_amd import inputs, jacc
+from gpu_util import context, say
+
+pytestmark = pytest.mark.gpu
+
+
+# ------------------------------------------------------------------ sum
+@pytest.mark.parametrize("n,K", [(1, 1), (1000, 1), (1000, 3), (123_457, 4), (2_000_003, 8)])
+def test_sum_small(n, K):
+    say(f"sum n={n} K={K}")
+    x = inputs.uniform(n, seed=n, lo=-1.0, hi=1.0)
+    ref = oracle.sum_(x)
+    mag = float(np.abs(x).sum())
+    with context(K) as c:
+        c.enter(x)
+        s = c.sum(x)
+        sq = c.sum(x, squares=True)
+    assert abs(s - ref) <= 1e-13 * mag
+    assert abs(sq - oracle.sum_(x, squares=True)) <= 1e-13 * float((x * x).sum())
+
+
+def test_sum_512_cubed_k1_k4():
+    say("sum 512^3 K=1,4")
+    x = inputs.uniform((512, 512, 512), seed=7)
+    ref = oracle.sum_(x)
+    for K in (1, 4):
+        with context(K) as c:
+            c.enter(x)
+            s = c.sum(x)
+        assert abs(s - ref) <= 1e-13 * ref
+
+
+def test_sum_integer_exact_and_deferred_slots():
+    say("sum integer exact")
+    x = (np.arange(1 << 20) % 1024).astype(np.float64)
+    with context(2) as c:
+        c.enter(x)
+        c.sum(x, slot=5, sync=False)
+        c.sum(x, squares=True, slot=6, sync=False)
+        vals = c.reductions(5, 2)
+    assert vals[0] == (1 << 10) * (1023 * 1024 // 2)
+    assert vals[1] == (1 << 10) * sum(i * i for i in range(1024))
+
+
+# ------------------------------------------------------------------ GEMM
+def _gemm_dev(A, B, K):
+    C = np.zeros((A.shape[0], B.shape[1]))
+    with context(K) as c:
+        c.enter(A)
+        c.enter(B, whole=True)
+        c.enter(C, clause=jacc.CREATE)
+        c.gemm(A, B, C)
+        c.exit(C, jacc.COPYOUT)
+    return C
+
+
+@pytest.mark.parametrize("M,N,L,K", [(64, 64, 16, 1), (200, 150, 130, 1), (200, 150, 130, 3),
+                                     (129, 257, 33, 2), (1, 5, 7, 1), (300, 17, 1000, 4)])
+def test_gemm_small_frobenius_and_integer_exact(M, N, L, K):
+    say(f"gemm {M}x{N}x{L} K={K}")
+    A, B = inputs.gemm_inputs(M, N, L, seed=3)
+    ref = oracle.gemm(A, B)
+    C = _gemm_dev(A, B, K)
+    assert np.linalg.norm(C - ref) <= 1e-12 * np.linalg.norm(A) * np.linalg.norm(B)
+    Ai, Bi = inputs.gemm_inputs(M, N, L, seed=4, integer=True)
+    assert np.array_equal(_gemm_dev(Ai, Bi, K), oracle.gemm(Ai, Bi))
+
+
+def test_gemm_4096_sampled_rows():
+    say("gemm 4096^3 K=1 and K=4, sampled rows")
+    n = 4096
+    A, B = inputs.gemm_inputs(n, n, n, seed=3)
+    C1 = _gemm_dev(A, B, 1)
+    C4 = _gemm_dev(A, B, 4)
+    assert np.array_equal(C1, C4)  # no split-k: partitioning never changes an element's sum order
+    rows = [0, 1023, 1024, 2047, 4095]
+    for r in rows:
+        ref = oracle.gemm_rows(A, B, r, r + 1)
+        assert np.linalg.norm(C4[r] - ref[0]) <= 1e-12 * np.linalg.norm(A[r]) * np.linalg.norm(B)
+    Ai, Bi = inputs.gemm_inputs(n, n, n, seed=5, integer=True)
+    Ci = _gemm_dev(Ai, Bi, 4)
+    for r in rows:
+        assert np.array_equal(Ci[r], oracle.gemm_rows(Ai, Bi, r, r + 1)[0])
+
+
+# ------------------------------------------------------------------ SpMV
+def _spmv_dev(rp, col, val, x, K):
+    y = np.zeros(rp.size - 1)
+    with context(K) as c:
+        c.enter(rp, halo=(1, 1))
+        c.enter(col, whole=True)
+        c.enter(val, whole=True)
+        c.enter(x, whole=True)
+        c.enter(y, clause=jacc.CREATE)
+        c.spmv(rp, col, val, x, y)
+        c.exit(y, jacc.COPYOUT)
+    return y
+
+
+def _row_bound(rp, col, val, x):
+    absx = np.abs(val * x[col])
+    cs = np.concatenate([[0.0], np.cumsum(absx)])
+    return cs[rp[1:]] - cs[rp[:-1]]
+
+
+@pytest.mark.parametrize("n,K", [(1, 1), (100, 1), (1000, 3), (5000, 4)])
+def test_spmv_small(n, K):
+    say(f"spmv n={n} K={K}")
+    rp, col, val, x = inputs.csr_matrix(n, n, 16, seed=8)
+    ref = oracle.spmv_csr(rp, col, val, x)
+    y = _spmv_dev(rp, col, val, x, K)
+    assert np.all(np.abs(y - ref) <= 1e-13 * _row_bound(rp, col, val, x))
+    rpi, coli, vali, _ = inputs.csr_matrix(n, n, 16, seed=9, integer_values=True)
+    xi = inputs.int_valued(n, seed=10, lo=-10, hi=10)
+    assert np.array_equal(_spmv_dev(rpi, coli, vali, xi, K), oracle.spmv_csr(rpi, coli, vali, xi))
+
+
+def test_spmv_2_22_rows_k1_k4():
+    say("spmv 2^22 rows K=1,4")
+    n = 1 << 22
+    rp, col, val, x = inputs.csr_matrix(n, n, 16, seed=4)
+    y1 = _spmv_dev(rp, col, val, x, 1)
+    y4 = _spmv_dev(rp, col, val, x, 4)
+    assert np.array_equal(y1, y4)
+    bound = _row_bound(rp, col, val, x)
+    for lo in (0, n // 4 - 3, n // 2, n - 100):
+        ref = oracle.spmv_csr(rp, col, val, x, rows=(lo, lo + 100))
+        assert np.all(np.abs(y4[lo:lo + 100] - ref[lo:lo + 100]) <= 1e-13 * bound[lo:lo + 100])

@@ -1,0 +1,105 @@
+"""GPU parity of the stencil loop bodies and of their K-partitioned runs
+against the CPU oracle (bit-exact: floating-point contraction is off on
+both sides and the operation order is the same)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_14340_amd import inputs, jacc
+from gpu_util import run_heat, run_jacobi, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _cfg(bx, by, tile, vec):
+    return jacc.config(bx=bx, by=by, tile=tile, vec=vec)
+
+
+# ------------------------------------------------------------------ Jacobi
+@pytest.mark.parametrize("K", [1, 4])
+def test_jacobi_512_100_steps_bit_exact(K):
+    say(f"jacobi 512^2 T=100 K={K}")
+    u0 = inputs.jacobi_grid(512, 512, seed=0)
+    ref = oracle.jacobi2d(u0, 100)
+    out = run_jacobi(u0, 100, K)
+    assert np.array_equal(out, ref)
+
+
+@pytest.mark.parametrize("shape,K,cfg", [
+    ((37, 29), 1, None), ((37, 29), 3, None), ((130, 67), 5, _cfg(64, 2, 3, 1)),
+    ((200, 258), 7, _cfg(128, 1, 5, 2)), ((64, 1030), 2, _cfg(64, 4, 1, 2)),
+    ((9, 9), 7, _cfg(64, 1, 1, 1)), ((300, 130), 4, _cfg(256, 4, 64, 2)),
+])
+def test_jacobi_ragged_shapes_partitions_configs(shape, K, cfg):
+    say(f"jacobi ragged {shape} K={K}")
+    u0 = inputs.jacobi_grid(*shape, seed=11)
+    u0[0, :] = 0.75  # a nonzero boundary row must be held, not overwritten
+    T = 6
+    ref = oracle.jacobi2d(u0, T)
+    out = run_jacobi(u0, T, K, cfg=cfg)
+    assert np.array_equal(out, ref)
+
+
+def test_jacobi_constant_and_linear_fields_exact_on_device():
+    say("jacobi fixed points")
+    c = np.full((66, 70), 0.3)
+    assert np.array_equal(run_jacobi(c, 5, 3), c)
+    i, j = np.meshgrid(np.arange(66), np.arange(70), indexing="ij")
+    lin = (4096.0 * i - 3.0 * j + 7.0).astype(np.float64)
+    assert np.array_equal(run_jacobi(lin, 5, 2), lin)
+
+
+def test_jacobi_8192_1000_steps_k8_equals_k1_and_sampled_oracle():
+    say("jacobi 8192^2 T=1000 K=1 and K=8")
+    u0 = inputs.jacobi_grid(8192, 8192, seed=1)
+    T = 1000
+    out1 = run_jacobi(u0, T, 1)
+    out8 = run_jacobi(u0, T, 8)
+    assert np.array_equal(out1, out8)
+    # sampled outputs computed one window at a time by the oracle: the row
+    # block boundaries of K=8 partitions and a corner
+    for (r0, c0) in [(1020, 4090), (6140, 8180), (0, 0)]:
+        say(f"  window at ({r0},{c0})")
+        ref = oracle.jacobi2d_window(u0, T, (r0, r0 + 8), (c0, c0 + 8))
+        assert np.array_equal(out8[r0:r0 + 8, c0:c0 + 8], ref)
+
+
+# ------------------------------------------------------------------ Heat
+def _rel_close(a, b, tol=1e-13):
+    return np.all(np.abs(a - b) <= tol * np.abs(b))
+
+
+@pytest.mark.parametrize("shape,K,cfg", [
+    ((34, 29, 40), 1, None), ((34, 29, 40), 4, None), ((19, 17, 67), 3, _cfg(64, 2, 3, 1)),
+    ((40, 12, 130), 2, _cfg(64, 1, 7, 2)), ((10, 70, 66), 4, _cfg(128, 4, 1, 2)),
+])
+def test_heat_small_bit_exact_and_residual(shape, K, cfg):
+    say(f"heat {shape} K={K}")
+    u0 = inputs.heat_field(*shape, seed=2)
+    T = 5
+    ref, ref_res = oracle.heat3d(u0, T, 0.1)
+    out, res = run_heat(u0, T, 0.1, K, cfg=cfg)
+    assert np.array_equal(out, ref)
+    assert _rel_close(res, ref_res)
+
+
+def test_heat_512_100_steps_k4():
+    say("heat 512^3 T=100 K=4 and K=1")
+    u0 = inputs.heat_field(512, 512, 512, seed=2)
+    T = 100
+    out4, res4 = run_heat(u0, T, 0.1, 4)
+    out1, res1 = run_heat(u0, T, 0.1, 1)
+    assert np.array_equal(out4, out1)
+    assert _rel_close(res4, res1)
+    # oracle at full size for the first two steps (field and residuals)
+    say("  oracle 2 steps at full size")
+    ref2, ref_res2 = oracle.heat3d(u0, 2, 0.1)
+    out2, res2 = run_heat(u0, 2, 0.1, 4)
+    assert np.array_equal(out2, ref2)
+    assert _rel_close(res2, ref_res2)
+    # sampled windows of the 100-step field at slab boundaries
+    for (z0, y0, x0) in [(127, 250, 300), (383, 0, 504)]:
+        say(f"  window at ({z0},{y0},{x0})")
+        ref = oracle.heat3d_window(u0, T, 0.1, (z0, z0 + 4), (y0, y0 + 4), (x0, x0 + 8))
+        assert np.array_equal(out4[z0:z0 + 4, y0:y0 + 4, x0:x0 + 8], ref)
+    assert np.all(np.diff(res4) <= 0)  # the explicit scheme is a contraction

@@ -1,0 +1,332 @@
+"""Host-side tests of the runtime (no GPU): the library loads and exports
+every symbol include/jacc.h declares; in dry-run mode (plan and trace only,
+no HIP call) the partition plan equals the brute-force set model, every
+trace is race-free and every kernel read is fresh, every emitted wait is
+needed, and the error paths return their documented status codes."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+from oracle import plan as P
+from paper_2110_14340_amd import jacc
+from trace_check import freshness_check, race_check
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DRY = jacc.INIT_DRYRUN | jacc.INIT_TRACE
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "jacc.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(jacc_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = jacc.lib()
+    syms = header_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(L, s), s
+    out = subprocess.run(["nm", "-D", "--defined-only", jacc.LIB_PATH], capture_output=True, text=True).stdout
+    for s in syms:
+        assert re.search(rf"\bT {s}$", out, flags=re.M), s
+    assert b"gfx950" in L.jacc_version()
+
+
+def test_library_is_built_for_gfx950():
+    out = subprocess.run(["strings", jacc.LIB_PATH], capture_output=True, text=True).stdout
+    assert "gfx950" in out
+
+
+# ------------------------------------------------------------------ plan
+def dry(K):
+    return jacc.Context(K, flags=DRY)
+
+
+def _loop_trace(c, fn):
+    c.trace_clear()
+    fn()
+    return c.trace()
+
+
+def test_jacobi_k8_plan_matches_model_and_counts():
+    E = 64
+    c = dry(8)
+    a = np.zeros((E, 16))
+    b = np.zeros((E, 16))
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    model = {"a": P.ArrayState(E, 8, 1, 1), "b": P.ArrayState(E, 8, 1, 1)}
+    names = {id(a): "a", id(b): "b"}
+    src, dst = a, b
+    full = c.trace()
+    for step in range(4):
+        tr = _loop_trace(c, lambda: c.jacobi2d(src, dst))
+        full += tr
+        ps = P.plan_loop(model, 1, E - 1, [(names[id(src)], "r", -1, 1, False), (names[id(dst)], "w", 0, 0, False)])
+        kernels = [t for t in tr if t["op"] == "KERNEL"]
+        assert [(t["dst"], t["lo"], t["hi"]) for t in kernels] == \
+            [(p, min(pp["I"]), max(pp["I"]) + 1) for p, pp in enumerate(ps)]
+        copies = sorted((t["dst"], t["src"], t["lo"], t["hi"]) for t in tr if t["op"] == "COPY")
+        want = sorted((p, s, lo, hi) for p, pp in enumerate(ps) for (_, s, lo, hi) in pp["copies"])
+        assert copies == want
+        assert len(copies) == (0 if step == 0 else 14)
+        waits = [t for t in tr if t["op"] == "WAIT"]
+        assert len(waits) <= 2 * 8
+        src, dst = dst, src
+    assert race_check(full) == []
+    assert freshness_check(full) == []
+
+
+@settings(max_examples=60, deadline=None)
+@given(E=st.integers(3, 24), K=st.integers(1, 6), hl=st.integers(0, 2), hh=st.integers(0, 2),
+       steps=st.integers(1, 4), data=st.data())
+def test_random_loop_sequences_match_model(E, K, hl, hh, steps, data):
+    K = min(K, E)
+    c = dry(K)
+    a = np.zeros((E, 3))
+    b = np.zeros((E, 3))
+    c.enter(a, halo=(hl, hh))
+    c.enter(b, halo=(hl, hh))
+    model = {"a": P.ArrayState(E, K, hl, hh), "b": P.ArrayState(E, K, hl, hh)}
+    arrays = {"a": a, "b": b}
+    full = c.trace()
+    for _ in range(steps):
+        rd = data.draw(st.sampled_from(["a", "b"]))
+        wr = "b" if rd == "a" else "a"
+        olo = data.draw(st.integers(-hl, 0))
+        ohi = data.draw(st.integers(0, hh))
+        lb = data.draw(st.integers(0, E))
+        ub = data.draw(st.integers(lb, E))
+        args = [(arrays[rd], jacc.READ, olo, ohi, 0), (arrays[wr], jacc.WRITE, 0, 0, 0)]
+        c.trace_clear()
+        # the SUM kind has one read argument; use a dedicated two-argument
+        # stencil-shaped loop through the JACOBI2D checks instead only when
+        # its bounds are interior; otherwise exercise the generic planner
+        # via SUM reads (read-only) on `rd`
+        st_rc = c.loop(jacc.SUM, jacc.bounds((lb, ub)), [(arrays[rd], jacc.READ, olo, ohi, 0)],
+                       scalars=(0.0,), slot=0, raw=True)
+        try:
+            ps = P.plan_loop(model, lb, ub, [(rd, "r", olo, ohi, False)])
+        except ValueError:
+            assert st_rc == jacc.ERR_RANGE
+            continue
+        assert st_rc == jacc.OK, c.last_error()
+        tr = c.trace()
+        full += tr
+        kernels = [(t["dst"], t["lo"], t["hi"]) for t in tr if t["op"] == "KERNEL"]
+        assert kernels == [(p, min(pp["I"]), max(pp["I"]) + 1) for p, pp in enumerate(ps) if pp["I"]]
+        # now a write of `wr` restricted to interior rows so that a later
+        # read needs copies
+        if 1 <= lb and ub <= E - 1 and E >= 3:
+            c.trace_clear()
+            rc = c.loop(jacc.JACOBI2D, jacc.bounds((lb, ub), (1, 2)),
+                        [(arrays[rd], jacc.READ, -1, 1, 0), (arrays[wr], jacc.WRITE, 0, 0, 0)], raw=True)
+            try:
+                ps = P.plan_loop(model, lb, ub, [(rd, "r", -1, 1, False), (wr, "w", 0, 0, False)])
+            except ValueError:
+                assert rc == jacc.ERR_RANGE
+                continue
+            assert rc == jacc.OK, c.last_error()
+            tr = c.trace()
+            full += tr
+            copies = sorted((t["dst"], t["src"], t["lo"], t["hi"]) for t in tr if t["op"] == "COPY")
+            want = sorted((p, s, lo, hi) for p, pp in enumerate(ps) for (_, s, lo, hi) in pp["copies"])
+            assert copies == want
+    assert race_check(full) == []
+    assert freshness_check(full) == []
+    c.close()
+
+
+def test_every_wait_is_needed():
+    E = 40
+    c = dry(4)
+    a = np.zeros((E, 8))
+    b = np.zeros((E, 8))
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    src, dst = a, b
+    for _ in range(5):
+        c.jacobi2d(src, dst)
+        src, dst = dst, src
+    tr = c.trace()
+    assert race_check(tr) == []
+    nwait = sum(1 for t in tr if t["op"] == "WAIT")
+    assert nwait > 0
+    for i in range(nwait):
+        assert race_check(tr, skip_wait=i) != [], f"wait {i} is not needed"
+
+
+def test_heat_and_reduction_plan_race_free():
+    c = dry(3)
+    u = np.zeros((17, 5, 6))
+    v = np.zeros((17, 5, 6))
+    c.enter(u, halo=(1, 1))
+    c.enter(v, halo=(1, 1))
+    for t in range(4):
+        s, d = (u, v) if t % 2 == 0 else (v, u)
+        c.heat3d(s, d, 0.1, slot=t)
+    c.update(u, jacc.UPDATE_HOST, 3, 12)
+    c.update(v, jacc.UPDATE_DEVICE, 0, 17)
+    c.heat3d(v, u, 0.1)
+    c.exit(u)
+    c.exit(v)
+    tr = c.trace()
+    assert race_check(tr) == []
+    assert freshness_check(tr) == []
+    combines = [t for t in tr if t["op"] == "COMBINE"]
+    assert [t["kind"] for t in combines] == [0, 1, 2, 3]
+
+
+def test_gemm_and_spmv_whole_arrays_plan():
+    c = dry(4)
+    A = np.zeros((33, 7))
+    B = np.zeros((7, 9))
+    C = np.zeros((33, 9))
+    c.enter(A)
+    c.enter(B, whole=True)
+    c.enter(C, clause=jacc.CREATE)
+    c.gemm(A, B, C)
+    n = 50
+    rp = np.zeros(n + 1, dtype=np.int32)
+    col = np.zeros(3, dtype=np.int32)
+    val = np.zeros(3)
+    x = np.zeros(n)
+    y = np.zeros(n)
+    c.enter(rp, halo=(1, 1))
+    c.enter(col, whole=True)
+    c.enter(val, whole=True)
+    c.enter(x, whole=True)
+    c.enter(y, clause=jacc.CREATE)
+    c.spmv(rp, col, val, x, y)
+    c.exit(C)
+    c.exit(y)
+    tr = c.trace()
+    kern = [t for t in tr if t["op"] == "KERNEL"]
+    assert [(t["lo"], t["hi"]) for t in kern[:4]] == [P.block(33, 4, p) for p in range(4)]
+    assert [(t["lo"], t["hi"]) for t in kern[4:]] == [P.block(50, 4, p) for p in range(4)]
+    assert not [t for t in tr if t["op"] == "COPY"]
+    # B is replicated: every partition's slab holds all 7 rows
+    allocs = [t for t in tr if t["op"] == "ALLOC" and t["array"] == 1]
+    assert all((t["lo"], t["hi"]) == (0, 7) for t in allocs)
+    assert race_check(tr) == [] and freshness_check(tr) == []
+
+
+def test_update_host_gathers_from_latest_writers():
+    c = dry(4)
+    a = np.zeros((20, 4))
+    b = np.zeros((20, 4))
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    c.jacobi2d(a, b)
+    c.trace_clear()
+    c.update(b, jacc.UPDATE_HOST, 2, 18)
+    d2h = [(t["src"], t["lo"], t["hi"]) for t in c.trace() if t["op"] == "D2H"]
+    assert d2h == [(0, 2, 5), (1, 5, 10), (2, 10, 15), (3, 15, 18)]
+
+
+# ------------------------------------------------------------------ errors
+def test_error_statuses():
+    c = dry(4)
+    a = np.zeros((16, 8))
+    b = np.zeros((16, 8))
+    other = np.zeros((16, 8))
+    assert c.enter(a, halo=(1, 1), raw=True) == jacc.OK
+    assert c.enter(b, halo=(0, 0), raw=True) == jacc.OK
+    # read rows outside the slab: halo not declared on b
+    assert c.jacobi2d(b, a, raw=True) == jacc.ERR_RANGE
+    assert "outside its slab" in c.last_error()
+    # not present
+    assert c.jacobi2d(a, other, raw=True) == jacc.ERR_NOT_PRESENT
+    # the same array read with a halo and written (aliasing): partitions overlap
+    assert c.jacobi2d(a, a, raw=True) == jacc.ERR_RANGE
+    # interior pointer as a loop argument
+    bn = jacc.bounds((1, 15), (1, 7))
+    rc = c.loop(jacc.JACOBI2D, bn, [(a.ctypes.data + 8, jacc.READ, -1, 1, 0), (b, jacc.WRITE, 0, 0, 0)], raw=True)
+    assert rc == jacc.ERR_UNSUPPORTED
+    # bad kind, argument count, bounds, config
+    assert c.loop(99, bn, [(a, jacc.READ, 0, 0, 0)], raw=True) == jacc.ERR_INVALID
+    assert c.loop(jacc.JACOBI2D, bn, [(a, jacc.READ, -1, 1, 0)], raw=True) == jacc.ERR_INVALID
+    assert c.loop(jacc.JACOBI2D, jacc.bounds((0, 16), (1, 7)), [(a, jacc.READ, -1, 1, 0), (b, jacc.WRITE, 0, 0, 0)],
+                  raw=True) == jacc.ERR_RANGE
+    assert c.jacobi2d(a, b, cfg=jacc.config(bx=100), raw=True) == jacc.ERR_INVALID
+    assert c.jacobi2d(a, b, cfg=jacc.config(vec=3), raw=True) == jacc.ERR_INVALID
+    # repeated enter: same descriptor bumps the count; another descriptor fails
+    assert c.enter(a, halo=(1, 1), raw=True) == jacc.OK
+    assert c.enter(a, halo=(2, 2), raw=True) == jacc.ERR_ALREADY_PRESENT
+    assert c.exit(a, raw=True) == jacc.OK
+    assert c.exit(a, raw=True) == jacc.OK
+    assert c.exit(a, raw=True) == jacc.ERR_NOT_PRESENT
+    # partitions with different K
+    d = np.zeros((16, 8))
+    assert c.enter(d, halo=(1, 1), K=2, raw=True) == jacc.OK
+    c.enter(a, halo=(1, 1))
+    assert c.jacobi2d(a, d, raw=True) == jacc.ERR_UNSUPPORTED
+    # K larger than the rows of dim 0
+    small = np.zeros((3, 8))
+    assert c.enter(small, raw=True) == jacc.ERR_INVALID
+    # reductions need a target
+    x = np.zeros(10)
+    c.enter(x)
+    assert c.loop(jacc.SUM, jacc.bounds((0, 10)), [(x, jacc.READ, 0, 0, 0)], raw=True) == jacc.ERR_INVALID
+    assert c.close() == jacc.OK
+
+
+def test_allocator_failure_returns_alloc():
+    class Failing:
+        def __init__(self):
+            self.n = 0
+            self._a = jacc.Allocator.ALLOC(self._alloc)
+            self._f = jacc.Allocator.FREE(lambda p, u: None)
+            self.struct = jacc.Allocator(self._a, self._f, None)
+
+        def _alloc(self, nbytes, user):
+            self.n += 1
+            return None if self.n > 3 else 4096 * self.n
+
+    c = jacc.Context(2, allocator=Failing(), flags=DRY)
+    a = np.zeros((10, 4))
+    assert c.enter(a, raw=True) == jacc.ERR_ALLOC
+    assert c.close() == jacc.OK
+
+
+def test_injected_device_fault_is_sticky():
+    code = r"""
+import numpy as np, sys
+sys.path.insert(0, sys.argv[1])
+from paper_2110_14340_amd import jacc
+c = jacc.Context(4, flags=jacc.INIT_DRYRUN | jacc.INIT_TRACE)
+a = np.zeros((32, 8)); b = np.zeros((32, 8))
+c.enter(a, halo=(1, 1)); c.enter(b, halo=(1, 1))
+c.jacobi2d(a, b)
+rc = c.jacobi2d(b, a, raw=True)
+rc2 = c.jacobi2d(a, b, raw=True)
+rc3 = c.update(a, jacc.UPDATE_HOST, raw=True)
+print(rc, rc2, rc3, c.close())
+"""
+    env = dict(os.environ, JACC_FAULT_INJECT="copy:3")
+    out = subprocess.run([sys.executable, "-c", code, ROOT], capture_output=True, text=True, env=env)
+    assert out.stdout.split() == [str(jacc.ERR_DEVICE)] * 4, out.stderr
+    env = dict(os.environ, JACC_FAULT_INJECT="launch:6")
+    out = subprocess.run([sys.executable, "-c", code, ROOT], capture_output=True, text=True, env=env)
+    assert out.stdout.split() == [str(jacc.ERR_DEVICE)] * 4, out.stderr
+
+
+def test_serialize_mode_uses_one_stream():
+    c = jacc.Context(4, flags=DRY | jacc.INIT_SERIALIZE)
+    a = np.zeros((20, 6))
+    b = np.zeros((20, 6))
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    c.jacobi2d(a, b)
+    c.jacobi2d(b, a)
+    tr = c.trace()
+    assert {t["stream"] for t in tr if t["op"] in ("KERNEL", "COPY")} == {0}
+    assert not [t for t in tr if t["op"] == "WAIT"]
+    assert freshness_check(tr) == []
