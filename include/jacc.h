@@ -219,8 +219,51 @@ int jacc_reduction_get(jacc_ctx *ctx, int slot, double *out);
 int jacc_reduction_read(jacc_ctx *ctx, int first, int count, double *out);
 
 /* Text of the last error on this context (library-owned; valid until the
- * next call on ctx). */
+ * next call on ctx).  jacc_last_error(NULL) gives the reason of the last
+ * failed jacc_init on the calling thread. */
 const char *jacc_last_error(const jacc_ctx *ctx);
+
+/* ---- batches: many loop nests in one captured HIP graph ---------------------
+ * The paper overlaps independent kernels through asynchronous queues to gain
+ * kernel-level parallelism (Sec. "Automated Asynchronous Execution"); here a
+ * whole sequence of loop calls is captured once into a hipGraph (partition
+ * streams forked from and joined back into stream 0) and replayed.
+ *
+ * jacc_batch_begin starts stream capture: the following jacc_parallel_loop
+ * calls are planned as usual (copies, waits, launches) but recorded instead
+ * of executed.  Loops whose configuration has persistent = 1 are not
+ * launched one by one: consecutive independent ones are packed into one
+ * persistent-kernel launch that walks a task table of all their tiles.  No
+ * data_enter/exit, update, wait or synchronous reduction is allowed inside.
+ *
+ * jacc_batch_end closes the capture, instantiates the graph, runs it once
+ * (so the calls take effect exactly once) and returns its id.  It also plans
+ * the calls a second time from the state the first execution leaves; if that
+ * plan issues the same copies, waits and launches, the graph is replay-safe
+ * and jacc_batch_launch may replay it `repeats` more times (otherwise it
+ * returns JACC_ERR_UNSUPPORTED).  Every launch joins all streams into
+ * stream 0 before the graph and forks them after it. */
+int jacc_batch_begin(jacc_ctx *ctx);
+int jacc_batch_end(jacc_ctx *ctx, int *graph_id);
+int jacc_batch_launch(jacc_ctx *ctx, int graph_id, int repeats);
+/* Number of loop calls, persistent groups, and replay safety of a graph. */
+int jacc_batch_info(jacc_ctx *ctx, int graph_id, int *loops, int *persistent_groups, int *replay_safe);
+int jacc_batch_destroy(jacc_ctx *ctx, int graph_id);
+/* Replays a replay-safe graph `warmup` times untimed, then `reps` times,
+ * each timed with HIP events on stream 0; ms[0..reps) receives the times. */
+int jacc_batch_time(jacc_ctx *ctx, int graph_id, int warmup, int reps, double *ms);
+
+/* ---- configuration timing (the autotuner's measurement) --------------------
+ * Runs one loop call `warmup` times, then `reps` times, each timed with HIP
+ * events from a start event on stream 0 (every partition stream waits for
+ * it) to an end event after all partition streams have joined stream 0.
+ * ms[0..reps) receives the times in milliseconds.  A configuration with
+ * persistent = 1 is timed as a one-loop batch.  The paper names auto-tuning
+ * as future work (Sec. "Conclusion"); the selection rule built on these
+ * samples (median, ties to the lowest candidate) lives with the tuner. */
+int jacc_time_loop(jacc_ctx *ctx, int kind, const jacc_bounds *bounds, int nargs, const jacc_arg *args,
+                   const double *scalars, int nscalars, const jacc_config *cfg, int warmup, int reps,
+                   double *ms);
 
 /* Device pointer of partition p's slab of the array containing `host`, and
  * the slab's first and one-past-last rows.  For callers that run their own
@@ -240,8 +283,10 @@ enum {
     JACC_OP_WAIT = 8,    /* stream waits for stream src up to seq */
     JACC_OP_SYNC = 9,    /* host waits for stream */
     JACC_OP_COMBINE = 10, /* reduction combine on stream into slot `kind` */
-    JACC_OP_ACCESS = 11   /* the preceding op on stream touches slab dst of array rows
+    JACC_OP_ACCESS = 11,  /* the op `seq` on stream touches slab dst of array rows
                              [lo,hi): kind 1 = read, 2 = write */
+    JACC_OP_JOIN = 12     /* all streams joined: every later op is ordered after every
+                             earlier op (around graph launches and timed runs) */
 };
 
 typedef struct {

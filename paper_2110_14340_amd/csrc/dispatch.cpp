@@ -39,7 +39,8 @@ Cfg default_config(int kind, const Launch &L, Cfg c) {
 
 int check_config(const Launch &L) {
     const Cfg &c = L.cfg;
-    if (c.persistent) return 1;  // persistent execution only inside a batch
+    if (c.persistent != 0 && c.persistent != 1) return 1;
+    if (c.persistent && L.kind != JACC_LOOP_JACOBI2D && L.kind != JACC_LOOP_HEAT3D) return 1;
     switch (L.kind) {
         case JACC_LOOP_JACOBI2D:
         case JACC_LOOP_HEAT3D:

@@ -54,11 +54,10 @@ finalise_kernel(const double *__restrict__ p, int64_t n, double *__restrict__ ou
     if (threadIdx.x == 0) *out = s;
 }
 
-__global__ void combine_kernel(const double *__restrict__ partials, uint64_t mask, double *__restrict__ out) {
+__global__ void combine_kernel(const double *__restrict__ partials, CombineList list, double *__restrict__ out) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         double s = 0.0;
-        for (int p = 0; p < 64; ++p)
-            if (mask >> p & 1) s += partials[p];
+        for (int k = 0; k < list.n; ++k) s += partials[list.idx[k]];
         *out = s;
     }
 }
@@ -91,8 +90,8 @@ hipError_t launch_finalise(const double *partials, int64_t n, double *out, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_combine(const double *partials, uint64_t mask, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, s, partials, mask, out);
+hipError_t launch_combine(const double *partials, const CombineList &list, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, s, partials, list, out);
     return hipGetLastError();
 }
 

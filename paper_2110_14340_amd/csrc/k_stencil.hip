@@ -1,4 +1,5 @@
-// Stencil loop bodies for gfx950: Jacobi-2D 5-point and heat-3D 7-point.
+// Stencil loop bodies for gfx950: Jacobi-2D 5-point and heat-3D 7-point,
+// and the persistent kernel that runs many small sweeps in one launch.
 //
 // Both stream the array once from HBM: each lane owns VEC consecutive
 // elements of the contiguous (innermost) dimension and marches through
@@ -10,10 +11,15 @@
 // Loads for the next U rows are issued before the current U rows are
 // computed so each lane keeps several 16-byte loads in flight.
 //
-// Arithmetic (with floating-point contraction disabled at build time):
+// A tile is the work of one workgroup; the regular kernels map blockIdx to
+// tiles, the persistent kernel walks a task table's tiles with a fixed
+// grid.  Both call the same tile functions, so results are bit-identical.
+//
+// Arithmetic (floating-point contraction disabled at build time):
 //   Jacobi: out = 0.25 * ((up + down) + (left + right))
 //   Heat:   lap = ((xm + xp) + (ym + yp)) + (zm + zp) - 6.0*u ;  out = u + alpha*lap
 // which is the operation order of the CPU oracle, so results are bit-exact.
+#include "jacc.h"
 #include "k_common.h"
 #include "kernels.h"
 
@@ -23,9 +29,6 @@ namespace {
 
 constexpr int kU = 4;  // rows loaded ahead of the rows being computed
 
-// ---------------------------------------------------------------------------
-// Jacobi-2D
-// ---------------------------------------------------------------------------
 // One ring entry: VEC own values plus, for the two edge lanes of the wave,
 // the element just left (lane 0) or right (lane 63) of the wave's span.
 template <int VEC>
@@ -35,9 +38,8 @@ struct Row {
 };
 
 template <int VEC>
-__device__ __forceinline__ void load_row(const double *__restrict__ in, int64_t row, int64_t nx, int64_t j,
-                                         bool inb, int lane, bool need_l, bool need_r, Row<VEC> &r) {
-    const double *p = in + row * nx + j;
+__device__ __forceinline__ void load_row(const double *__restrict__ p, bool inb, int lane, bool need_l, bool need_r,
+                                         Row<VEC> &r) {
     if (inb) {
         load_vec<VEC>(p, r.v);
     } else {
@@ -49,17 +51,46 @@ __device__ __forceinline__ void load_row(const double *__restrict__ in, int64_t 
     if (lane == kWave - 1 && need_r) r.edge = p[VEC];
 }
 
+// Left/right neighbours of the VEC values of `mid` (cross-lane shuffles; the
+// edge lanes use the element they loaded beside the wave's span).
 template <int VEC>
-__global__ void __launch_bounds__(1024)
-jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t nx, int64_t r_lo, int64_t r_hi,
-                int64_t c_lo, int64_t c_hi, int64_t col0, int tile) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t j = col0 + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
-    const int64_t i0 = r_lo + ((int64_t)blockIdx.y * blockDim.y + threadIdx.y) * tile;
-    if (i0 >= r_hi) return;  // uniform across the wave (one threadIdx.y per wave)
-    const int64_t i1 = i0 + tile < r_hi ? i0 + tile : r_hi;
+__device__ __forceinline__ void horizontal(const Row<VEC> &mid, int lane, double (&left)[VEC], double (&right)[VEC]) {
+    double lprev = __shfl_up(mid.v[VEC - 1], 1, kWave);
+    double rnext = __shfl_down(mid.v[0], 1, kWave);
+    if (lane == 0) lprev = mid.edge;
+    if (lane == kWave - 1) rnext = mid.edge;
+    left[0] = lprev;
+    right[VEC - 1] = rnext;
+#pragma unroll
+    for (int v = 1; v < VEC; ++v) left[v] = mid.v[v - 1];
+#pragma unroll
+    for (int v = 0; v < VEC - 1; ++v) right[v] = mid.v[v + 1];
+}
 
-    const bool inb = j < c_hi + 1 && j < nx;  // lane holds columns needed by the box
+template <int VEC>
+__device__ __forceinline__ void store_masked(double *q, const double (&o)[VEC], bool all, const bool (&comp)[VEC]) {
+    if (all) {
+        store_vec<VEC>(q, o);
+    } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+            if (comp[v]) q[v] = o[v];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi-2D tile: lanes [tx] of row-group [ty] of workgroup tile (bxi, byi)
+// ---------------------------------------------------------------------------
+template <int VEC>
+__device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, double *__restrict__ out, int64_t nx,
+                                            int64_t r_lo, int64_t r_hi, int64_t c_lo, int64_t c_hi, int64_t col0,
+                                            int tile, int64_t bxi, int64_t byi, int tx, int ty, int bdx, int bdy) {
+    const int lane = tx & (kWave - 1);
+    const int64_t j = col0 + (bxi * bdx + tx) * VEC;
+    const int64_t i0 = r_lo + (byi * bdy + ty) * tile;
+    if (i0 >= r_hi) return;  // uniform across the wave (one ty per wave)
+    const int64_t i1 = i0 + tile < r_hi ? i0 + tile : r_hi;
+    const bool inb = j < c_hi + 1 && j < nx;  // lane holds columns the box needs
     bool comp[VEC];
     bool all = true;
 #pragma unroll
@@ -67,8 +98,6 @@ jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t
         comp[v] = (j + v >= c_lo) && (j + v < c_hi);
         all = all && comp[v];
     }
-    // the wave's edge lanes need one more element when they compute the
-    // element next to the wave's span
     const bool need_l = comp[0];
     const bool need_r = comp[VEC - 1];
 
@@ -76,14 +105,14 @@ jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t
 #pragma unroll
     for (int k = 0; k < kU + 2; ++k) {
         const int64_t row = i0 - 1 + k;
-        if (row <= i1) load_row<VEC>(in, row, nx, j, inb, lane, need_l, need_r, r[k]);
+        if (row <= i1) load_row<VEC>(in + row * nx + j, inb, lane, need_l, need_r, r[k]);
     }
     for (int64_t i = i0; i < i1; i += kU) {
         Row<VEC> nxt[kU];
 #pragma unroll
         for (int k = 0; k < kU; ++k) {
             const int64_t row = i + kU + 1 + k;
-            if (row <= i1) load_row<VEC>(in, row, nx, j, inb, lane, need_l, need_r, nxt[k]);
+            if (row <= i1) load_row<VEC>(in + row * nx + j, inb, lane, need_l, need_r, nxt[k]);
         }
 #pragma unroll
         for (int k = 0; k < kU; ++k) {
@@ -91,18 +120,7 @@ jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t
             if (row < i1) {
                 const Row<VEC> &up = r[k], &mid = r[k + 1], &dn = r[k + 2];
                 double left[VEC], right[VEC];
-                // left of v[0] is the previous lane's last value; right of
-                // v[VEC-1] is the next lane's first value
-                double lprev = __shfl_up(mid.v[VEC - 1], 1, kWave);
-                double rnext = __shfl_down(mid.v[0], 1, kWave);
-                if (lane == 0) lprev = mid.edge;
-                if (lane == kWave - 1) rnext = mid.edge;
-                left[0] = lprev;
-                right[VEC - 1] = rnext;
-#pragma unroll
-                for (int v = 1; v < VEC; ++v) left[v] = mid.v[v - 1];
-#pragma unroll
-                for (int v = 0; v < VEC - 1; ++v) right[v] = mid.v[v + 1];
+                horizontal<VEC>(mid, lane, left, right);
                 double o[VEC];
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {
@@ -110,14 +128,7 @@ jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t
                     const double horz = left[v] + right[v];
                     o[v] = 0.25 * (vert + horz);
                 }
-                double *q = out + row * nx + j;
-                if (all) {
-                    store_vec<VEC>(q, o);
-                } else {
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v)
-                        if (comp[v]) q[v] = o[v];
-                }
+                store_masked<VEC>(out + row * nx + j, o, all, comp);
             }
         }
 #pragma unroll
@@ -127,29 +138,95 @@ jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t
     }
 }
 
-// ---------------------------------------------------------------------------
-// Heat-3D (+ optional residual)
-// ---------------------------------------------------------------------------
 template <int VEC>
-struct Col {
-    double v[VEC];
-    double edge;
-};
+__global__ void __launch_bounds__(1024)
+jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t nx, int64_t r_lo, int64_t r_hi,
+                int64_t c_lo, int64_t c_hi, int64_t col0, int tile) {
+    jacobi_tile<VEC>(in, out, nx, r_lo, r_hi, c_lo, c_hi, col0, tile, blockIdx.x, blockIdx.y, threadIdx.x,
+                     threadIdx.y, blockDim.x, blockDim.y);
+}
 
-template <int VEC>
-__device__ __forceinline__ void load_col(const double *__restrict__ in, int64_t z, int64_t y, int64_t ny,
-                                         int64_t nx, int64_t x, bool inb, int lane, bool need_l, bool need_r,
-                                         Col<VEC> &c) {
-    const double *p = in + (z * ny + y) * nx + x;
-    if (inb) {
-        load_vec<VEC>(p, c.v);
-    } else {
+// ---------------------------------------------------------------------------
+// Heat-3D tile: row y = y_lo + byi*bdy + ty, planes [z_lo + bzi*tile, +tile)
+// Returns this lane's sum of (u'-u)^2 when RES.
+// ---------------------------------------------------------------------------
+template <int VEC, bool RES>
+__device__ __forceinline__ double heat_tile(const double *__restrict__ in, double *__restrict__ out, int64_t ny,
+                                            int64_t nx, int64_t z_lo, int64_t z_hi, int64_t y_lo, int64_t y_hi,
+                                            int64_t x_lo, int64_t x_hi, int64_t col0, int tile, double alpha,
+                                            int64_t bxi, int64_t byi, int64_t bzi, int tx, int ty, int bdx, int bdy) {
+    const int lane = tx & (kWave - 1);
+    const int64_t x = col0 + (bxi * bdx + tx) * VEC;
+    const int64_t y = y_lo + byi * bdy + ty;
+    const int64_t z0 = z_lo + bzi * tile;
+    const int64_t z1 = z0 + tile < z_hi ? z0 + tile : z_hi;
+    double acc = 0.0;
+    if (y >= y_hi || z0 >= z1) return acc;  // uniform across the wave
+    const bool inb = x < x_hi + 1 && x < nx;
+    bool comp[VEC];
+    bool all = true;
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) c.v[v] = 0.0;
+    for (int v = 0; v < VEC; ++v) {
+        comp[v] = (x + v >= x_lo) && (x + v < x_hi);
+        all = all && comp[v];
     }
-    c.edge = 0.0;
-    if (lane == 0 && need_l) c.edge = p[-1];
-    if (lane == kWave - 1 && need_r) c.edge = p[VEC];
+    const bool need_l = comp[0];
+    const bool need_r = comp[VEC - 1];
+    const int64_t plane = ny * nx;
+    const double *base = in + y * nx + x;
+
+    Row<VEC> r[kU + 2];
+#pragma unroll
+    for (int k = 0; k < kU + 2; ++k) {
+        const int64_t z = z0 - 1 + k;
+        if (z <= z1) load_row<VEC>(base + z * plane, inb, lane, need_l, need_r, r[k]);
+    }
+    for (int64_t zb = z0; zb < z1; zb += kU) {
+        Row<VEC> nxt[kU];
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            const int64_t z = zb + kU + 1 + k;
+            if (z <= z1) load_row<VEC>(base + z * plane, inb, lane, need_l, need_r, nxt[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            const int64_t z = zb + k;
+            if (z < z1) {
+                const Row<VEC> &zm = r[k], &c = r[k + 1], &zp = r[k + 2];
+                // y neighbours: rows of the same plane (cache hits)
+                double ym[VEC], yp[VEC];
+                const double *pc = base + z * plane;
+                if (inb) {
+                    load_vec<VEC>(pc - nx, ym);
+                    load_vec<VEC>(pc + nx, yp);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) ym[v] = yp[v] = 0.0;
+                }
+                double xm[VEC], xp[VEC];
+                horizontal<VEC>(c, lane, xm, xp);
+                double o[VEC];
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    const double px = xm[v] + xp[v];
+                    const double py = ym[v] + yp[v];
+                    const double pz = zm.v[v] + zp.v[v];
+                    const double lap = ((px + py) + pz) - 6.0 * c.v[v];
+                    o[v] = c.v[v] + alpha * lap;
+                    if (RES && comp[v]) {
+                        const double d = o[v] - c.v[v];
+                        acc += d * d;
+                    }
+                }
+                store_masked<VEC>(out + z * plane + y * nx + x, o, all, comp);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) r[k] = r[kU + k];
+#pragma unroll
+        for (int k = 0; k < kU; ++k) r[2 + k] = nxt[k];
+    }
+    return acc;
 }
 
 template <int VEC, bool RES>
@@ -158,101 +235,54 @@ heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t n
               int64_t z_hi, int64_t y_lo, int64_t y_hi, int64_t x_lo, int64_t x_hi, int64_t col0, int tile,
               double alpha, double *__restrict__ wg_partials) {
     __shared__ double sh[16];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t x = col0 + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
-    const int64_t y = y_lo + (int64_t)blockIdx.y * blockDim.y + threadIdx.y;
-    const int64_t z0 = z_lo + (int64_t)blockIdx.z * tile;
-    const int64_t z1 = z0 + tile < z_hi ? z0 + tile : z_hi;
-    double acc = 0.0;
-    // y is uniform per wave; a wave outside the box does no memory access
-    // but must still take part in the workgroup reduction
-    if (y < y_hi && z0 < z1) {
-        const bool inb = x < x_hi + 1 && x < nx;
-        bool comp[VEC];
-        bool all = true;
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-            comp[v] = (x + v >= x_lo) && (x + v < x_hi);
-            all = all && comp[v];
-        }
-        const bool need_l = comp[0];
-        const bool need_r = comp[VEC - 1];
-        const int64_t plane = ny * nx;
-
-        Col<VEC> r[kU + 2];
-#pragma unroll
-        for (int k = 0; k < kU + 2; ++k) {
-            const int64_t z = z0 - 1 + k;
-            if (z <= z1) load_col<VEC>(in, z, y, ny, nx, x, inb, lane, need_l, need_r, r[k]);
-        }
-        for (int64_t zb = z0; zb < z1; zb += kU) {
-            Col<VEC> nxt[kU];
-#pragma unroll
-            for (int k = 0; k < kU; ++k) {
-                const int64_t z = zb + kU + 1 + k;
-                if (z <= z1) load_col<VEC>(in, z, y, ny, nx, x, inb, lane, need_l, need_r, nxt[k]);
-            }
-#pragma unroll
-            for (int k = 0; k < kU; ++k) {
-                const int64_t z = zb + k;
-                if (z < z1) {
-                    const Col<VEC> &zm = r[k], &c = r[k + 1], &zp = r[k + 2];
-                    // y neighbours of this plane (rows of the same plane, cache hits)
-                    double ym[VEC], yp[VEC];
-                    const double *pc = in + (z * ny + y) * nx + x;
-                    if (inb) {
-                        load_vec<VEC>(pc - nx, ym);
-                        load_vec<VEC>(pc + nx, yp);
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < VEC; ++v) ym[v] = yp[v] = 0.0;
-                    }
-                    double lprev = __shfl_up(c.v[VEC - 1], 1, kWave);
-                    double rnext = __shfl_down(c.v[0], 1, kWave);
-                    if (lane == 0) lprev = c.edge;
-                    if (lane == kWave - 1) rnext = c.edge;
-                    double xm[VEC], xp[VEC];
-                    xm[0] = lprev;
-                    xp[VEC - 1] = rnext;
-#pragma unroll
-                    for (int v = 1; v < VEC; ++v) xm[v] = c.v[v - 1];
-#pragma unroll
-                    for (int v = 0; v < VEC - 1; ++v) xp[v] = c.v[v + 1];
-                    double o[VEC];
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) {
-                        const double px = xm[v] + xp[v];
-                        const double py = ym[v] + yp[v];
-                        const double pz = zm.v[v] + zp.v[v];
-                        const double lap = ((px + py) + pz) - 6.0 * c.v[v];
-                        o[v] = c.v[v] + alpha * lap;
-                        if (RES && comp[v]) {
-                            const double d = o[v] - c.v[v];
-                            acc += d * d;
-                        }
-                    }
-                    double *q = out + (z * ny + y) * nx + x;
-                    if (all) {
-                        store_vec<VEC>(q, o);
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < VEC; ++v)
-                            if (comp[v]) q[v] = o[v];
-                    }
-                    (void)plane;
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 2; ++k) r[k] = r[kU + k];
-#pragma unroll
-            for (int k = 0; k < kU; ++k) r[2 + k] = nxt[k];
-        }
-    }
+    const double acc = heat_tile<VEC, RES>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, alpha,
+                                           blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, threadIdx.y, blockDim.x,
+                                           blockDim.y);
     if (RES) {
         const double s = block_sum(acc, sh);
         if (threadIdx.x == 0 && threadIdx.y == 0) {
             const int64_t b = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
             wg_partials[b] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent kernel: a fixed grid walks the tiles of all tasks in order
+// (workgroup b takes tiles b, b + grid, b + 2*grid, ...).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kPersistentThreads)
+persistent_kernel(const PTask *__restrict__ tasks, int ntasks, int64_t total) {
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0, hi = ntasks - 1;  // last task whose first tile is <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tasks[mid].tile_begin <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const PTask &T = tasks[lo];
+        const int64_t local = t - T.tile_begin;
+        const int64_t bxi = local % T.gx;
+        const int64_t rest = local / T.gx;
+        if (T.kind == JACC_LOOP_JACOBI2D) {
+            if (T.vec == 2)
+                jacobi_tile<2>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, bxi, rest,
+                               threadIdx.x, 0, kPersistentThreads, 1);
+            else
+                jacobi_tile<1>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, bxi, rest,
+                               threadIdx.x, 0, kPersistentThreads, 1);
+        } else {
+            const int64_t byi = rest % T.gy, bzi = rest / T.gy;
+            if (T.vec == 2)
+                (void)heat_tile<2, false>(T.in, T.out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2],
+                                          T.hi[2], T.col0, T.tile, T.alpha, bxi, byi, bzi, threadIdx.x, 0,
+                                          kPersistentThreads, 1);
+            else
+                (void)heat_tile<1, false>(T.in, T.out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2],
+                                          T.hi[2], T.col0, T.tile, T.alpha, bxi, byi, bzi, threadIdx.x, 0,
+                                          kPersistentThreads, 1);
         }
     }
 }
@@ -264,13 +294,15 @@ heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t n
 // ---------------------------------------------------------------------------
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+static int64_t col_start(int64_t lo, int vec) { return vec == 2 ? (lo & ~(int64_t)1) : lo; }
+
 hipError_t launch_jacobi2d(const Launch &L, hipStream_t s) {
     const Cfg &c = L.cfg;
     const int64_t nx = L.ext[1];
-    const int64_t col0 = c.vec == 2 ? (L.lo[1] & ~(int64_t)1) : L.lo[1];
+    const int64_t col0 = col_start(L.lo[1], c.vec);
     const int64_t ncols = L.hi[1] - col0;
     const int64_t nrows = L.hi[0] - L.lo[0];
-    if (nrows <= 0 || ncols <= 0) return hipSuccess;
+    if (nrows <= 0 || L.hi[1] <= L.lo[1]) return hipSuccess;
     dim3 block(c.bx, c.by);
     dim3 grid((unsigned)cdiv(ncols, (int64_t)c.bx * c.vec), (unsigned)cdiv(nrows, (int64_t)c.by * c.tile));
     const double *in = (const double *)L.a[0].ptr;
@@ -291,32 +323,83 @@ static dim3 heat_grid(const Launch &L, int64_t col0) {
                 (unsigned)cdiv(L.hi[0] - L.lo[0], c.tile));
 }
 
+static bool heat_empty(const Launch &L) {
+    return L.hi[0] <= L.lo[0] || L.hi[1] <= L.lo[1] || L.hi[2] <= L.lo[2];
+}
+
 int64_t heat3d_workgroups(const Launch &L) {
-    const int64_t col0 = L.cfg.vec == 2 ? (L.lo[2] & ~(int64_t)1) : L.lo[2];
-    dim3 g = heat_grid(L, col0);
+    if (heat_empty(L)) return 0;
+    dim3 g = heat_grid(L, col_start(L.lo[2], L.cfg.vec));
     return (int64_t)g.x * g.y * g.z;
 }
 
 hipError_t launch_heat3d(const Launch &L, hipStream_t s) {
     const Cfg &c = L.cfg;
     const int64_t ny = L.ext[1], nx = L.ext[2];
-    const int64_t col0 = c.vec == 2 ? (L.lo[2] & ~(int64_t)1) : L.lo[2];
-    if (L.hi[0] <= L.lo[0] || L.hi[1] <= L.lo[1] || L.hi[2] <= L.lo[2]) return hipSuccess;
+    const int64_t col0 = col_start(L.lo[2], c.vec);
+    if (heat_empty(L)) return hipSuccess;
     dim3 block(c.bx, c.by);
     dim3 grid = heat_grid(L, col0);
     const double *in = (const double *)L.a[0].ptr;
     double *out = (double *)L.a[1].ptr;
     const double alpha = L.scalars[0];
     const bool res = L.wg_partials != nullptr;
-#define HEAT_ARGS in, out, ny, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1], L.lo[2], L.hi[2], col0, c.tile, alpha, L.wg_partials
+#define HEAT_ARGS \
+    in, out, ny, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1], L.lo[2], L.hi[2], col0, c.tile, alpha, L.wg_partials
     if (c.vec == 2) {
-        if (res) hipLaunchKernelGGL((heat3d_kernel<2, true>), grid, block, 0, s, HEAT_ARGS);
-        else hipLaunchKernelGGL((heat3d_kernel<2, false>), grid, block, 0, s, HEAT_ARGS);
+        if (res)
+            hipLaunchKernelGGL((heat3d_kernel<2, true>), grid, block, 0, s, HEAT_ARGS);
+        else
+            hipLaunchKernelGGL((heat3d_kernel<2, false>), grid, block, 0, s, HEAT_ARGS);
     } else {
-        if (res) hipLaunchKernelGGL((heat3d_kernel<1, true>), grid, block, 0, s, HEAT_ARGS);
-        else hipLaunchKernelGGL((heat3d_kernel<1, false>), grid, block, 0, s, HEAT_ARGS);
+        if (res)
+            hipLaunchKernelGGL((heat3d_kernel<1, true>), grid, block, 0, s, HEAT_ARGS);
+        else
+            hipLaunchKernelGGL((heat3d_kernel<1, false>), grid, block, 0, s, HEAT_ARGS);
     }
 #undef HEAT_ARGS
+    return hipGetLastError();
+}
+
+bool make_task(const Launch &L, PTask *t) {
+    *t = PTask{};
+    t->kind = L.kind;
+    t->vec = L.cfg.vec;
+    t->tile = L.cfg.tile;
+    t->in = (const double *)L.a[0].ptr;
+    t->out = (double *)L.a[1].ptr;
+    for (int d = 0; d < 3; ++d) {
+        t->lo[d] = L.lo[d];
+        t->hi[d] = L.hi[d];
+    }
+    const int64_t w = (int64_t)kPersistentThreads * t->vec;
+    if (L.kind == JACC_LOOP_JACOBI2D) {
+        t->e1 = L.ext[1];
+        t->col0 = col_start(L.lo[1], t->vec);
+        if (L.hi[0] <= L.lo[0] || L.hi[1] <= L.lo[1]) return true;
+        t->gx = cdiv(L.hi[1] - t->col0, w);
+        t->gy = cdiv(L.hi[0] - L.lo[0], t->tile);
+        t->gz = 1;
+    } else if (L.kind == JACC_LOOP_HEAT3D) {
+        t->e1 = L.ext[1];
+        t->e2 = L.ext[2];
+        t->alpha = L.scalars[0];
+        t->col0 = col_start(L.lo[2], t->vec);
+        if (heat_empty(L)) return true;
+        t->gx = cdiv(L.hi[2] - t->col0, w);
+        t->gy = L.hi[1] - L.lo[1];
+        t->gz = cdiv(L.hi[0] - L.lo[0], t->tile);
+    } else {
+        return false;
+    }
+    t->ntiles = t->gx * t->gy * t->gz;
+    return true;
+}
+
+hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, hipStream_t s) {
+    if (ntasks <= 0 || tiles <= 0) return hipSuccess;
+    const int64_t grid = tiles < 2048 ? tiles : 2048;  // 256 CUs x 8 workgroups of 256 threads
+    hipLaunchKernelGGL(persistent_kernel, dim3((unsigned)grid), dim3(kPersistentThreads), 0, s, tasks, ntasks, tiles);
     return hipGetLastError();
 }
 

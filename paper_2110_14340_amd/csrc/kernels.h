@@ -49,9 +49,38 @@ int check_config(const Launch &L);
 // Fills in defaults for zero fields of a configuration.
 Cfg default_config(int kind, const Launch &L, Cfg c);
 
-// Reduction combine: out[0] = sum of partials[p] over the partitions p whose
-// bit is set in `mask`, added in increasing p (p < 64).
-hipError_t launch_combine(const double *partials, uint64_t mask, double *out, hipStream_t s);
+// Reduction combine: out[0] = sum of partials[idx[k]] for k = 0..n-1 in
+// that order (idx lists the streams of the reducing partitions in partition
+// order).
+struct CombineList {
+    int n;
+    int idx[64];
+};
+hipError_t launch_combine(const double *partials, const CombineList &list, double *out, hipStream_t s);
+
+// One loop of a persistent task group: a stencil sweep cut into tiles of
+// 256 threads (256*vec columns x `tile` rows, or x 1 row x `tile` planes).
+struct PTask {
+    int32_t kind;  // JACC_LOOP_JACOBI2D or JACC_LOOP_HEAT3D
+    int32_t vec, tile, pad_;
+    const double *in;
+    double *out;
+    int64_t e1, e2;  // extents of dims 1 and 2 (2-D: e1 = row length)
+    int64_t lo[3], hi[3];
+    int64_t col0;
+    double alpha;
+    int64_t gx, gy, gz;
+    int64_t ntiles, tile_begin;
+};
+constexpr int kPersistentThreads = 256;
+
+// Builds the task record of a launch (false if the kind cannot run inside
+// the persistent kernel).
+bool make_task(const Launch &L, PTask *t);
+
+// Launches the persistent kernel over `ntasks` device task records whose
+// tiles total `tiles`.
+hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, hipStream_t s);
 
 // Number of workgroups the loop's reduction writes partials for (for
 // sizing; <= wg_capacity is required).

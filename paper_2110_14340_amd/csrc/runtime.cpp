@@ -1,7 +1,8 @@
 // Runtime core of the K-partitioned loop-nest library: present table,
 // partition planner (owner blocks, iteration sub-ranges, access ranges),
 // coherence tracker and copy planner, stream/event scheduler with hazard
-// tracking, reduction combine, and the C ABI declared in jacc.h.
+// tracking, reduction combine, graph batches with persistent task groups,
+// the loop timer used by the autotuner, and the C ABI of jacc.h.
 //
 // Paper: JACC (Matsumura, Garcia De Gonzalo, Pena; HiPC 2021).  The data
 // model follows its data-region routines and present table (Sec. "JACC",
@@ -32,18 +33,16 @@ namespace {
 constexpr int kMaxK = 64;
 constexpr int kSlots = 4096;
 constexpr int kEventRing = 16;
-constexpr int64_t kWgCapacity = 1 << 16;  // workgroup partials per partition
+constexpr int64_t kWgCapacity = 1 << 16;  // workgroup partials per stream
+constexpr int kTaskCapacity = 4096;       // persistent tasks per batch
+
+thread_local std::string g_init_err;  // message of the last failed jacc_init
 
 struct Range {
     int64_t lo = 0, hi = 0;
     bool empty() const { return hi <= lo; }
 };
 inline Range isect(Range a, Range b) { return {std::max(a.lo, b.lo), std::min(a.hi, b.hi)}; }
-inline Range hull(Range a, Range b) {
-    if (a.empty()) return b;
-    if (b.empty()) return a;
-    return {std::min(a.lo, b.lo), std::max(a.hi, b.hi)};
-}
 
 // Sorted set of disjoint half-open intervals.
 struct IntervalSet {
@@ -56,7 +55,10 @@ struct IntervalSet {
             if (x.hi < r.lo) {
                 out.push_back(x);
             } else if (r.hi < x.lo) {
-                if (!placed) { out.push_back(r); placed = true; }
+                if (!placed) {
+                    out.push_back(r);
+                    placed = true;
+                }
                 out.push_back(x);
             } else {
                 r = {std::min(r.lo, x.lo), std::max(r.hi, x.hi)};
@@ -78,8 +80,7 @@ struct IntervalSet {
         }
         v.swap(out);
     }
-    // r minus the set
-    std::vector<Range> missing(Range r) const {
+    std::vector<Range> missing(Range r) const {  // r minus the set
         std::vector<Range> out;
         int64_t cur = r.lo;
         for (const Range &x : v) {
@@ -94,7 +95,7 @@ struct IntervalSet {
     }
 };
 
-// Piecewise-constant map over [0, E).
+// Piecewise-constant map over a row range.
 template <class T>
 struct IntervalMap {
     struct Piece {
@@ -103,7 +104,7 @@ struct IntervalMap {
     };
     std::vector<Piece> v;
     void init(int64_t lo, int64_t hi, const T &val) { v.assign(1, Piece{lo, hi, val}); }
-    size_t split(int64_t x) {  // index of the piece starting at x (v.size() if x == end)
+    size_t split(int64_t x) {  // index of the piece starting at x (v.size() at the end)
         for (size_t i = 0; i < v.size(); ++i) {
             if (v[i].lo == x) return i;
             if (v[i].lo < x && x < v[i].hi) {
@@ -162,6 +163,8 @@ struct Array {
     size_t bytes = 0;
     jacc_array_desc d{};
     int K = 1;
+    int home = 0;         // stream of partition 0 for transfers; partition p uses (home + p) mod streams
+    int last_stream = -1;  // base stream of the last loop that wrote this array
     int64_t E = 0, row_elems = 1;
     size_t esize = 8, row_bytes = 8;
     int refs = 1;
@@ -172,6 +175,13 @@ struct Array {
     Range block(int p) const {
         return {(int64_t)((__int128)p * E / K), (int64_t)((__int128)(p + 1) * E / K)};
     }
+};
+
+// Coherence and hazard state of one array (for the replay check of batches).
+struct ArraySnap {
+    IntervalMap<int32_t> writer;
+    std::vector<IntervalSet> valid;
+    std::vector<IntervalMap<Access>> acc;
 };
 
 struct EvEntry {
@@ -187,6 +197,42 @@ struct StreamState {
     std::vector<EvEntry> ring;
     int ring_next = 0;
     std::vector<int64_t> waited;  // waited[q]: ops of stream q known complete before our next op
+    hipEvent_t join_ev = nullptr;
+    int64_t last_use = 0;  // loop tick of the last loop issued on this stream
+};
+
+struct SeqRef {
+    int s = 0;
+    int64_t seq = 0;
+};
+
+struct LoopCall {
+    int kind;
+    jacc_bounds b;
+    std::vector<jacc_arg> args;
+    std::vector<double> scalars;
+    int slot;
+    bool has_cfg;
+    jacc_config cfg;
+};
+
+struct PendingAccess {
+    Array *A;
+    int p;
+    Range r;
+    bool write;
+};
+
+struct Batch {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<LoopCall> calls;
+    std::vector<jacc_trace_op> captured;  // ops planned while capturing
+    bool replay_safe = false;
+    jk::PTask *dev_tasks = nullptr;   // kTaskCapacity device task records
+    jk::PTask *host_tasks = nullptr;  // pinned staging of the same size
+    int tasks_used = 0;
+    int groups = 0;
 };
 
 size_t dtype_size(int dt) {
@@ -205,28 +251,41 @@ struct jacc_ctx {
     int K = 1;
     unsigned flags = 0;
     bool dry = false, tracing = false, serialize = false;
+    bool plan_only = false;  // planning pass without device work (batch replay check)
     jacc_allocator alloc{};
     bool use_hipmalloc = true;
     bool own_streams = false;
     std::vector<StreamState> st;
     std::map<uintptr_t, Array *> present;
     int next_id = 0;
+    int next_home = 0;
+    int64_t tick = 0;
     int status = JACC_OK;
     std::string err;
     std::vector<jacc_trace_op> trace;
+    std::vector<jacc_trace_op> *oplog = nullptr;
     uintptr_t fake_next = (uintptr_t)1 << 44;
-    // reductions
-    double *slots = nullptr;        // kSlots doubles
-    double *partials = nullptr;     // kMaxK doubles
-    double *wg = nullptr;           // K * kWgCapacity doubles
-    int64_t combine_seq = 0;        // seq (on stream 0) of the last combine (readers of partials)
-    std::vector<int64_t> slot_seq;  // seq on stream 0 that produced each slot
+    // reductions (buffers indexed by stream)
+    double *slots = nullptr;             // kSlots doubles
+    double *partials = nullptr;          // kMaxK doubles, one per stream
+    double *wg = nullptr;                // streams * kWgCapacity doubles
+    std::vector<SeqRef> partial_reader;  // last combine that read partials[s]
+    std::vector<SeqRef> slot_src;        // op that produced each slot
+    // batches
+    std::vector<Batch *> batches;
+    Batch *cur = nullptr;
+    std::vector<jk::PTask> ptasks;  // pending persistent group
+    std::vector<PendingAccess> paccs;
+    std::vector<Array *> parrays;
+    hipEvent_t fork_ev = nullptr, t0 = nullptr, t1 = nullptr;
     // fault injection (tests): fail the n-th op of a kind
     int fault_kind = 0;  // 1 copy, 2 launch
     int64_t fault_n = -1, fault_count = 0;
 };
 
 namespace {
+
+bool live(const jacc_ctx *c) { return !c->dry && !c->plan_only; }
 
 int set_err(jacc_ctx *c, int code, const char *fmt, ...) {
     char buf[512];
@@ -243,15 +302,15 @@ int dev_fail(jacc_ctx *c, hipError_t e, const char *what) {
     return set_err(c, JACC_ERR_DEVICE, "%s failed: %s (%d)", what, hipGetErrorString(e), (int)e);
 }
 
-#define HIPCHK(c, expr, what)                          \
-    do {                                               \
-        hipError_t e_ = (expr);                        \
+#define HIPCHK(c, expr, what)                               \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
         if (e_ != hipSuccess) return dev_fail(c, e_, what); \
     } while (0)
 
-void trace(jacc_ctx *c, int op, int stream, int array, int src, int dst, int kind, int64_t lo,
-           int64_t hi, int64_t seq) {
-    if (!c->tracing) return;
+void trace(jacc_ctx *c, int op, int stream, int array, int src, int dst, int kind, int64_t lo, int64_t hi,
+           int64_t seq) {
+    if (!c->tracing && !c->oplog) return;
     jacc_trace_op t;
     t.op = op;
     t.stream = stream;
@@ -262,10 +321,12 @@ void trace(jacc_ctx *c, int op, int stream, int array, int src, int dst, int kin
     t.lo = lo;
     t.hi = hi;
     t.seq = seq;
-    c->trace.push_back(t);
+    if (c->tracing && !c->plan_only) c->trace.push_back(t);
+    if (c->oplog) c->oplog->push_back(t);
 }
 
-int stream_of(const jacc_ctx *c, int p) { return c->serialize ? 0 : p; }
+int nstreams(const jacc_ctx *c) { return (int)c->st.size(); }
+int stream_of(const jacc_ctx *c, const Array *A, int p) { return c->serialize ? 0 : (A->home + p) % nstreams(c); }
 
 // ---- device memory ------------------------------------------------------
 int dev_alloc(jacc_ctx *c, size_t bytes, void **out) {
@@ -299,9 +360,8 @@ void dev_free(jacc_ctx *c, void *p) {
 }
 
 // ---- streams, events, waits ----------------------------------------------
-int post_op(jacc_ctx *c, int s) {  // after an op has been enqueued on stream s
-    if (c->serialize && !c->dry) HIPCHK(c, hipDeviceSynchronize(), "hipDeviceSynchronize");
-    (void)s;
+int post_op(jacc_ctx *c) {
+    if (c->serialize && live(c) && !c->cur) HIPCHK(c, hipDeviceSynchronize(), "hipDeviceSynchronize");
     return JACC_OK;
 }
 
@@ -310,7 +370,7 @@ int ensure_event(jacc_ctx *c, int q, int64_t n, int *idx) {
     StreamState &S = c->st[q];
     if (S.recorded < n) {
         EvEntry &E = S.ring[S.ring_next];
-        if (!c->dry) HIPCHK(c, hipEventRecord(E.ev, S.s), "hipEventRecord");
+        if (live(c)) HIPCHK(c, hipEventRecord(E.ev, S.s), "hipEventRecord");
         E.covers = S.seq;
         E.waited = S.waited;
         S.recorded = S.seq;
@@ -335,10 +395,42 @@ int ensure_wait(jacc_ctx *c, int d, int q, int64_t n) {
     int rc = ensure_event(c, q, n, &idx);
     if (rc) return rc;
     const EvEntry &E = c->st[q].ring[idx];
-    if (!c->dry) HIPCHK(c, hipStreamWaitEvent(D.s, E.ev, 0), "hipStreamWaitEvent");
+    if (live(c)) HIPCHK(c, hipStreamWaitEvent(D.s, E.ev, 0), "hipStreamWaitEvent");
     trace(c, JACC_OP_WAIT, d, -1, q, -1, 0, 0, 0, E.covers);
     D.waited[q] = std::max(D.waited[q], E.covers);
     for (size_t k = 0; k < E.waited.size(); ++k) D.waited[k] = std::max(D.waited[k], E.waited[k]);
+    return JACC_OK;
+}
+
+// After a full join (around a graph launch, or at the start of a capture)
+// every stream knows every op issued so far is complete, and no event
+// recorded before the join is waited on afterwards.
+void assume_joined(jacc_ctx *c) {
+    trace(c, JACC_OP_JOIN, -1, -1, -1, -1, 0, 0, 0, 0);
+    for (auto &S : c->st) S.seq++;
+    for (auto &S : c->st) {
+        for (size_t q = 0; q < c->st.size(); ++q) S.waited[q] = c->st[q].seq;
+        for (auto &E : S.ring) E.covers = -1;
+        S.recorded = S.seq;
+    }
+}
+
+// Stream 0 waits for all other streams (eager events).
+int join_into0(jacc_ctx *c) {
+    if (!live(c)) return JACC_OK;
+    for (int s = 1; s < nstreams(c); ++s) {
+        HIPCHK(c, hipEventRecord(c->st[s].join_ev, c->st[s].s), "hipEventRecord");
+        HIPCHK(c, hipStreamWaitEvent(c->st[0].s, c->st[s].join_ev, 0), "hipStreamWaitEvent");
+    }
+    return JACC_OK;
+}
+
+// All other streams wait for stream 0's current position.
+int fork_from0(jacc_ctx *c) {
+    if (!live(c)) return JACC_OK;
+    HIPCHK(c, hipEventRecord(c->fork_ev, c->st[0].s), "hipEventRecord");
+    for (int s = 1; s < nstreams(c); ++s)
+        HIPCHK(c, hipStreamWaitEvent(c->st[s].s, c->fork_ev, 0), "hipStreamWaitEvent");
     return JACC_OK;
 }
 
@@ -347,7 +439,6 @@ int ensure_wait(jacc_ctx *c, int d, int q, int64_t n) {
 int hazard(jacc_ctx *c, Array *A, int p, Range r, bool write, int s) {
     if (r.empty()) return JACC_OK;
     Slab &sl = A->slabs[p];
-    int rc = JACC_OK;
     std::vector<std::pair<int, int64_t>> need;
     sl.acc.for_range(r, [&](IntervalMap<Access>::Piece &pc) {
         if (pc.val.ws >= 0 && pc.val.ws != s) need.push_back({pc.val.ws, pc.val.wseq});
@@ -356,7 +447,7 @@ int hazard(jacc_ctx *c, Array *A, int p, Range r, bool write, int s) {
                 if (rd.first != s) need.push_back({rd.first, rd.second});
     });
     for (auto &w : need) {
-        rc = ensure_wait(c, s, w.first, w.second);
+        int rc = ensure_wait(c, s, w.first, w.second);
         if (rc) return rc;
     }
     const int64_t next = c->st[s].seq + 1;
@@ -368,7 +459,10 @@ int hazard(jacc_ctx *c, Array *A, int p, Range r, bool write, int s) {
         } else if (pc.val.ws != s) {
             bool found = false;
             for (auto &rd : pc.val.reads)
-                if (rd.first == s) { rd.second = next; found = true; }
+                if (rd.first == s) {
+                    rd.second = next;
+                    found = true;
+                }
             if (!found) pc.val.reads.push_back({s, next});
         }
     });
@@ -378,7 +472,7 @@ int hazard(jacc_ctx *c, Array *A, int p, Range r, bool write, int s) {
 }
 
 bool inject_fault(jacc_ctx *c, int kind) {
-    if (c->fault_kind != kind) return false;
+    if (c->fault_kind != kind || c->plan_only) return false;
     return ++c->fault_count == c->fault_n;
 }
 
@@ -393,9 +487,8 @@ Array *lookup(jacc_ctx *c, const void *host) {
 }
 
 // ---- copies ------------------------------------------------------------
-// Copy rows r of array A from slab q to slab p, on p's stream.
-int issue_copy(jacc_ctx *c, Array *A, int q, int p, Range r) {
-    const int s = stream_of(c, p);
+// Copy rows r of array A from slab q to slab p, on stream s.
+int issue_copy(jacc_ctx *c, Array *A, int q, int p, Range r, int s) {
     int rc = hazard(c, A, q, r, false, s);
     if (rc) return rc;
     rc = hazard(c, A, p, r, true, s);
@@ -407,18 +500,18 @@ int issue_copy(jacc_ctx *c, Array *A, int q, int p, Range r) {
     const Slab &src = A->slabs[q];
     const Slab &dst = A->slabs[p];
     size_t bytes = (size_t)(r.hi - r.lo) * A->row_bytes;
-    if (!c->dry) {
+    if (live(c)) {
         char *sp = (char *)src.dev + (size_t)(r.lo - src.rows.lo) * A->row_bytes;
         char *dp = (char *)dst.dev + (size_t)(r.lo - dst.rows.lo) * A->row_bytes;
         HIPCHK(c, hipMemcpyAsync(dp, sp, bytes, hipMemcpyDeviceToDevice, c->st[s].s), "hipMemcpyAsync(D2D)");
     }
     c->st[s].seq++;
     trace(c, JACC_OP_COPY, s, A->id, q, p, 0, r.lo, r.hi, c->st[s].seq);
-    return post_op(c, s);
+    return post_op(c);
 }
 
-// Pull into slab p every row of `need` that it does not hold fresh.
-int make_fresh(jacc_ctx *c, Array *A, int p, Range need) {
+// Pull into slab p (on stream s) every row of `need` it does not hold fresh.
+int make_fresh(jacc_ctx *c, Array *A, int p, Range need, int s) {
     if (need.empty()) return JACC_OK;
     std::vector<Range> miss = A->valid[p].missing(need);
     for (const Range &m : miss) {
@@ -430,7 +523,7 @@ int make_fresh(jacc_ctx *c, Array *A, int p, Range need) {
             if (q < 0 || q == p)
                 return set_err(c, JACC_ERR_INVALID, "internal: rows [%lld,%lld) of array %d stale with no writer",
                                (long long)pc.second.lo, (long long)pc.second.hi, A->id);
-            int rc = issue_copy(c, A, q, p, pc.second);
+            int rc = issue_copy(c, A, q, p, pc.second, s);
             if (rc) return rc;
         }
         A->valid[p].add(m);
@@ -442,12 +535,14 @@ void note_write(Array *A, int p, Range w) {
     if (w.empty()) return;
     A->writer.assign(w, p);
     for (int q = 0; q < A->K; ++q) {
-        if (q == p) A->valid[q].add(w);
-        else A->valid[q].sub(w);
+        if (q == p)
+            A->valid[q].add(w);
+        else
+            A->valid[q].sub(w);
     }
 }
 
-// Owner of each row for gathers: the last writer, else the block owner.
+// Source of each row for gathers: the last writer, else the block owner.
 template <class F>
 void for_owner_pieces(Array *A, Range r, F f) {
     std::vector<std::pair<int, Range>> pieces;
@@ -470,25 +565,25 @@ void for_owner_pieces(Array *A, Range r, F f) {
 }
 
 int sync_stream(jacc_ctx *c, int s) {
-    if (!c->dry) HIPCHK(c, hipStreamSynchronize(c->st[s].s), "hipStreamSynchronize");
+    if (live(c)) HIPCHK(c, hipStreamSynchronize(c->st[s].s), "hipStreamSynchronize");
     trace(c, JACC_OP_SYNC, s, -1, -1, -1, 0, 0, 0, c->st[s].seq);
     return JACC_OK;
 }
 
 int sync_all(jacc_ctx *c) {
-    for (size_t s = 0; s < c->st.size(); ++s) {
-        int rc = sync_stream(c, (int)s);
+    for (int s = 0; s < nstreams(c); ++s) {
+        int rc = sync_stream(c, s);
         if (rc) return rc;
     }
     return JACC_OK;
 }
 
 int h2d_rows(jacc_ctx *c, Array *A, int p, Range r) {
-    const int s = stream_of(c, p);
+    const int s = stream_of(c, A, p);
     int rc = hazard(c, A, p, r, true, s);
     if (rc) return rc;
     const Slab &sl = A->slabs[p];
-    if (!c->dry) {
+    if (live(c)) {
         char *dp = (char *)sl.dev + (size_t)(r.lo - sl.rows.lo) * A->row_bytes;
         const char *hp = (const char *)A->host + (size_t)r.lo * A->row_bytes;
         HIPCHK(c, hipMemcpyAsync(dp, hp, (size_t)(r.hi - r.lo) * A->row_bytes, hipMemcpyHostToDevice, c->st[s].s),
@@ -496,15 +591,15 @@ int h2d_rows(jacc_ctx *c, Array *A, int p, Range r) {
     }
     c->st[s].seq++;
     trace(c, JACC_OP_H2D, s, A->id, -1, p, 0, r.lo, r.hi, c->st[s].seq);
-    return post_op(c, s);
+    return post_op(c);
 }
 
 int d2h_rows(jacc_ctx *c, Array *A, int p, Range r) {
-    const int s = stream_of(c, p);
+    const int s = stream_of(c, A, p);
     int rc = hazard(c, A, p, r, false, s);
     if (rc) return rc;
     const Slab &sl = A->slabs[p];
-    if (!c->dry) {
+    if (live(c)) {
         const char *sp = (const char *)sl.dev + (size_t)(r.lo - sl.rows.lo) * A->row_bytes;
         char *hp = (char *)A->host + (size_t)r.lo * A->row_bytes;
         HIPCHK(c, hipMemcpyAsync(hp, sp, (size_t)(r.hi - r.lo) * A->row_bytes, hipMemcpyDeviceToHost, c->st[s].s),
@@ -512,7 +607,7 @@ int d2h_rows(jacc_ctx *c, Array *A, int p, Range r) {
     }
     c->st[s].seq++;
     trace(c, JACC_OP_D2H, s, A->id, p, -1, 0, r.lo, r.hi, c->st[s].seq);
-    return post_op(c, s);
+    return post_op(c);
 }
 
 int gather(jacc_ctx *c, Array *A, Range r) {
@@ -521,7 +616,7 @@ int gather(jacc_ctx *c, Array *A, Range r) {
     for_owner_pieces(A, r, [&](int p, Range x) {
         if (rc) return;
         rc = d2h_rows(c, A, p, x);
-        used[stream_of(c, p)] = 1;
+        used[stream_of(c, A, p)] = 1;
     });
     if (rc) return rc;
     for (size_t s = 0; s < used.size(); ++s)
@@ -549,6 +644,51 @@ bool desc_equal(const jacc_array_desc &a, const jacc_array_desc &b) {
     return true;
 }
 
+// ---- persistent task groups ------------------------------------------------
+// Launches the pending persistent tasks as one persistent kernel on stream 0:
+// the task table is staged through pinned memory into the batch's device
+// table, then a grid sized to the chip walks all tasks' tiles.
+int flush_group(jacc_ctx *c) {
+    if (c->ptasks.empty()) return JACC_OK;
+    Batch *B = c->cur;
+    const int s = 0;
+    const int n = (int)c->ptasks.size();
+    if (!B || B->tasks_used + n > kTaskCapacity)
+        return set_err(c, JACC_ERR_UNSUPPORTED, "more than %d persistent tasks in one batch", kTaskCapacity);
+    for (const PendingAccess &a : c->paccs) {
+        int rc = hazard(c, a.A, a.p, a.r, a.write, s);
+        if (rc) return rc;
+    }
+    int64_t tiles = 0;
+    for (auto &t : c->ptasks) {
+        t.tile_begin = tiles;
+        tiles += t.ntiles;
+    }
+    if (live(c)) {
+        jk::PTask *h = B->host_tasks + B->tasks_used;
+        jk::PTask *d = B->dev_tasks + B->tasks_used;
+        std::memcpy(h, c->ptasks.data(), (size_t)n * sizeof(jk::PTask));
+        HIPCHK(c, hipMemcpyAsync(d, h, (size_t)n * sizeof(jk::PTask), hipMemcpyHostToDevice, c->st[s].s),
+               "hipMemcpyAsync(task table)");
+        HIPCHK(c, jk::launch_persistent(d, n, tiles, c->st[s].s), "persistent kernel launch");
+    }
+    B->tasks_used += n;
+    B->groups++;
+    c->st[s].seq++;
+    trace(c, JACC_OP_KERNEL, s, -1, -1, -1, -n, 0, tiles, c->st[s].seq);
+    c->ptasks.clear();
+    c->paccs.clear();
+    c->parrays.clear();
+    int idx;
+    return ensure_event(c, s, c->st[s].seq, &idx);
+}
+
+bool pending_touches(const jacc_ctx *c, const Array *A) {
+    for (const Array *x : c->parrays)
+        if (x == A) return true;
+    return false;
+}
+
 // ---- loop kinds: argument tables --------------------------------------------
 struct KindInfo {
     int nargs;
@@ -572,16 +712,20 @@ struct PartPlan {
     std::vector<Range> rng;  // per argument
 };
 
-#define GUARD(c)                                   \
-    do {                                           \
-        if (!(c)) return JACC_ERR_INVALID;         \
-        if ((c)->status) {                         \
-            return JACC_ERR_DEVICE;                \
-        }                                          \
+#define GUARD(c)                           \
+    do {                                   \
+        if (!(c)) return JACC_ERR_INVALID; \
+        if ((c)->status) {                 \
+            return JACC_ERR_DEVICE;        \
+        }                                  \
     } while (0)
 
-int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc_arg *args,
-              const double *scalars, int nscalars, int slot, double *red_host, const jacc_config *cfg) {
+// Validates a loop call and builds its launch template and per-partition
+// plan.  On success *primary_out is the argument whose owner blocks split
+// the iterations (the written array; the read array for SUM).
+int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc_arg *args, const double *scalars,
+                 int nscalars, bool want_red, const jacc_config *cfg, Array **arr, jk::Launch &L,
+                 std::vector<PartPlan> &plan, int *primary_out) {
     KindInfo ki;
     if (!kind_info(kind, &ki)) return set_err(c, JACC_ERR_INVALID, "unknown loop kind %d", kind);
     if (!b || nargs != ki.nargs || !args)
@@ -589,16 +733,11 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     if (b->ndim != ki.ndim) return set_err(c, JACC_ERR_INVALID, "loop kind %d takes %d-D bounds", kind, ki.ndim);
     for (int d = 0; d < b->ndim; ++d)
         if (b->lo[d] < 0 || b->hi[d] < b->lo[d]) return set_err(c, JACC_ERR_INVALID, "bad bounds in dim %d", d);
-    if (nscalars < 0 || nscalars > 4 || (nscalars > 0 && !scalars))
-        return set_err(c, JACC_ERR_INVALID, "bad scalars");
-    const bool want_red = slot >= 0 || red_host;
+    if (nscalars < 0 || nscalars > 4 || (nscalars > 0 && !scalars)) return set_err(c, JACC_ERR_INVALID, "bad scalars");
     if (ki.red == 0 && want_red) return set_err(c, JACC_ERR_INVALID, "loop kind %d has no reduction", kind);
     if (ki.red == 2 && !want_red) return set_err(c, JACC_ERR_INVALID, "loop kind %d needs a reduction target", kind);
-    if (slot >= kSlots) return set_err(c, JACC_ERR_INVALID, "reduction slot %d out of range", slot);
     if (kind == JACC_LOOP_HEAT3D && nscalars < 1) return set_err(c, JACC_ERR_INVALID, "HEAT3D needs alpha");
 
-    // resolve arguments
-    Array *arr[8];
     int K = -1;
     for (int i = 0; i < nargs; ++i) {
         if (args[i].mode < JACC_READ || args[i].mode > JACC_READWRITE)
@@ -612,15 +751,14 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
         if (A->K != K) return set_err(c, JACC_ERR_UNSUPPORTED, "arguments are partitioned with different K");
         arr[i] = A;
     }
-    // dtype / shape checks per kind
     auto is = [&](int i, int dt, int nd) { return arr[i]->d.dtype == dt && arr[i]->d.ndim == nd; };
-    jk::Launch L{};
+    L = jk::Launch{};
     L.kind = kind;
     L.ndim = b->ndim;
     L.nargs = nargs;
     for (int i = 0; i < nscalars; ++i) L.scalars[i] = scalars[i];
-    for (int i = 0; i < 4; ++i) L.ext[i] = arr[0]->d.extent[i];
-    int primary = -1;  // the argument whose owner blocks split the iterations
+    for (int i = 0; i < 4; ++i) L.ext[i] = arr[0]->d.ndim > i ? arr[0]->d.extent[i] : 0;
+    int primary = -1;
     switch (kind) {
         case JACC_LOOP_JACOBI2D:
             if (!is(0, JACC_F64, 2) || !is(1, JACC_F64, 2) || arr[0]->d.extent[0] != arr[1]->d.extent[0] ||
@@ -669,11 +807,10 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     if (!(args[primary].mode & JACC_WRITE) && kind != JACC_LOOP_SUM)
         return set_err(c, JACC_ERR_INVALID, "the output argument must be declared writable");
 
-    // plan: iteration sub-range and per-argument rows for every partition
     Array *P = arr[primary];
-    std::vector<PartPlan> plan(K);
+    plan.assign(K, PartPlan{});
     for (int p = 0; p < K; ++p) {
-        Range own = P->whole ? Range{p == 0 ? 0 : 0, p == 0 ? P->E : 0} : P->block(p);
+        Range own = P->whole ? (p == 0 ? Range{0, P->E} : Range{0, 0}) : P->block(p);
         plan[p].iters = isect({b->lo[0], b->hi[0]}, own);
         plan[p].rng.resize(nargs);
         for (int i = 0; i < nargs; ++i) {
@@ -701,8 +838,8 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             }
         }
     }
-    // writes of one array by two partitions, or a read of rows another
-    // partition writes in the same loop (the paper duplicates such loops)
+    // one array written by two partitions, or read by one partition where
+    // another writes it in the same loop (the paper duplicates such loops)
     for (int i = 0; i < nargs; ++i) {
         if (!(args[i].mode & JACC_WRITE)) continue;
         for (int j = 0; j < nargs; ++j) {
@@ -717,42 +854,86 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
                 }
         }
     }
-    // configuration
     jk::Cfg cf{0, 0, 0, 0, 0};
     if (cfg) cf = {cfg->bx, cfg->by, cfg->tile, cfg->vec, cfg->persistent};
     L.cfg = jk::default_config(kind, L, cf);
     if (jk::check_config(L) != 0)
-        return set_err(c, JACC_ERR_INVALID, "configuration bx=%d by=%d tile=%d vec=%d not valid for kind %d", L.cfg.bx,
-                       L.cfg.by, L.cfg.tile, L.cfg.vec, kind);
+        return set_err(c, JACC_ERR_INVALID,
+                       "configuration bx=%d by=%d tile=%d vec=%d persistent=%d not valid for kind %d", L.cfg.bx,
+                       L.cfg.by, L.cfg.tile, L.cfg.vec, L.cfg.persistent, kind);
+    if (L.cfg.persistent) {
+        if (!c->cur) return set_err(c, JACC_ERR_INVALID, "persistent execution needs an open batch");
+        if (want_red) return set_err(c, JACC_ERR_UNSUPPORTED, "persistent execution of a reduction");
+    }
+    *primary_out = primary;
+    return JACC_OK;
+}
 
-    // issue
-    uint64_t active = 0;
+int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc_arg *args, const double *scalars,
+              int nscalars, int slot, double *red_host, const jacc_config *cfg) {
+    const bool want_red = slot >= 0 || red_host;
+    if (slot >= kSlots) return set_err(c, JACC_ERR_INVALID, "reduction slot %d out of range", slot);
+    if (red_host && c->cur) return set_err(c, JACC_ERR_INVALID, "a synchronous reduction inside a batch");
+    Array *arr[8];
+    jk::Launch L;
+    std::vector<PartPlan> plan;
+    int primary = -1;
+    int rc = prepare_loop(c, kind, b, nargs, args, scalars, nscalars, want_red, cfg, arr, L, plan, &primary);
+    if (rc) return rc;
+    const bool persistent = L.cfg.persistent != 0;
+    // a pending persistent group is launched before anything that touches
+    // its arrays, and before any non-persistent loop
+    bool conflict = !persistent;
+    for (int i = 0; i < nargs && !conflict; ++i) conflict = pending_touches(c, arr[i]);
+    if (conflict) {
+        rc = flush_group(c);
+        if (rc) return rc;
+    }
+    if (c->cur && !c->plan_only) {
+        LoopCall lc;
+        lc.kind = kind;
+        lc.b = *b;
+        lc.args.assign(args, args + nargs);
+        lc.scalars.assign(scalars, scalars + nscalars);
+        lc.slot = slot;
+        lc.has_cfg = cfg != nullptr;
+        if (cfg) lc.cfg = *cfg;
+        c->cur->calls.push_back(lc);
+    }
+    Array *P = arr[primary];
+    const int K = P->K;
+    // Streams: with one partition per stream, partition p runs on stream p.
+    // With fewer partitions than streams the loop goes where its data was
+    // last produced (a dependent loop stays on the same queue), and a loop
+    // with no device-side producer takes the least recently used stream —
+    // the queue choice of the paper's automated asynchronous execution.
+    int base = 0;
+    const int ns = nstreams(c);
+    if (K < ns && !c->serialize) {
+        base = -1;
+        for (int i = 0; i < nargs && base < 0; ++i)
+            if ((args[i].mode & JACC_READ) && arr[i]->last_stream >= 0) base = arr[i]->last_stream;
+        if (base < 0) base = P->last_stream;
+        if (base < 0) {
+            base = 0;
+            for (int s = 1; s < ns; ++s)
+                if (c->st[s].last_use < c->st[base].last_use) base = s;
+        }
+    }
+    ++c->tick;
+    for (int p = 0; p < K; ++p) c->st[c->serialize ? 0 : (base + p) % ns].last_use = c->tick;
+    for (int i = 0; i < nargs; ++i)
+        if (args[i].mode & JACC_WRITE) arr[i]->last_stream = base;
+    std::vector<int> order;  // streams of the partitions that reduce, in partition order
     for (int p = 0; p < K; ++p) {
         const PartPlan &pp = plan[p];
         if (pp.iters.empty()) continue;
-        const int s = stream_of(c, p);
-        int rc;
-        // bring every read row up to date
+        const int s = persistent ? 0 : (c->serialize ? 0 : (base + p) % ns);
         for (int i = 0; i < nargs; ++i)
             if (args[i].mode & JACC_READ) {
-                rc = make_fresh(c, arr[i], p, pp.rng[i]);
+                rc = make_fresh(c, arr[i], p, pp.rng[i], s);
                 if (rc) return rc;
             }
-        // hazards of the kernel's own accesses
-        for (int i = 0; i < nargs; ++i) {
-            if (args[i].mode & JACC_READ) {
-                rc = hazard(c, arr[i], p, pp.rng[i], false, s);
-                if (rc) return rc;
-            }
-            if (args[i].mode & JACC_WRITE) {
-                rc = hazard(c, arr[i], p, pp.rng[i], true, s);
-                if (rc) return rc;
-            }
-        }
-        if (want_red) {  // partials[p] is read by the previous combine on stream 0
-            rc = ensure_wait(c, s, stream_of(c, 0), c->combine_seq);
-            if (rc) return rc;
-        }
         jk::Launch LP = L;
         LP.lo[0] = pp.iters.lo;
         LP.hi[0] = pp.iters.hi;
@@ -767,25 +948,53 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             LP.a[i].slab_hi = sl.rows.hi;
             LP.a[i].row_elems = arr[i]->row_elems;
         }
+        if (persistent) {
+            jk::PTask t;
+            if (!jk::make_task(LP, &t))
+                return set_err(c, JACC_ERR_UNSUPPORTED, "loop kind %d cannot run persistent", kind);
+            if (t.ntiles > 0) c->ptasks.push_back(t);
+            for (int i = 0; i < nargs; ++i) {
+                if (args[i].mode & JACC_READ) c->paccs.push_back({arr[i], p, pp.rng[i], false});
+                if (args[i].mode & JACC_WRITE) c->paccs.push_back({arr[i], p, pp.rng[i], true});
+                c->parrays.push_back(arr[i]);
+            }
+            for (int i = 0; i < nargs; ++i)
+                if (args[i].mode & JACC_WRITE) note_write(arr[i], p, pp.rng[i]);
+            continue;
+        }
+        for (int i = 0; i < nargs; ++i) {
+            if (args[i].mode & JACC_READ) {
+                rc = hazard(c, arr[i], p, pp.rng[i], false, s);
+                if (rc) return rc;
+            }
+            if (args[i].mode & JACC_WRITE) {
+                rc = hazard(c, arr[i], p, pp.rng[i], true, s);
+                if (rc) return rc;
+            }
+        }
         if (want_red) {
-            LP.wg_partials = c->wg + (size_t)p * kWgCapacity;
+            // partials[s] and the workgroup scratch of stream s are read by
+            // the last combine that used them
+            rc = ensure_wait(c, s, c->partial_reader[s].s, c->partial_reader[s].seq);
+            if (rc) return rc;
+            LP.wg_partials = c->wg + (size_t)s * kWgCapacity;
             LP.wg_capacity = kWgCapacity;
-            LP.part_out = c->partials + p;
+            LP.part_out = c->partials + s;
             if (jk::reduction_workgroups(LP) > kWgCapacity)
                 return set_err(c, JACC_ERR_UNSUPPORTED, "reduction needs more than %lld workgroups",
                                (long long)kWgCapacity);
-            active |= (uint64_t)1 << p;
+            order.push_back(s);
         }
         if (inject_fault(c, 2)) {
             c->status = JACC_ERR_DEVICE;
             return set_err(c, JACC_ERR_DEVICE, "injected fault in launch %lld", (long long)c->fault_count);
         }
-        if (!c->dry) HIPCHK(c, jk::launch_loop(LP, c->st[s].s), "kernel launch");
+        if (live(c)) HIPCHK(c, jk::launch_loop(LP, c->st[s].s), "kernel launch");
         c->st[s].seq++;
         trace(c, JACC_OP_KERNEL, s, -1, -1, p, kind, pp.iters.lo, pp.iters.hi, c->st[s].seq);
-        rc = post_op(c, s);
+        rc = post_op(c);
         if (rc) return rc;
-        if (c->st.size() > 1) {  // precise event for the partitions that will read these rows
+        if (nstreams(c) > 1) {  // a precise event for partitions that will read these rows
             int idx;
             rc = ensure_event(c, s, c->st[s].seq, &idx);
             if (rc) return rc;
@@ -794,34 +1003,102 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             if (args[i].mode & JACC_WRITE) note_write(arr[i], p, pp.rng[i]);
     }
     if (want_red) {
-        const int s0 = stream_of(c, 0);
-        for (int p = 0; p < K; ++p)
-            if (active >> p & 1) {
-                int rc = ensure_wait(c, s0, stream_of(c, p), c->st[stream_of(c, p)].seq);
-                if (rc) return rc;
-            }
-        int sl = slot >= 0 ? slot : kSlots - 1;  // a synchronous-only reduction uses the last slot
-        if (!c->dry) {
-            if (active == 0)
-                HIPCHK(c, hipMemsetAsync(c->slots + sl, 0, sizeof(double), c->st[s0].s), "hipMemsetAsync");
-            else
-                HIPCHK(c, jk::launch_combine(c->partials, active, c->slots + sl, c->st[s0].s), "combine launch");
+        const int s0 = c->serialize ? 0 : base % ns;
+        for (int s : order) {
+            rc = ensure_wait(c, s0, s, c->st[s].seq);
+            if (rc) return rc;
+        }
+        const int sl = slot >= 0 ? slot : kSlots - 1;  // a synchronous-only reduction uses the last slot
+        rc = ensure_wait(c, s0, c->slot_src[sl].s, c->slot_src[sl].seq);  // earlier writer of the slot
+        if (rc) return rc;
+        if (live(c)) {
+            jk::CombineList cl{};
+            cl.n = (int)order.size();
+            for (size_t k = 0; k < order.size(); ++k) cl.idx[k] = order[k];
+            HIPCHK(c, jk::launch_combine(c->partials, cl, c->slots + sl, c->st[s0].s), "combine launch");
         }
         c->st[s0].seq++;
-        c->combine_seq = c->st[s0].seq;
-        c->slot_seq[sl] = c->st[s0].seq;
+        for (int s : order) c->partial_reader[s] = {s0, c->st[s0].seq};
+        c->slot_src[sl] = {s0, c->st[s0].seq};
         trace(c, JACC_OP_COMBINE, s0, -1, -1, -1, sl, 0, 0, c->st[s0].seq);
-        int rc = post_op(c, s0);
+        rc = post_op(c);
         if (rc) return rc;
         if (red_host) {
             rc = sync_stream(c, s0);
             if (rc) return rc;
-            if (!c->dry)
+            if (live(c))
                 HIPCHK(c, hipMemcpy(red_host, c->slots + sl, sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy(D2H)");
             else
                 *red_host = 0.0;
         }
     }
+    return JACC_OK;
+}
+
+// ---- batches ----------------------------------------------------------------
+void snapshot(jacc_ctx *c, std::map<Array *, ArraySnap> &snap) {
+    snap.clear();
+    for (auto &kv : c->present) {
+        ArraySnap s;
+        s.writer = kv.second->writer;
+        s.valid = kv.second->valid;
+        for (auto &sl : kv.second->slabs) s.acc.push_back(sl.acc);
+        snap[kv.second] = s;
+    }
+}
+
+void restore(jacc_ctx *c, std::map<Array *, ArraySnap> &snap) {
+    for (auto &kv : snap) {
+        kv.first->writer = kv.second.writer;
+        kv.first->valid = kv.second.valid;
+        for (size_t p = 0; p < kv.second.acc.size(); ++p) kv.first->slabs[p].acc = kv.second.acc[p];
+    }
+}
+
+// Structural form of an op list (what is copied or launched where), without
+// sequence numbers.
+std::vector<std::vector<int64_t>> structure(const std::vector<jacc_trace_op> &ops) {
+    std::vector<std::vector<int64_t>> out;
+    for (const auto &t : ops) {
+        if (t.op == JACC_OP_RECORD || t.op == JACC_OP_SYNC || t.op == JACC_OP_JOIN) continue;
+        if (t.op == JACC_OP_WAIT)
+            out.push_back({t.op, t.stream, t.src});
+        else
+            out.push_back({t.op, t.stream, t.array, t.src, t.dst, t.kind, t.lo, t.hi});
+    }
+    return out;
+}
+
+// Plans the recorded calls of batch B once more without device work, from
+// the current state, logging the ops into *log.
+int replan(jacc_ctx *c, Batch *B, std::vector<jacc_trace_op> *log) {
+    Batch probe;
+    Batch *saved = c->cur;
+    c->plan_only = true;
+    c->oplog = log;
+    c->cur = &probe;
+    assume_joined(c);
+    int rc = JACC_OK;
+    for (auto &lc : B->calls) {
+        rc = loop_impl(c, lc.kind, &lc.b, (int)lc.args.size(), lc.args.data(), lc.scalars.data(),
+                       (int)lc.scalars.size(), lc.slot, nullptr, lc.has_cfg ? &lc.cfg : nullptr);
+        if (rc) break;
+    }
+    if (!rc) rc = flush_group(c);
+    c->cur = saved;
+    c->plan_only = false;
+    c->oplog = nullptr;
+    return rc;
+}
+
+int launch_graph(jacc_ctx *c, Batch *B, int repeats) {
+    int rc = join_into0(c);
+    if (rc) return rc;
+    if (live(c))
+        for (int r = 0; r < repeats; ++r) HIPCHK(c, hipGraphLaunch(B->exec, c->st[0].s), "hipGraphLaunch");
+    rc = fork_from0(c);
+    if (rc) return rc;
+    assume_joined(c);
     return JACC_OK;
 }
 
@@ -832,13 +1109,20 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
 // ============================================================================
 extern "C" {
 
-const char *jacc_version(void) { return "jacc-mi355x 0.1 (gfx950)"; }
+const char *jacc_version(void) { return "jacc-mi355x 0.2 (gfx950)"; }
 
 int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator *alloc, unsigned flags) {
+    g_init_err.clear();
     if (!out) return JACC_ERR_INVALID;
     *out = nullptr;
-    if (K < 1 || K > kMaxK) return JACC_ERR_INVALID;
-    if (alloc && (!alloc->alloc || !alloc->free)) return JACC_ERR_INVALID;
+    if (K < 1 || K > kMaxK) {
+        g_init_err = "K must lie in [1, 64]";
+        return JACC_ERR_INVALID;
+    }
+    if (alloc && (!alloc->alloc || !alloc->free)) {
+        g_init_err = "allocator without alloc/free";
+        return JACC_ERR_INVALID;
+    }
     jacc_ctx *c = nullptr;
     try {
         c = new jacc_ctx();
@@ -851,8 +1135,7 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
             c->alloc = *alloc;
             c->use_hipmalloc = false;
         }
-        if (const char *f = getenv("JACC_FAULT_INJECT")) {
-            // "<copy|launch>:<n>"
+        if (const char *f = getenv("JACC_FAULT_INJECT")) {  // "<copy|launch>:<n>"
             const char *colon = strchr(f, ':');
             if (colon) {
                 if (!strncmp(f, "copy", 4)) c->fault_kind = 1;
@@ -860,54 +1143,54 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
                 c->fault_n = atoll(colon + 1);
             }
         }
-        const int nstreams = c->serialize ? 1 : K;
-        c->st.resize(nstreams);
+        const int ns = c->serialize ? 1 : K;
+        c->st.resize(ns);
         c->own_streams = (streams == nullptr);
-        for (int s = 0; s < nstreams; ++s) {
+        c->partial_reader.assign(ns, SeqRef{});
+        c->slot_src.assign(kSlots, SeqRef{});
+        int rc = JACC_OK;
+        for (int s = 0; s < ns && !rc; ++s) {
             StreamState &S = c->st[s];
-            S.waited.assign(nstreams, 0);
+            S.waited.assign(ns, 0);
             S.ring.resize(kEventRing);
             if (c->dry) continue;
+            hipError_t e = hipSuccess;
             if (streams)
                 S.s = (hipStream_t)streams[s];
-            else {
-                hipError_t e = hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking);
-                if (e != hipSuccess) {
-                    int rc = dev_fail(c, e, "hipStreamCreateWithFlags");
-                    jacc_finalize(c);
-                    return rc;
-                }
-            }
-            for (auto &E : S.ring) {
-                hipError_t e = hipEventCreateWithFlags(&E.ev, hipEventDisableTiming);
-                if (e != hipSuccess) {
-                    int rc = dev_fail(c, e, "hipEventCreateWithFlags");
-                    jacc_finalize(c);
-                    return rc;
-                }
-            }
+            else
+                e = hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking);
+            for (auto &E : S.ring)
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&E.ev, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&S.join_ev, hipEventDisableTiming);
+            if (e != hipSuccess) rc = dev_fail(c, e, "stream/event creation");
         }
-        c->slot_seq.assign(kSlots, 0);
-        int rc = dev_alloc(c, kSlots * sizeof(double), (void **)&c->slots);
+        if (!rc && !c->dry) {
+            hipError_t e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreate(&c->t0);
+            if (e == hipSuccess) e = hipEventCreate(&c->t1);
+            if (e != hipSuccess) rc = dev_fail(c, e, "event creation");
+        }
+        if (!rc) rc = dev_alloc(c, kSlots * sizeof(double), (void **)&c->slots);
         if (!rc) rc = dev_alloc(c, kMaxK * sizeof(double), (void **)&c->partials);
-        if (!rc) rc = dev_alloc(c, (size_t)K * kWgCapacity * sizeof(double), (void **)&c->wg);
+        if (!rc) rc = dev_alloc(c, (size_t)ns * kWgCapacity * sizeof(double), (void **)&c->wg);
+        if (!rc && !c->dry) {
+            hipError_t e = hipMemset(c->slots, 0, kSlots * sizeof(double));
+            if (e == hipSuccess) e = hipDeviceSynchronize();
+            if (e != hipSuccess) rc = dev_fail(c, e, "hipMemset");
+        }
         if (rc) {
+            g_init_err = c->err;
+            c->status = JACC_OK;
             jacc_finalize(c);
             return rc;
         }
-        if (!c->dry) {
-            hipError_t e = hipMemset(c->slots, 0, kSlots * sizeof(double));
-            if (e != hipSuccess) {
-                int rc2 = dev_fail(c, e, "hipMemset");
-                jacc_finalize(c);
-                return rc2;
-            }
-        }
     } catch (const std::bad_alloc &) {
         delete c;
+        g_init_err = "host allocation failed";
         return JACC_ERR_ALLOC;
     } catch (...) {
         delete c;
+        g_init_err = "internal error";
         return JACC_ERR_INVALID;
     }
     *out = c;
@@ -918,9 +1201,29 @@ int jacc_finalize(jacc_ctx *c) {
     if (!c) return JACC_ERR_INVALID;
     int status = c->status;
     try {
+        if (c->cur) {  // abandon an open capture
+            if (live(c)) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(c->st[0].s, &g);
+                if (g) (void)hipGraphDestroy(g);
+            }
+            c->batches.push_back(c->cur);
+            c->cur = nullptr;
+        }
         if (!c->dry)
             for (auto &S : c->st)
                 if (S.s) (void)hipStreamSynchronize(S.s);
+        for (Batch *B : c->batches) {
+            if (!B) continue;
+            if (!c->dry) {
+                if (B->exec) (void)hipGraphExecDestroy(B->exec);
+                if (B->graph) (void)hipGraphDestroy(B->graph);
+                if (B->host_tasks) (void)hipHostFree(B->host_tasks);
+            }
+            dev_free(c, B->dev_tasks);
+            delete B;
+        }
+        c->batches.clear();
         for (auto &kv : c->present) free_array(c, kv.second);
         c->present.clear();
         dev_free(c, c->slots);
@@ -930,8 +1233,12 @@ int jacc_finalize(jacc_ctx *c) {
             for (auto &S : c->st) {
                 for (auto &E : S.ring)
                     if (E.ev) (void)hipEventDestroy(E.ev);
+                if (S.join_ev) (void)hipEventDestroy(S.join_ev);
                 if (c->own_streams && S.s) (void)hipStreamDestroy(S.s);
             }
+            if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+            if (c->t0) (void)hipEventDestroy(c->t0);
+            if (c->t1) (void)hipEventDestroy(c->t1);
         }
     } catch (...) {
     }
@@ -942,6 +1249,7 @@ int jacc_finalize(jacc_ctx *c) {
 int jacc_data_enter(jacc_ctx *c, void *host, const jacc_array_desc *d, int clause) {
     GUARD(c);
     try {
+        if (c->cur) return set_err(c, JACC_ERR_INVALID, "data regions cannot change inside a batch");
         if (!host || !d) return set_err(c, JACC_ERR_INVALID, "NULL host pointer or descriptor");
         if (clause != JACC_COPYIN && clause != JACC_CREATE && clause != JACC_COPY)
             return set_err(c, JACC_ERR_INVALID, "bad clause %d", clause);
@@ -976,6 +1284,7 @@ int jacc_data_enter(jacc_ctx *c, void *host, const jacc_array_desc *d, int claus
         A->bytes = bytes;
         A->d = *d;
         A->K = K;
+        A->home = (K == nstreams(c) || c->serialize) ? 0 : (c->next_home++ % nstreams(c));
         A->E = d->extent[0];
         A->row_elems = row;
         A->esize = es;
@@ -1020,6 +1329,7 @@ int jacc_data_enter(jacc_ctx *c, void *host, const jacc_array_desc *d, int claus
 int jacc_data_exit(jacc_ctx *c, void *host, int clause) {
     GUARD(c);
     try {
+        if (c->cur) return set_err(c, JACC_ERR_INVALID, "data regions cannot change inside a batch");
         if (clause != JACC_COPYOUT && clause != JACC_DELETE) return set_err(c, JACC_ERR_INVALID, "bad clause %d", clause);
         Array *A = lookup(c, host);
         if (!A) return set_err(c, JACC_ERR_NOT_PRESENT, "%p is not present", host);
@@ -1042,6 +1352,7 @@ int jacc_data_exit(jacc_ctx *c, void *host, int clause) {
 int jacc_update(jacc_ctx *c, void *host, int dir, int64_t row_lo, int64_t row_hi) {
     GUARD(c);
     try {
+        if (c->cur) return set_err(c, JACC_ERR_INVALID, "updates cannot run inside a batch");
         Array *A = lookup(c, host);
         if (!A) return set_err(c, JACC_ERR_NOT_PRESENT, "%p is not present", host);
         if (row_hi < 0) row_hi = A->E;
@@ -1080,15 +1391,17 @@ int jacc_parallel_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, c
 
 int jacc_wait(jacc_ctx *c) {
     GUARD(c);
+    if (c->cur) return set_err(c, JACC_ERR_INVALID, "jacc_wait inside a batch");
     return sync_all(c);
 }
 
 int jacc_reduction_get(jacc_ctx *c, int slot, double *out) {
     GUARD(c);
     if (slot < 0 || slot >= kSlots || !out) return set_err(c, JACC_ERR_INVALID, "bad slot or output");
-    int rc = sync_stream(c, 0);
+    if (c->cur) return set_err(c, JACC_ERR_INVALID, "reduction readback inside a batch");
+    int rc = sync_stream(c, c->slot_src[slot].s);
     if (rc) return rc;
-    if (c->dry) {
+    if (!live(c)) {
         *out = 0.0;
         return JACC_OK;
     }
@@ -1100,10 +1413,11 @@ int jacc_reduction_read(jacc_ctx *c, int first, int count, double *out) {
     GUARD(c);
     if (first < 0 || count < 0 || first + count > kSlots || (count && !out))
         return set_err(c, JACC_ERR_INVALID, "bad slot range");
+    if (c->cur) return set_err(c, JACC_ERR_INVALID, "reduction readback inside a batch");
     int rc = sync_all(c);
     if (rc) return rc;
     if (!count) return JACC_OK;
-    if (c->dry) {
+    if (!live(c)) {
         memset(out, 0, (size_t)count * sizeof(double));
         return JACC_OK;
     }
@@ -1112,7 +1426,199 @@ int jacc_reduction_read(jacc_ctx *c, int first, int count, double *out) {
     return JACC_OK;
 }
 
-const char *jacc_last_error(const jacc_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+int jacc_batch_begin(jacc_ctx *c) {
+    GUARD(c);
+    if (c->cur) return set_err(c, JACC_ERR_INVALID, "a batch is already open");
+    Batch *B = new Batch();
+    int rc = dev_alloc(c, kTaskCapacity * sizeof(jk::PTask), (void **)&B->dev_tasks);
+    if (rc) {
+        delete B;
+        return rc;
+    }
+    if (!c->dry) {
+        hipError_t e = hipHostMalloc((void **)&B->host_tasks, kTaskCapacity * sizeof(jk::PTask), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            dev_free(c, B->dev_tasks);
+            delete B;
+            return dev_fail(c, e, "hipHostMalloc");
+        }
+    }
+    // everything issued before the batch completes before the graph runs:
+    // each launch joins every stream into stream 0 first
+    rc = join_into0(c);
+    if (rc) return rc;
+    if (live(c)) HIPCHK(c, hipStreamBeginCapture(c->st[0].s, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+    c->cur = B;
+    rc = fork_from0(c);
+    if (rc) return rc;
+    assume_joined(c);
+    c->oplog = &B->captured;
+    return JACC_OK;
+}
+
+int jacc_batch_end(jacc_ctx *c, int *graph_id) {
+    GUARD(c);
+    if (!c->cur) return set_err(c, JACC_ERR_INVALID, "no open batch");
+    if (!graph_id) return set_err(c, JACC_ERR_INVALID, "NULL graph id");
+    Batch *B = c->cur;
+    int rc = flush_group(c);
+    c->oplog = nullptr;
+    if (rc) return rc;
+    for (int s = 1; s < nstreams(c) && live(c); ++s) {  // join every stream back into the origin
+        HIPCHK(c, hipEventRecord(c->st[s].join_ev, c->st[s].s), "hipEventRecord");
+        HIPCHK(c, hipStreamWaitEvent(c->st[0].s, c->st[s].join_ev, 0), "hipStreamWaitEvent");
+    }
+    if (live(c)) {
+        HIPCHK(c, hipStreamEndCapture(c->st[0].s, &B->graph), "hipStreamEndCapture");
+        HIPCHK(c, hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    }
+    c->cur = nullptr;
+    c->batches.push_back(B);
+    *graph_id = (int)c->batches.size() - 1;
+    // Replay check.  The graph holds the ops planned from the state before the
+    // batch; the coherence state now is the state after one execution.  If
+    // planning the same calls from this state gives the same copies, waits
+    // and launches, a replay re-executes exactly what a second execution
+    // needs, and the state after it is unchanged (the written rows and the
+    // copied rows are the same), so every later replay is correct too.
+    try {
+        std::map<Array *, ArraySnap> s1;
+        snapshot(c, s1);
+        std::vector<jacc_trace_op> second;
+        int rc2 = replan(c, B, &second);
+        B->replay_safe = (rc2 == JACC_OK && structure(second) == structure(B->captured));
+        restore(c, s1);
+        if (!B->replay_safe) c->err = "batch is not replay-safe";
+    } catch (...) {
+        c->plan_only = false;
+        c->oplog = nullptr;
+        c->cur = nullptr;
+        B->replay_safe = false;
+    }
+    assume_joined(c);
+    // the batch's calls take effect now: the graph runs once
+    return launch_graph(c, B, 1);
+}
+
+int jacc_batch_launch(jacc_ctx *c, int graph_id, int repeats) {
+    GUARD(c);
+    if (c->cur) return set_err(c, JACC_ERR_INVALID, "batch launch inside an open batch");
+    if (graph_id < 0 || graph_id >= (int)c->batches.size() || !c->batches[graph_id])
+        return set_err(c, JACC_ERR_INVALID, "unknown graph %d", graph_id);
+    if (repeats < 0) return set_err(c, JACC_ERR_INVALID, "negative repeats");
+    Batch *B = c->batches[graph_id];
+    if (!B->replay_safe)
+        return set_err(c, JACC_ERR_UNSUPPORTED, "graph %d is not replay-safe (a later pass plans other copies)",
+                       graph_id);
+    if (repeats == 0) return JACC_OK;
+    return launch_graph(c, B, repeats);
+}
+
+int jacc_batch_info(jacc_ctx *c, int graph_id, int *loops, int *persistent_groups, int *replay_safe) {
+    GUARD(c);
+    if (graph_id < 0 || graph_id >= (int)c->batches.size() || !c->batches[graph_id])
+        return set_err(c, JACC_ERR_INVALID, "unknown graph %d", graph_id);
+    Batch *B = c->batches[graph_id];
+    if (loops) *loops = (int)B->calls.size();
+    if (persistent_groups) *persistent_groups = B->groups;
+    if (replay_safe) *replay_safe = B->replay_safe ? 1 : 0;
+    return JACC_OK;
+}
+
+int jacc_batch_destroy(jacc_ctx *c, int graph_id) {
+    GUARD(c);
+    if (c->cur) return set_err(c, JACC_ERR_INVALID, "batch destroy inside an open batch");
+    if (graph_id < 0 || graph_id >= (int)c->batches.size() || !c->batches[graph_id])
+        return set_err(c, JACC_ERR_INVALID, "unknown graph %d", graph_id);
+    Batch *B = c->batches[graph_id];
+    int rc = sync_all(c);
+    if (rc) return rc;
+    if (!c->dry) {
+        if (B->exec) (void)hipGraphExecDestroy(B->exec);
+        if (B->graph) (void)hipGraphDestroy(B->graph);
+        if (B->host_tasks) (void)hipHostFree(B->host_tasks);
+    }
+    dev_free(c, B->dev_tasks);
+    delete B;
+    c->batches[graph_id] = nullptr;
+    return JACC_OK;
+}
+
+int jacc_batch_time(jacc_ctx *c, int graph_id, int warmup, int reps, double *ms) {
+    GUARD(c);
+    if (c->dry) return set_err(c, JACC_ERR_UNSUPPORTED, "timing needs the device");
+    if (reps < 1 || !ms || warmup < 0) return set_err(c, JACC_ERR_INVALID, "bad repetition count");
+    int rc = jacc_batch_launch(c, graph_id, warmup);
+    if (rc) return rc;
+    Batch *B = c->batches[graph_id];
+    rc = join_into0(c);
+    if (rc) return rc;
+    for (int r = 0; r < reps; ++r) {
+        HIPCHK(c, hipEventRecord(c->t0, c->st[0].s), "hipEventRecord");
+        HIPCHK(c, hipGraphLaunch(B->exec, c->st[0].s), "hipGraphLaunch");
+        HIPCHK(c, hipEventRecord(c->t1, c->st[0].s), "hipEventRecord");
+        HIPCHK(c, hipEventSynchronize(c->t1), "hipEventSynchronize");
+        float f = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&f, c->t0, c->t1), "hipEventElapsedTime");
+        ms[r] = f;
+    }
+    rc = fork_from0(c);
+    if (rc) return rc;
+    assume_joined(c);
+    return JACC_OK;
+}
+
+int jacc_time_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc_arg *args,
+                   const double *scalars, int nscalars, const jacc_config *cfg, int warmup, int reps, double *ms) {
+    GUARD(c);
+    if (c->dry) return set_err(c, JACC_ERR_UNSUPPORTED, "timing needs the device");
+    if (c->cur) return set_err(c, JACC_ERR_INVALID, "timing inside an open batch");
+    if (reps < 1 || !ms || warmup < 0) return set_err(c, JACC_ERR_INVALID, "bad repetition count");
+    try {
+        if (cfg && cfg->persistent) {  // persistent configurations run as a one-loop graph
+            int rc = jacc_batch_begin(c);
+            if (rc) return rc;
+            rc = loop_impl(c, kind, b, nargs, args, scalars, nscalars, -1, nullptr, cfg);
+            int g = -1;
+            int rc_end = jacc_batch_end(c, &g);
+            if (!rc) rc = rc_end;
+            if (!rc) rc = jacc_batch_time(c, g, warmup, reps, ms);
+            if (g >= 0) {
+                int rc2 = jacc_batch_destroy(c, g);
+                if (!rc) rc = rc2;
+            }
+            return rc;
+        }
+        const int slot = kind == JACC_LOOP_SUM ? kSlots - 2 : -1;
+        for (int r = 0; r < warmup; ++r) {
+            int rc = loop_impl(c, kind, b, nargs, args, scalars, nscalars, slot, nullptr, cfg);
+            if (rc) return rc;
+        }
+        for (int r = 0; r < reps; ++r) {
+            int rc = join_into0(c);
+            if (rc) return rc;
+            HIPCHK(c, hipEventRecord(c->t0, c->st[0].s), "hipEventRecord");
+            rc = fork_from0(c);
+            if (rc) return rc;
+            assume_joined(c);
+            rc = loop_impl(c, kind, b, nargs, args, scalars, nscalars, slot, nullptr, cfg);
+            if (rc) return rc;
+            rc = join_into0(c);
+            if (rc) return rc;
+            HIPCHK(c, hipEventRecord(c->t1, c->st[0].s), "hipEventRecord");
+            HIPCHK(c, hipEventSynchronize(c->t1), "hipEventSynchronize");
+            float f = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&f, c->t0, c->t1), "hipEventElapsedTime");
+            ms[r] = f;
+            assume_joined(c);
+        }
+        return JACC_OK;
+    } catch (...) {
+        return set_err(c, JACC_ERR_INVALID, "internal error");
+    }
+}
+
+const char *jacc_last_error(const jacc_ctx *c) { return c ? c->err.c_str() : g_init_err.c_str(); }
 
 int jacc_slab_info(jacc_ctx *c, void *host, int p, void **dev, int64_t *row_lo, int64_t *row_hi) {
     if (!c) return JACC_ERR_INVALID;

@@ -25,7 +25,7 @@ READ, WRITE, READWRITE = 1, 2, 3
 JACOBI2D, HEAT3D, SUM, GEMM, SPMV_CSR = 1, 2, 3, 4, 5
 INIT_DRYRUN, INIT_TRACE, INIT_SERIALIZE = 1, 2, 4
 OP_NAMES = {1: "ALLOC", 2: "FREE", 3: "H2D", 4: "D2H", 5: "COPY", 6: "KERNEL", 7: "RECORD", 8: "WAIT",
-            9: "SYNC", 10: "COMBINE", 11: "ACCESS"}
+            9: "SYNC", 10: "COMBINE", 11: "ACCESS", 12: "JOIN"}
 STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOT_PRESENT", -3: "ALREADY_PRESENT", -4: "RANGE", -5: "ALLOC",
                 -6: "DEVICE", -7: "UNSUPPORTED"}
 
@@ -77,6 +77,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2110_14340_amd.build` "
                            "(there is no non-HIP fallback)")
+    # PyTorch ships its own HIP runtime; it must be loaded before libjacc.so
+    # so that the library binds to the same runtime instead of loading a
+    # second one (two runtimes in one process cannot share streams).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
     L.jacc_version.restype = ctypes.c_char_p
@@ -94,6 +101,15 @@ def lib():
     L.jacc_last_error.argtypes = [vp]
     L.jacc_last_error.restype = ctypes.c_char_p
     L.jacc_slab_info.argtypes = [vp, vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.jacc_batch_begin.argtypes = [vp]
+    L.jacc_batch_end.argtypes = [vp, ctypes.POINTER(i32)]
+    L.jacc_batch_launch.argtypes = [vp, i32, i32]
+    L.jacc_batch_info.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.jacc_batch_destroy.argtypes = [vp, i32]
+    L.jacc_batch_time.argtypes = [vp, i32, i32, i32, ctypes.POINTER(ctypes.c_double)]
+    L.jacc_time_loop.argtypes = [vp, i32, ctypes.POINTER(Bounds), i32, ctypes.POINTER(Arg),
+                                 ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(Config), i32, i32,
+                                 ctypes.POINTER(ctypes.c_double)]
     L.jacc_trace_len.argtypes = [vp]
     L.jacc_trace_get.argtypes = [vp, i32, ctypes.POINTER(TraceOp)]
     L.jacc_trace_clear.argtypes = [vp]
@@ -183,7 +199,7 @@ class Context:
         self.ctx = ctypes.c_void_p()
         st = self.L.jacc_init(ctypes.byref(self.ctx), K, sp, ap, flags)
         if st != OK:
-            raise JaccError(st, "jacc_init failed")
+            raise JaccError(st, "jacc_init failed: " + self.L.jacc_last_error(None).decode())
         self.arrays = {}
 
     # -- helpers ---------------------------------------------------------
@@ -282,6 +298,49 @@ class Context:
         b = bounds((0, y.shape[0]))
         return self.loop(SPMV_CSR, b, [(rp, READ, 0, 1, 0), (col, READ, 0, 0, 1), (val, READ, 0, 0, 1),
                                        (x, READ, 0, 0, 1), (y, WRITE, 0, 0, 0)], raw=raw)
+
+    # -- batches and timing ----------------------------------------------------
+    def batch_begin(self):
+        return self._check(self.L.jacc_batch_begin(self.ctx))
+
+    def batch_end(self):
+        g = ctypes.c_int(-1)
+        self._check(self.L.jacc_batch_end(self.ctx, ctypes.byref(g)))
+        return g.value
+
+    def batch_launch(self, graph, repeats=1, raw=False):
+        st = self.L.jacc_batch_launch(self.ctx, graph, repeats)
+        return st if raw else self._check(st)
+
+    def batch_info(self, graph):
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        self._check(self.L.jacc_batch_info(self.ctx, graph, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"loops": a.value, "persistent_groups": b.value, "replay_safe": bool(c.value)}
+
+    def batch_destroy(self, graph):
+        return self._check(self.L.jacc_batch_destroy(self.ctx, graph))
+
+    def batch_time(self, graph, warmup=2, reps=10):
+        out = np.zeros(reps, dtype=np.float64)
+        self._check(self.L.jacc_batch_time(self.ctx, graph, warmup, reps,
+                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def time_loop(self, kind, bnds, args, scalars=(), cfg=None, warmup=2, reps=10, raw=False):
+        """HIP-event times (ms) of `reps` runs of one loop call."""
+        n = len(args)
+        A = (Arg * n)()
+        for i, (a, mode, lo, hi, whole) in enumerate(args):
+            A[i] = Arg(self._ptr(a), mode, lo, hi, int(whole))
+        S = (ctypes.c_double * max(1, len(scalars)))(*scalars)
+        out = np.zeros(reps, dtype=np.float64)
+        st = self.L.jacc_time_loop(self.ctx, kind, ctypes.byref(bnds), n, A, S, len(scalars),
+                                   ctypes.byref(cfg) if cfg is not None else None, warmup, reps,
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        if raw:
+            return st, out
+        self._check(st)
+        return out
 
     # -- sync / reductions -----------------------------------------------------
     def wait(self):

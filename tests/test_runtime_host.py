@@ -330,3 +330,104 @@ def test_serialize_mode_uses_one_stream():
     assert {t["stream"] for t in tr if t["op"] in ("KERNEL", "COPY")} == {0}
     assert not [t for t in tr if t["op"] == "WAIT"]
     assert freshness_check(tr) == []
+
+
+# ------------------------------------------------------------------ batches
+def test_batch_two_step_jacobi_is_replay_safe_and_race_free():
+    c = dry(4)
+    a = np.zeros((40, 8))
+    b = np.zeros((40, 8))
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    c.jacobi2d(a, b)
+    c.jacobi2d(b, a)
+    c.batch_begin()
+    c.jacobi2d(a, b)
+    c.jacobi2d(b, a)
+    g = c.batch_end()
+    info = c.batch_info(g)
+    assert info == {"loops": 2, "persistent_groups": 0, "replay_safe": True}
+    c.batch_launch(g, 3)
+    c.jacobi2d(a, b)  # eager work after the graph sees the joined state
+    c.exit(b)
+    c.exit(a)
+    tr = c.trace()
+    assert race_check(tr) == [] and freshness_check(tr) == []
+
+
+def test_batch_not_replay_safe_is_refused():
+    c = dry(4)
+    a = np.zeros((40, 8))
+    b = np.zeros((40, 8))
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    c.jacobi2d(a, b)          # b's halo rows are now stale in the neighbours
+    c.batch_begin()
+    c.jacobi2d(b, a)          # first execution copies them; a second would not
+    g = c.batch_end()
+    assert not c.batch_info(g)["replay_safe"]
+    assert c.batch_launch(g, 1, raw=True) == jacc.ERR_UNSUPPORTED
+    assert race_check(c.trace()) == []
+
+
+def test_batch_persistent_group_packs_independent_loops():
+    c = dry(2)
+    arrs = []
+    for i in range(6):
+        u = np.zeros((10 + i, 12))
+        v = np.zeros((10 + i, 12))
+        c.enter(u, halo=(1, 1), K=1)
+        c.enter(v, halo=(1, 1), K=1)
+        arrs.append((u, v))
+    h = np.zeros((6, 5, 7))
+    g3 = np.zeros((6, 5, 7))
+    c.enter(h, halo=(1, 1), K=1)
+    c.enter(g3, halo=(1, 1), K=1)
+    pcfg = jacc.config(tile=2, vec=2, persistent=1)
+    c.batch_begin()
+    for u, v in arrs[:3]:
+        c.jacobi2d(u, v, cfg=pcfg)
+    c.heat3d(h, g3, 0.1, cfg=jacc.config(tile=1, vec=1, persistent=1))
+    c.jacobi2d(arrs[0][1], arrs[0][0], cfg=pcfg)   # reads a pending output: new group
+    for u, v in arrs[3:]:
+        c.jacobi2d(u, v, cfg=jacc.config(tile=1, vec=2, persistent=1))
+    c.jacobi2d(arrs[1][1], arrs[1][0])              # non-persistent: flushes first
+    g = c.batch_end()
+    info = c.batch_info(g)
+    assert info["loops"] == 9 and info["persistent_groups"] == 2
+    tr = c.trace()
+    groups = [t for t in tr if t["op"] == "KERNEL" and t["dst"] == -1]
+    assert [-t["kind"] for t in groups] == [4, 4]
+    assert race_check(tr) == [] and freshness_check(tr) == []
+
+
+def test_persistent_outside_batch_is_invalid():
+    c = dry(1)
+    a = np.zeros((10, 10))
+    b = np.zeros((10, 10))
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    assert c.jacobi2d(a, b, cfg=jacc.config(persistent=1), raw=True) == jacc.ERR_INVALID
+    c.batch_begin()
+    assert c.enter(np.zeros(4), raw=True) == jacc.ERR_INVALID   # no data regions inside a batch
+    assert c.loop(jacc.SUM, jacc.bounds((0, 10)), [(a, jacc.READ, 0, 0, 0)], scalars=(0.0,), sync=True,
+                  raw=True) == jacc.ERR_INVALID
+    g = c.batch_end()
+    assert g == 0
+
+
+def test_independent_k1_loops_spread_over_streams():
+    c = dry(4)
+    pairs = []
+    for i in range(4):
+        u = np.zeros((12, 12))
+        v = np.zeros((12, 12))
+        c.enter(u, halo=(1, 1), K=1)
+        c.enter(v, halo=(1, 1), K=1)
+        pairs.append((u, v))
+    c.trace_clear()
+    for u, v in pairs:
+        c.jacobi2d(u, v)
+    streams = [t["stream"] for t in c.trace() if t["op"] == "KERNEL"]
+    assert len(set(streams)) == 4
+    assert race_check(c.trace()) == []

@@ -2,7 +2,8 @@
 
 * race_check: happens-before race detector.  Ops on one stream are ordered;
   a WAIT orders the waiting stream after the awaited op; a host SYNC orders
-  every later op after the synchronised stream.  Two accesses to the same
+  every later op after the synchronised stream; a JOIN orders every later op
+  after every earlier one.  Two accesses to the same
   rows of the same slab from different streams, at least one a write, must
   be ordered, otherwise the trace has a race.
 * freshness_check: replays the trace in issue order with symbolic versions
@@ -35,11 +36,14 @@ def race_check(trace, skip_wait=None):
             if skip_wait is not None and wait_i == skip_wait:
                 continue
             d, q, m = t["stream"], t["src"], t["seq"]
-            vc[d] = _max(vc[d], op_vc[(q, m)])
+            vc[d] = _max(vc[d], op_vc.get((q, m), {q: m}))  # ops before the trace started: only q's clock
         elif op == "SYNC":
             s, m = t["stream"], t["seq"]
             if (s, m) in op_vc:
                 host = _max(host, op_vc[(s, m)])
+        elif op == "JOIN":
+            for v in op_vc.values():
+                host = _max(host, v)
         elif op == "ACCESS":
             pending[(t["stream"], t["seq"])].append(t)
         elif op in OPS_WITH_SEQ:
