@@ -271,6 +271,46 @@ int jacc_time_loop(jacc_ctx *ctx, int kind, const jacc_bounds *bounds, int nargs
 int jacc_slab_info(jacc_ctx *ctx, void *host, int p, void **dev, int64_t *row_lo,
                    int64_t *row_hi);
 
+/* ---- learned cost model -------------------------------------------------------
+ * A small FP32 network that predicts the log run time of a loop nest under a
+ * launch configuration from F standardised features (1 <= F <= 16):
+ *   h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), h3 = relu(W3 h2 + b3),
+ *   yhat = w4 . h3 + b4, with hidden width 64 and relu'(0) = 0;
+ * loss = mean over a batch of (yhat - y)^2; Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8) with bias correction.  Forward, backward, gradient reduction and
+ * Adam run in the library's HIP kernels on the context's stream 0; host
+ * arrays are copied in and out (all calls return after their results are on
+ * the host).  The paper has no learned model; it names auto-tuning as
+ * future work (Sec. "Conclusion").
+ * Parameter vector (floats): W1 [64 x F] row-major | b1 [64] | W2 [64 x 64] |
+ * b2 [64] | W3 [64 x 64] | b3 [64] | w4 [64] | b4 [1]. */
+typedef struct jacc_model jacc_model;
+/* Number of parameters for F features (or JACC_ERR_INVALID). */
+int jacc_model_nparams(int nfeat);
+/* New model on ctx with all parameters zero, scaler mean 0 / std 1. */
+int jacc_model_create(jacc_ctx *ctx, int nfeat, jacc_model **out);
+int jacc_model_destroy(jacc_model *m);
+/* Parameters in the layout above; setting them also resets Adam's state. */
+int jacc_model_set_params(jacc_model *m, const float *params, int nparams);
+int jacc_model_get_params(jacc_model *m, float *params, int nparams);
+/* Feature standardisation x' = (x - mean) / std applied inside the forward
+ * pass (std > 0). */
+int jacc_model_set_scaler(jacc_model *m, const float *mean, const float *stdev);
+/* yhat[0..n) for the raw feature rows X [n x F]. */
+int jacc_model_predict(jacc_model *m, const float *X, int n, float *yhat);
+/* Loss and parameter gradient of the batch X [n x F], y [n] (grad: nparams
+ * floats, either output may be NULL). */
+int jacc_model_gradients(jacc_model *m, const float *X, const float *y, int n, float *grad, float *loss);
+/* One Adam step with learning rate lr on the gradient of the last
+ * jacc_model_gradients call. */
+int jacc_model_adam_step(jacc_model *m, float lr);
+/* Minibatch training: `epochs` passes over (X, y) in an order shuffled per
+ * epoch from `seed` (splitmix64 + Fisher-Yates), minibatches of `batch`
+ * rows, one Adam step each.  epoch_loss[e] (optional) receives the mean
+ * minibatch loss of epoch e. */
+int jacc_model_train(jacc_model *m, const float *X, const float *y, int n, int epochs, int batch, float lr,
+                     uint64_t seed, float *epoch_loss);
+
 /* ---- operation trace (planning and tests) ------------------------------ */
 enum {
     JACC_OP_ALLOC = 1,   /* array a, partition dst, rows [lo,hi) */

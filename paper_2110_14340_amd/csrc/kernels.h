@@ -96,4 +96,30 @@ hipError_t launch_finalise(const double *partials, int64_t n, double *out, hipSt
 hipError_t launch_gemm(const Launch &L, hipStream_t s);
 hipError_t launch_spmv(const Launch &L, hipStream_t s);
 
+// ---- learned cost model (k_mlp.hip) ----------------------------------------
+constexpr int kMlpHidden = 64;
+constexpr int kMlpMaxFeatures = 16;
+
+// Device buffers of one model: parameters, Adam moments, gradient, feature
+// scaler, and per-sample scratch for `cap` samples.
+struct MlpBufs {
+    int F = 0, cap = 0;
+    float *params = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *mu = nullptr, *sd = nullptr;
+    float *xs = nullptr, *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *yhat = nullptr, *g = nullptr;
+    float *d1 = nullptr, *d2 = nullptr, *d3 = nullptr, *sqerr = nullptr;
+    float *loss = nullptr;  // loss of each training step
+    int64_t loss_at = 0;    // index written by the next backward pass
+};
+int mlp_nparams(int F);
+size_t mlp_lds_bytes(int F);
+// Forward pass of n samples (rows idx[b] of X, or row b when idx is null);
+// keep = store the activations for a backward pass.
+hipError_t mlp_forward(const MlpBufs &B, const float *X, const int *idx, int n, float *yhat, bool keep,
+                       hipStream_t s);
+// Deltas, parameter gradient (B.grad) and mean squared error (B.loss[loss_at])
+// of the last kept forward pass.
+hipError_t mlp_backward(const MlpBufs &B, const float *y, const int *idx, int n, hipStream_t s);
+// One Adam step (t is 1-based).
+hipError_t mlp_adam(const MlpBufs &B, int t, float lr, hipStream_t s);
+
 }  // namespace jk

@@ -394,6 +394,9 @@ int ensure_wait(jacc_ctx *c, int d, int q, int64_t n) {
     int idx = -1;
     int rc = ensure_event(c, q, n, &idx);
     if (rc) return rc;
+    if (idx < 0)
+        return set_err(c, JACC_ERR_INVALID, "internal: no event of stream %d covers op %lld (recorded %lld)", q,
+                       (long long)n, (long long)c->st[q].recorded);
     const EvEntry &E = c->st[q].ring[idx];
     if (live(c)) HIPCHK(c, hipStreamWaitEvent(D.s, E.ev, 0), "hipStreamWaitEvent");
     trace(c, JACC_OP_WAIT, d, -1, q, -1, 0, 0, 0, E.covers);
@@ -1646,3 +1649,16 @@ int jacc_trace_clear(jacc_ctx *c) {
 }
 
 }  // extern "C"
+
+// ---- internal access for other library modules -------------------------------
+#include "ctx_internal.h"
+
+namespace jr {
+bool dry(const jacc_ctx *c) { return c->dry; }
+bool failed(const jacc_ctx *c) { return c->status != JACC_OK; }
+hipStream_t stream0(const jacc_ctx *c) { return c->st[0].s; }
+int alloc(jacc_ctx *c, size_t bytes, void **out) { return dev_alloc(c, bytes, out); }
+void release(jacc_ctx *c, void *p) { dev_free(c, p); }
+int device_error(jacc_ctx *c, hipError_t e, const char *what) { return dev_fail(c, e, what); }
+int error(jacc_ctx *c, int code, const char *msg) { return set_err(c, code, "%s", msg); }
+}  // namespace jr

@@ -110,6 +110,17 @@ def lib():
     L.jacc_time_loop.argtypes = [vp, i32, ctypes.POINTER(Bounds), i32, ctypes.POINTER(Arg),
                                  ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(Config), i32, i32,
                                  ctypes.POINTER(ctypes.c_double)]
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.jacc_model_nparams.argtypes = [i32]
+    L.jacc_model_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    L.jacc_model_destroy.argtypes = [vp]
+    L.jacc_model_set_params.argtypes = [vp, fp, i32]
+    L.jacc_model_get_params.argtypes = [vp, fp, i32]
+    L.jacc_model_set_scaler.argtypes = [vp, fp, fp]
+    L.jacc_model_predict.argtypes = [vp, fp, i32, fp]
+    L.jacc_model_gradients.argtypes = [vp, fp, fp, i32, fp, fp]
+    L.jacc_model_adam_step.argtypes = [vp, ctypes.c_float]
+    L.jacc_model_train.argtypes = [vp, fp, fp, i32, i32, i32, ctypes.c_float, ctypes.c_uint64, fp]
     L.jacc_trace_len.argtypes = [vp]
     L.jacc_trace_get.argtypes = [vp, i32, ctypes.POINTER(TraceOp)]
     L.jacc_trace_clear.argtypes = [vp]
@@ -381,3 +392,88 @@ class Context:
 
     def trace_clear(self):
         self.L.jacc_trace_clear(self.ctx)
+
+
+# ---- learned cost model -------------------------------------------------------
+PARAM_ORDER = ("W1", "b1", "W2", "b2", "W3", "b3", "w4", "b4")
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Model:
+    """The FP32 cost-model network living on a context's device (its
+    forward, backward and Adam run in the library's HIP kernels)."""
+
+    H = 64
+
+    def __init__(self, ctx, nfeat):
+        self.c = ctx
+        self.L = ctx.L
+        self.F = nfeat
+        self.P = self.L.jacc_model_nparams(nfeat)
+        self.m = ctypes.c_void_p()
+        ctx._check(self.L.jacc_model_create(ctx.ctx, nfeat, ctypes.byref(self.m)))
+
+    def close(self):
+        if self.m:
+            self.L.jacc_model_destroy(self.m)
+            self.m = ctypes.c_void_p()
+
+    def shapes(self):
+        H, F = self.H, self.F
+        return {"W1": (H, F), "b1": (H,), "W2": (H, H), "b2": (H,), "W3": (H, H), "b3": (H,), "w4": (H,),
+                "b4": (1,)}
+
+    def pack(self, params):
+        return _f32(np.concatenate([np.asarray(params[k], dtype=np.float64).reshape(-1) for k in PARAM_ORDER]))
+
+    def unpack(self, flat):
+        out, o = {}, 0
+        for k in PARAM_ORDER:
+            shp = self.shapes()[k]
+            n = int(np.prod(shp))
+            out[k] = np.asarray(flat[o:o + n]).reshape(shp)
+            o += n
+        return out
+
+    def set_params(self, params):
+        flat = self.pack(params) if isinstance(params, dict) else _f32(params)
+        self.c._check(self.L.jacc_model_set_params(self.m, _fptr(flat), flat.size))
+
+    def get_params(self):
+        flat = np.zeros(self.P, dtype=np.float32)
+        self.c._check(self.L.jacc_model_get_params(self.m, _fptr(flat), self.P))
+        return self.unpack(flat)
+
+    def set_scaler(self, mean, std):
+        mu, sd = _f32(mean), _f32(std)
+        self.c._check(self.L.jacc_model_set_scaler(self.m, _fptr(mu), _fptr(sd)))
+
+    def predict(self, X):
+        X = _f32(X)
+        out = np.zeros(X.shape[0], dtype=np.float32)
+        self.c._check(self.L.jacc_model_predict(self.m, _fptr(X), X.shape[0], _fptr(out)))
+        return out
+
+    def gradients(self, X, y):
+        X, y = _f32(X), _f32(y)
+        g = np.zeros(self.P, dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        self.c._check(self.L.jacc_model_gradients(self.m, _fptr(X), _fptr(y), X.shape[0], _fptr(g), _fptr(loss)))
+        return float(loss[0]), self.unpack(g)
+
+    def adam_step(self, lr=1e-3):
+        self.c._check(self.L.jacc_model_adam_step(self.m, ctypes.c_float(lr)))
+
+    def train(self, X, y, epochs, batch=256, lr=1e-3, seed=0):
+        X, y = _f32(X), _f32(y)
+        losses = np.zeros(max(1, epochs), dtype=np.float32)
+        self.c._check(self.L.jacc_model_train(self.m, _fptr(X), _fptr(y), X.shape[0], epochs, batch,
+                                              ctypes.c_float(lr), ctypes.c_uint64(seed), _fptr(losses)))
+        return losses[:epochs]
