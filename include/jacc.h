@@ -26,7 +26,10 @@
  *     loops that write element i of dim 0 from outer iteration i.
  *   - Coherence: before a partition runs, the rows it reads that its slab
  *     does not hold in their latest version are copied from the partition
- *     that wrote them last (device-local copies).  This replaces the paper's
+ *     that wrote them last (device-local copies).  For the stencil kinds the
+ *     producing partition instead also writes the output rows that other
+ *     slabs hold as halo (a write-through restricted to the holders of each
+ *     row), so no copy is needed at all.  Both replace the paper's
  *     send-everything-after-each-kernel scheme with range-driven transfers.
  *   - Asynchrony: partition p's work runs on stream p.  Cross-stream waits
  *     are inserted only for the rows actually shared (read-after-write and
@@ -160,7 +163,9 @@ enum {
 enum {
     JACC_INIT_DRYRUN = 1u << 0, /* plan and trace only: no HIP call, fake device addresses */
     JACC_INIT_TRACE = 1u << 1,  /* record every planned operation (see jacc_trace_get) */
-    JACC_INIT_SERIALIZE = 1u << 2 /* one stream for every partition, device sync after each op */
+    JACC_INIT_SERIALIZE = 1u << 2, /* one stream for every partition, device sync after each op */
+    JACC_INIT_LAZY = 1u << 3       /* halo rows are pulled before each read (default: a stencil
+                                      partition also writes the output rows other slabs hold) */
 };
 
 /* Create a context with K partitions (1 <= K <= 64).  streams: K hipStream_t
@@ -226,12 +231,11 @@ const char *jacc_last_error(const jacc_ctx *ctx);
 /* ---- batches: many loop nests in one captured HIP graph ---------------------
  * The paper overlaps independent kernels through asynchronous queues to gain
  * kernel-level parallelism (Sec. "Automated Asynchronous Execution"); here a
- * whole sequence of loop calls is captured once into a hipGraph (partition
- * streams forked from and joined back into stream 0) and replayed.
+ * whole sequence of loop calls is captured once into a hipGraph and replayed.
  *
- * jacc_batch_begin starts stream capture: the following jacc_parallel_loop
- * calls are planned as usual (copies, waits, launches) but recorded instead
- * of executed.  Loops whose configuration has persistent = 1 are not
+ * jacc_batch_begin starts stream capture on stream 0: the following
+ * jacc_parallel_loop calls are planned as usual (copies, launches) but
+ * recorded into a single-stream graph instead of executed.  Loops whose configuration has persistent = 1 are not
  * launched one by one: consecutive independent ones are packed into one
  * persistent-kernel launch that walks a task table of all their tiles.  No
  * data_enter/exit, update, wait or synchronous reduction is allowed inside.

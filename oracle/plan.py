@@ -85,11 +85,15 @@ class ArrayState:
         self.valid = [set(s) for s in self.slabs]
 
 
-def plan_loop(arrays, lb, ub, args):
+def plan_loop(arrays, lb, ub, args, refresh="pull"):
     """Plan one loop nest.
 
     arrays: dict name -> ArrayState (all partitioned arrays share E and K).
     args: list of (name, mode, off_lo, off_hi, whole) with mode 'r' or 'w'.
+    refresh: "pull" copies stale rows before a read; "holders" has every
+    write also refresh the other slabs that hold the written rows (the
+    paper's send-updated-data-after-the-kernel, restricted to the holders),
+    so nothing is ever stale.
     Returns a list, per partition p, of dicts with keys I (set), reads
     {name: rows}, writes {name: rows}, copies [(name, src, lo, hi)], and
     updates the states.  Raises ValueError on a range violation.
@@ -153,5 +157,8 @@ def plan_loop(arrays, lb, ub, args):
             st.valid[p] |= rows
             for q in range(K):
                 if q != p:
-                    st.valid[q] -= rows
+                    if refresh == "holders":
+                        st.valid[q] |= rows & st.slabs[q]
+                    else:
+                        st.valid[q] -= rows
     return plans

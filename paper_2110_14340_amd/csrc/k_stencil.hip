@@ -78,13 +78,24 @@ __device__ __forceinline__ void store_masked(double *q, const double (&o)[VEC], 
     }
 }
 
+// Stores an output row (or plane) `r` at offset `off` from its row start,
+// and again into every mirror holding row r (uniform test per row).
+template <int VEC>
+__device__ __forceinline__ void store_out(double *out, int64_t off, int64_t r, const Mirrors &mir,
+                                          const double (&o)[VEC], bool all, const bool (&comp)[VEC]) {
+    store_masked<VEC>(out + off, o, all, comp);
+    for (int k = 0; k < mir.n; ++k)
+        if (r >= mir.m[k].lo && r < mir.m[k].hi) store_masked<VEC>(mir.m[k].ptr + off, o, all, comp);
+}
+
 // ---------------------------------------------------------------------------
 // Jacobi-2D tile: lanes [tx] of row-group [ty] of workgroup tile (bxi, byi)
 // ---------------------------------------------------------------------------
 template <int VEC>
 __device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, double *__restrict__ out, int64_t nx,
                                             int64_t r_lo, int64_t r_hi, int64_t c_lo, int64_t c_hi, int64_t col0,
-                                            int tile, int64_t bxi, int64_t byi, int tx, int ty, int bdx, int bdy) {
+                                            int tile, const Mirrors &mir, int64_t bxi, int64_t byi, int tx, int ty,
+                                            int bdx, int bdy) {
     const int lane = tx & (kWave - 1);
     const int64_t j = col0 + (bxi * bdx + tx) * VEC;
     const int64_t i0 = r_lo + (byi * bdy + ty) * tile;
@@ -128,7 +139,7 @@ __device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, doubl
                     const double horz = left[v] + right[v];
                     o[v] = 0.25 * (vert + horz);
                 }
-                store_masked<VEC>(out + row * nx + j, o, all, comp);
+                store_out<VEC>(out, row * nx + j, row, mir, o, all, comp);
             }
         }
 #pragma unroll
@@ -141,8 +152,8 @@ __device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, doubl
 template <int VEC>
 __global__ void __launch_bounds__(1024)
 jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t nx, int64_t r_lo, int64_t r_hi,
-                int64_t c_lo, int64_t c_hi, int64_t col0, int tile) {
-    jacobi_tile<VEC>(in, out, nx, r_lo, r_hi, c_lo, c_hi, col0, tile, blockIdx.x, blockIdx.y, threadIdx.x,
+                int64_t c_lo, int64_t c_hi, int64_t col0, int tile, Mirrors mir) {
+    jacobi_tile<VEC>(in, out, nx, r_lo, r_hi, c_lo, c_hi, col0, tile, mir, blockIdx.x, blockIdx.y, threadIdx.x,
                      threadIdx.y, blockDim.x, blockDim.y);
 }
 
@@ -154,7 +165,8 @@ template <int VEC, bool RES>
 __device__ __forceinline__ double heat_tile(const double *__restrict__ in, double *__restrict__ out, int64_t ny,
                                             int64_t nx, int64_t z_lo, int64_t z_hi, int64_t y_lo, int64_t y_hi,
                                             int64_t x_lo, int64_t x_hi, int64_t col0, int tile, double alpha,
-                                            int64_t bxi, int64_t byi, int64_t bzi, int tx, int ty, int bdx, int bdy) {
+                                            const Mirrors &mir, int64_t bxi, int64_t byi, int64_t bzi, int tx,
+                                            int ty, int bdx, int bdy) {
     const int lane = tx & (kWave - 1);
     const int64_t x = col0 + (bxi * bdx + tx) * VEC;
     const int64_t y = y_lo + byi * bdy + ty;
@@ -218,7 +230,7 @@ __device__ __forceinline__ double heat_tile(const double *__restrict__ in, doubl
                         acc += d * d;
                     }
                 }
-                store_masked<VEC>(out + z * plane + y * nx + x, o, all, comp);
+                store_out<VEC>(out, z * plane + y * nx + x, z, mir, o, all, comp);
             }
         }
 #pragma unroll
@@ -233,11 +245,11 @@ template <int VEC, bool RES>
 __global__ void __launch_bounds__(1024)
 heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t ny, int64_t nx, int64_t z_lo,
               int64_t z_hi, int64_t y_lo, int64_t y_hi, int64_t x_lo, int64_t x_hi, int64_t col0, int tile,
-              double alpha, double *__restrict__ wg_partials) {
+              double alpha, double *__restrict__ wg_partials, Mirrors mir) {
     __shared__ double sh[16];
     const double acc = heat_tile<VEC, RES>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, alpha,
-                                           blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, threadIdx.y, blockDim.x,
-                                           blockDim.y);
+                                           mir, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, threadIdx.y,
+                                           blockDim.x, blockDim.y);
     if (RES) {
         const double s = block_sum(acc, sh);
         if (threadIdx.x == 0 && threadIdx.y == 0) {
@@ -268,20 +280,20 @@ persistent_kernel(const PTask *__restrict__ tasks, int ntasks, int64_t total) {
         const int64_t rest = local / T.gx;
         if (T.kind == JACC_LOOP_JACOBI2D) {
             if (T.vec == 2)
-                jacobi_tile<2>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, bxi, rest,
-                               threadIdx.x, 0, kPersistentThreads, 1);
+                jacobi_tile<2>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.mir, bxi,
+                               rest, threadIdx.x, 0, kPersistentThreads, 1);
             else
-                jacobi_tile<1>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, bxi, rest,
-                               threadIdx.x, 0, kPersistentThreads, 1);
+                jacobi_tile<1>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.mir, bxi,
+                               rest, threadIdx.x, 0, kPersistentThreads, 1);
         } else {
             const int64_t byi = rest % T.gy, bzi = rest / T.gy;
             if (T.vec == 2)
                 (void)heat_tile<2, false>(T.in, T.out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2],
-                                          T.hi[2], T.col0, T.tile, T.alpha, bxi, byi, bzi, threadIdx.x, 0,
+                                          T.hi[2], T.col0, T.tile, T.alpha, T.mir, bxi, byi, bzi, threadIdx.x, 0,
                                           kPersistentThreads, 1);
             else
                 (void)heat_tile<1, false>(T.in, T.out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2],
-                                          T.hi[2], T.col0, T.tile, T.alpha, bxi, byi, bzi, threadIdx.x, 0,
+                                          T.hi[2], T.col0, T.tile, T.alpha, T.mir, bxi, byi, bzi, threadIdx.x, 0,
                                           kPersistentThreads, 1);
         }
     }
@@ -309,10 +321,10 @@ hipError_t launch_jacobi2d(const Launch &L, hipStream_t s) {
     double *out = (double *)L.a[1].ptr;
     if (c.vec == 2)
         hipLaunchKernelGGL(jacobi2d_kernel<2>, grid, block, 0, s, in, out, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1],
-                           col0, c.tile);
+                           col0, c.tile, L.mir);
     else
         hipLaunchKernelGGL(jacobi2d_kernel<1>, grid, block, 0, s, in, out, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1],
-                           col0, c.tile);
+                           col0, c.tile, L.mir);
     return hipGetLastError();
 }
 
@@ -345,7 +357,7 @@ hipError_t launch_heat3d(const Launch &L, hipStream_t s) {
     const double alpha = L.scalars[0];
     const bool res = L.wg_partials != nullptr;
 #define HEAT_ARGS \
-    in, out, ny, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1], L.lo[2], L.hi[2], col0, c.tile, alpha, L.wg_partials
+    in, out, ny, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1], L.lo[2], L.hi[2], col0, c.tile, alpha, L.wg_partials, L.mir
     if (c.vec == 2) {
         if (res)
             hipLaunchKernelGGL((heat3d_kernel<2, true>), grid, block, 0, s, HEAT_ARGS);
@@ -368,6 +380,7 @@ bool make_task(const Launch &L, PTask *t) {
     t->tile = L.cfg.tile;
     t->in = (const double *)L.a[0].ptr;
     t->out = (double *)L.a[1].ptr;
+    t->mir = L.mir;
     for (int d = 0; d < 3; ++d) {
         t->lo[d] = L.lo[d];
         t->hi[d] = L.hi[d];

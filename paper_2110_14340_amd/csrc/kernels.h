@@ -20,6 +20,18 @@ struct Cfg {
     int bx, by, tile, vec, persistent;
 };
 
+// Write-through targets of a stencil launch: rows [lo, hi) of dim 0 that the
+// launch writes are also stored at `ptr` (biased like Arg::ptr), which is
+// another partition's slab holding those rows as halo.
+struct Mirror {
+    double *ptr;
+    int64_t lo, hi;
+};
+struct Mirrors {
+    Mirror m[2];
+    int n;
+};
+
 // One partition's launch of one loop nest.
 struct Launch {
     int kind;
@@ -30,6 +42,7 @@ struct Launch {
     int nargs;
     double scalars[4];
     Cfg cfg;
+    Mirrors mir;  // stencil kinds only
     // reductions: workgroup partials go to `wg_partials` (capacity
     // `wg_capacity` doubles); the finaliser writes their ordered sum to
     // `part_out`.  Both null when the loop reduces nothing.
@@ -71,6 +84,7 @@ struct PTask {
     double alpha;
     int64_t gx, gy, gz;
     int64_t ntiles, tile_begin;
+    Mirrors mir;
 };
 constexpr int kPersistentThreads = 256;
 

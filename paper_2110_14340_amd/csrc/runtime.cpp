@@ -251,6 +251,7 @@ struct jacc_ctx {
     int K = 1;
     unsigned flags = 0;
     bool dry = false, tracing = false, serialize = false;
+    bool lazy = false;       // pull halo rows before reads instead of mirroring them at writes
     bool plan_only = false;  // planning pass without device work (batch replay check)
     jacc_allocator alloc{};
     bool use_hipmalloc = true;
@@ -649,8 +650,8 @@ bool desc_equal(const jacc_array_desc &a, const jacc_array_desc &b) {
 
 // ---- persistent task groups ------------------------------------------------
 // Launches the pending persistent tasks as one persistent kernel on stream 0:
-// the task table is staged through pinned memory into the batch's device
-// table, then a grid sized to the chip walks all tasks' tiles.
+// a grid sized to the chip walks all tasks' tiles, reading the task records
+// from the batch's device table.
 int flush_group(jacc_ctx *c) {
     if (c->ptasks.empty()) return JACC_OK;
     Batch *B = c->cur;
@@ -668,12 +669,10 @@ int flush_group(jacc_ctx *c) {
         tiles += t.ntiles;
     }
     if (live(c)) {
-        jk::PTask *h = B->host_tasks + B->tasks_used;
-        jk::PTask *d = B->dev_tasks + B->tasks_used;
-        std::memcpy(h, c->ptasks.data(), (size_t)n * sizeof(jk::PTask));
-        HIPCHK(c, hipMemcpyAsync(d, h, (size_t)n * sizeof(jk::PTask), hipMemcpyHostToDevice, c->st[s].s),
-               "hipMemcpyAsync(task table)");
-        HIPCHK(c, jk::launch_persistent(d, n, tiles, c->st[s].s), "persistent kernel launch");
+        // the table is written to pinned memory now and uploaded once when
+        // the batch closes, before the graph first runs
+        std::memcpy(B->host_tasks + B->tasks_used, c->ptasks.data(), (size_t)n * sizeof(jk::PTask));
+        HIPCHK(c, jk::launch_persistent(B->dev_tasks + B->tasks_used, n, tiles, c->st[s].s), "persistent kernel launch");
     }
     B->tasks_used += n;
     B->groups++;
@@ -682,8 +681,7 @@ int flush_group(jacc_ctx *c) {
     c->ptasks.clear();
     c->paccs.clear();
     c->parrays.clear();
-    int idx;
-    return ensure_event(c, s, c->st[s].seq, &idx);
+    return JACC_OK;
 }
 
 bool pending_touches(const jacc_ctx *c, const Array *A) {
@@ -923,15 +921,33 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
                 if (c->st[s].last_use < c->st[base].last_use) base = s;
         }
     }
+    // inside a batch everything is captured on stream 0 (a single-stream
+    // graph); the partitions of a stencil step become tiles of one
+    // persistent launch when the configuration asks for it
+    const bool one_stream = c->serialize || c->cur != nullptr;
+    auto stream_for = [&](int p) { return (one_stream || persistent) ? 0 : (base + p) % ns; };
     ++c->tick;
-    for (int p = 0; p < K; ++p) c->st[c->serialize ? 0 : (base + p) % ns].last_use = c->tick;
+    for (int p = 0; p < K; ++p) c->st[stream_for(p)].last_use = c->tick;
     for (int i = 0; i < nargs; ++i)
         if (args[i].mode & JACC_WRITE) arr[i]->last_stream = base;
+    // mirrors: a stencil partition also writes the rows of its output that
+    // other slabs hold as halo (at most one neighbour block on each side)
+    const bool can_mirror =
+        !c->lazy && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) && !P->whole && K > 1;
     std::vector<int> order;  // streams of the partitions that reduce, in partition order
     for (int p = 0; p < K; ++p) {
         const PartPlan &pp = plan[p];
         if (pp.iters.empty()) continue;
-        const int s = persistent ? 0 : (c->serialize ? 0 : (base + p) % ns);
+        const int s = stream_for(p);
+        std::vector<std::pair<int, Range>> mirrors;
+        if (can_mirror) {
+            for (int q = 0; q < K; ++q) {
+                if (q == p) continue;
+                Range x = isect(pp.rng[primary], P->slabs[q].rows);
+                if (!x.empty()) mirrors.push_back({q, x});
+            }
+            if (mirrors.size() > 2) mirrors.clear();  // then the readers pull instead
+        }
         for (int i = 0; i < nargs; ++i)
             if (args[i].mode & JACC_READ) {
                 rc = make_fresh(c, arr[i], p, pp.rng[i], s);
@@ -951,6 +967,16 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             LP.a[i].slab_hi = sl.rows.hi;
             LP.a[i].row_elems = arr[i]->row_elems;
         }
+        LP.mir.n = (int)mirrors.size();
+        for (size_t k = 0; k < mirrors.size(); ++k) {
+            const Slab &sq = P->slabs[mirrors[k].first];
+            LP.mir.m[k].ptr = (double *)((char *)sq.dev - (intptr_t)((size_t)sq.rows.lo * P->row_bytes));
+            LP.mir.m[k].lo = mirrors[k].second.lo;
+            LP.mir.m[k].hi = mirrors[k].second.hi;
+        }
+        auto note_mirrors = [&]() {
+            for (auto &m : mirrors) P->valid[m.first].add(m.second);
+        };
         if (persistent) {
             jk::PTask t;
             if (!jk::make_task(LP, &t))
@@ -961,8 +987,10 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
                 if (args[i].mode & JACC_WRITE) c->paccs.push_back({arr[i], p, pp.rng[i], true});
                 c->parrays.push_back(arr[i]);
             }
+            for (auto &m : mirrors) c->paccs.push_back({P, m.first, m.second, true});
             for (int i = 0; i < nargs; ++i)
                 if (args[i].mode & JACC_WRITE) note_write(arr[i], p, pp.rng[i]);
+            note_mirrors();
             continue;
         }
         for (int i = 0; i < nargs; ++i) {
@@ -974,6 +1002,10 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
                 rc = hazard(c, arr[i], p, pp.rng[i], true, s);
                 if (rc) return rc;
             }
+        }
+        for (auto &m : mirrors) {  // writes into another partition's slab
+            rc = hazard(c, P, m.first, m.second, true, s);
+            if (rc) return rc;
         }
         if (want_red) {
             // partials[s] and the workgroup scratch of stream s are read by
@@ -997,16 +1029,17 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
         trace(c, JACC_OP_KERNEL, s, -1, -1, p, kind, pp.iters.lo, pp.iters.hi, c->st[s].seq);
         rc = post_op(c);
         if (rc) return rc;
-        if (nstreams(c) > 1) {  // a precise event for partitions that will read these rows
+        if (nstreams(c) > 1 && !one_stream) {  // a precise event for partitions that will read these rows
             int idx;
             rc = ensure_event(c, s, c->st[s].seq, &idx);
             if (rc) return rc;
         }
         for (int i = 0; i < nargs; ++i)
             if (args[i].mode & JACC_WRITE) note_write(arr[i], p, pp.rng[i]);
+        note_mirrors();
     }
     if (want_red) {
-        const int s0 = c->serialize ? 0 : base % ns;
+        const int s0 = one_stream ? 0 : base % ns;
         for (int s : order) {
             rc = ensure_wait(c, s0, s, c->st[s].seq);
             if (rc) return rc;
@@ -1134,6 +1167,7 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
         c->dry = (flags & JACC_INIT_DRYRUN) != 0;
         c->tracing = (flags & JACC_INIT_TRACE) != 0;
         c->serialize = (flags & JACC_INIT_SERIALIZE) != 0;
+        c->lazy = (flags & JACC_INIT_LAZY) != 0;
         if (alloc) {
             c->alloc = *alloc;
             c->use_hipmalloc = false;
@@ -1452,8 +1486,6 @@ int jacc_batch_begin(jacc_ctx *c) {
     if (rc) return rc;
     if (live(c)) HIPCHK(c, hipStreamBeginCapture(c->st[0].s, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
     c->cur = B;
-    rc = fork_from0(c);
-    if (rc) return rc;
     assume_joined(c);
     c->oplog = &B->captured;
     return JACC_OK;
@@ -1467,13 +1499,13 @@ int jacc_batch_end(jacc_ctx *c, int *graph_id) {
     int rc = flush_group(c);
     c->oplog = nullptr;
     if (rc) return rc;
-    for (int s = 1; s < nstreams(c) && live(c); ++s) {  // join every stream back into the origin
-        HIPCHK(c, hipEventRecord(c->st[s].join_ev, c->st[s].s), "hipEventRecord");
-        HIPCHK(c, hipStreamWaitEvent(c->st[0].s, c->st[s].join_ev, 0), "hipStreamWaitEvent");
-    }
     if (live(c)) {
         HIPCHK(c, hipStreamEndCapture(c->st[0].s, &B->graph), "hipStreamEndCapture");
         HIPCHK(c, hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        if (B->tasks_used > 0)
+            HIPCHK(c, hipMemcpy(B->dev_tasks, B->host_tasks, (size_t)B->tasks_used * sizeof(jk::PTask),
+                                hipMemcpyHostToDevice),
+                   "hipMemcpy(task tables)");
     }
     c->cur = nullptr;
     c->batches.push_back(B);

@@ -1,0 +1,132 @@
+"""Batched/learned experiment: hundreds of uneven stencil sweeps in one
+captured graph, configured three ways — by the exhaustive autotuner, by the
+learned cost model, and by a fixed default configuration — and the graph
+time of each (regret of the model against the tuner, gain over the default).
+
+Shapes: 2-D Jacobi sweeps with both sides log-uniform in [64, 4096] and 3-D
+heat sweeps with sides log-uniform in [32, 512] (test batch seed 5, data
+seed 6); the model is trained only on timings of other shapes (seed 7+).
+These stand in for applications with tens to hundreds of kernels of uneven
+sizes (the paper's benchmark table).
+"""
+import math
+import time
+
+import numpy as np
+
+from . import inputs, jacc, tuner
+
+
+def _data(shape, seed):
+    return inputs.jacobi_grid(*shape, seed=seed) if len(shape) == 2 else inputs.heat_field(*shape, seed=seed)
+
+
+def _sweep(ctx, u, v, cfg):
+    c = jacc.config(bx=cfg["bx"], by=cfg["by"], tile=cfg["tile"], vec=cfg["vec"], persistent=cfg["persistent"])
+    if u.ndim == 2:
+        ctx.jacobi2d(u, v, cfg=c)
+    else:
+        ctx.heat3d(u, v, 0.1, cfg=c)
+
+
+def graph_time(shapes, datas, configs, reps=10, keep_outputs=False):
+    """Enters every loop's arrays with its configuration's K, captures all
+    sweeps into one graph, and returns (median ms of `reps` replays, outputs)."""
+    K = max(c["K"] for c in configs)
+    ctx = jacc.Context(max(2, K))
+    ins, outs = [], []
+    try:
+        for sh, d, cfg in zip(shapes, datas, configs):
+            u = d.copy()
+            v = d.copy()
+            ctx.enter(u, halo=(1, 1), K=cfg["K"])
+            ctx.enter(v, halo=(1, 1), K=cfg["K"])
+            ins.append(u)
+            outs.append(v)
+        ctx.batch_begin()
+        for u, v, cfg in zip(ins, outs, configs):
+            _sweep(ctx, u, v, cfg)
+        g = ctx.batch_end()
+        info = ctx.batch_info(g)
+        ms = ctx.batch_time(g, warmup=2, reps=reps)
+        res = None
+        if keep_outputs:
+            res = []
+            for v in outs:
+                ctx.update(v, jacc.UPDATE_HOST)
+                res.append(v.copy())
+        return float(np.median(ms)), info, res
+    finally:
+        ctx.close()
+
+
+def run(n2d=128, n3d=128, train2d=24, train3d=24, epochs=300, tune_reps=5, graph_reps=10, log=print,
+        test_shapes=None, train_shapes=None):
+    t_start = time.perf_counter()
+    test_shapes = test_shapes or inputs.batch_shapes(5, n2d, n3d)
+    train_shapes = train_shapes or inputs.batch_shapes(7, train2d, train3d)
+    ctx = jacc.Context(2)
+    db = tuner.TimingDB()
+    # 1. exhaustive timings of the training shapes -> dataset
+    X, y, group = [], [], []
+    t0 = time.perf_counter()
+    for li, sh in enumerate(train_shapes):
+        cands, meds, _ = tuner.tune(ctx, sh, _data(sh, 1000 + li), db=db, reps=tune_reps)
+        for c, m in zip(cands, meds):
+            X.append(tuner.features(sh, c))
+            y.append(math.log(m))
+            group.append(li)
+    X, y, group = np.array(X), np.array(y), np.array(group)
+    t_train_tune = time.perf_counter() - t0
+    log(f"training set: {len(y)} timings from {len(train_shapes)} shapes ({t_train_tune:.1f} s)")
+    # 2. train the GPU network (80/20 split by loop for a held-out loss)
+    val = group % 5 == 4
+    model = tuner.CostModel(ctx, init_params=inputs.mlp_init(tuner.NFEAT, seed=8))
+    t0 = time.perf_counter()
+    losses = model.fit(X[~val], y[~val], epochs=epochs, batch=256, lr=1e-3, seed=9)
+    t_fit = time.perf_counter() - t0
+    val_mse = float(np.mean((model.predict(X[val]) - y[val]) ** 2)) if val.any() else None
+    log(f"model: loss {losses[0]:.4f} -> {losses[-1]:.4f} in {epochs} epochs ({t_fit:.1f} s), held-out mse {val_mse}")
+    # 3. the test batch: exhaustive choice, model choice, default
+    exh, mlp, dflt, datas = [], [], [], []
+    regret_loop = []
+    t0 = time.perf_counter()
+    for li, sh in enumerate(test_shapes):
+        d = _data(sh, 6000 + li)
+        datas.append(d)
+        cands, meds, _ = tuner.tune(ctx, sh, d, db=db, reps=tune_reps)
+        best = tuner.select(meds)
+        exh.append(cands[best])
+        pick, _ = model.pick(sh, cands)
+        mlp.append(pick)
+        dflt.append(dict(tuner.DEFAULT_CONFIG))
+        regret_loop.append(meds[cands.index(pick)] / meds[best] - 1.0)
+    t_test_tune = time.perf_counter() - t0
+    db.save()
+    model.close()
+    ctx.close()
+    log(f"test batch: {len(test_shapes)} loops tuned exhaustively ({t_test_tune:.1f} s)")
+    t_exh, info_e, out_e = graph_time(test_shapes, datas, exh, graph_reps, keep_outputs=True)
+    t_mlp, info_m, out_m = graph_time(test_shapes, datas, mlp, graph_reps, keep_outputs=True)
+    t_def, info_d, out_d = graph_time(test_shapes, datas, dflt, graph_reps, keep_outputs=True)
+    identical = all(np.array_equal(a, b) and np.array_equal(a, c) for a, b, c in zip(out_e, out_m, out_d))
+    cells = sum(float(np.prod([d - 2 for d in sh])) for sh in test_shapes)
+    alg_bytes = 16.0 * cells
+    result = {
+        "loops": len(test_shapes),
+        "algorithmic_gb": round(alg_bytes / 1e9, 3),
+        "graph_ms": {"exhaustive": round(t_exh, 4), "learned": round(t_mlp, 4), "default": round(t_def, 4)},
+        "graph_gbps": {"exhaustive": round(alg_bytes / t_exh / 1e6, 1), "learned": round(alg_bytes / t_mlp / 1e6, 1),
+                       "default": round(alg_bytes / t_def / 1e6, 1)},
+        "regret_learned_vs_exhaustive": round(t_mlp / t_exh - 1.0, 4),
+        "gain_learned_vs_default": round(t_def / t_mlp, 3),
+        "mean_per_loop_regret": round(float(np.mean(regret_loop)), 4),
+        "persistent_groups": {"exhaustive": info_e["persistent_groups"], "learned": info_m["persistent_groups"]},
+        "outputs_bit_identical_across_configs": bool(identical),
+        "train_timings": int(len(y)),
+        "train_shapes": len(train_shapes),
+        "model_loss_first_last": [round(float(losses[0]), 5), round(float(losses[-1]), 5)],
+        "heldout_mse": None if val_mse is None else round(val_mse, 5),
+        "seconds": round(time.perf_counter() - t_start, 1),
+    }
+    return result, (test_shapes, datas, out_m)

@@ -1,7 +1,7 @@
-"""GPU parity of batched execution: captured hipGraphs of partitioned loop
-sequences, replayed several times with eager work and host reads between
-replays, and persistent-kernel task groups of many small uneven sweeps —
-every output bit-identical to the CPU oracle."""
+"""GPU parity of batched execution: captured single-stream hipGraphs of
+partitioned loop sequences, replayed several times with eager work and host
+reads between replays, and persistent-kernel task groups of many small
+uneven sweeps — every output bit-identical to the CPU oracle."""
 import numpy as np
 import pytest
 
@@ -9,10 +9,7 @@ import oracle
 from paper_2110_14340_amd import inputs, jacc
 from gpu_util import context, say
 
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skip(reason="multi-stream graph capture ended in a host segfault inside "
-                                      "jacc_batch_end on the device; batches are being rebuilt on a "
-                                      "single-stream capture")]
+pytestmark = pytest.mark.gpu
 
 
 def test_graph_of_two_jacobi_steps_replayed_with_eager_work_between():
@@ -154,3 +151,22 @@ def test_batch_mixing_persistent_and_partitioned_loops():
         ref = s.copy()
         oracle.jacobi2d_sweep(s, ref)
         assert np.array_equal(o, ref)
+
+
+def test_graph_of_partitioned_steps_as_persistent_tasks_k8():
+    say("graph: 8 partitions per step as persistent tasks, mirrors, 20 replays")
+    u0 = inputs.jacobi_grid(515, 1030, seed=51)
+    a, b = u0.copy(), u0.copy()
+    cfg = jacc.config(tile=8, vec=2, persistent=1)
+    with context(8) as c:
+        c.enter(a, halo=(1, 1))
+        c.enter(b, halo=(1, 1))
+        c.batch_begin()
+        c.jacobi2d(a, b, cfg=cfg)
+        c.jacobi2d(b, a, cfg=cfg)
+        g = c.batch_end()
+        assert c.batch_info(g) == {"loops": 2, "persistent_groups": 2, "replay_safe": True}
+        c.batch_launch(g, 19)
+        c.exit(b)
+        c.exit(a)
+    assert np.array_equal(a, oracle.jacobi2d(u0, 40))

@@ -19,6 +19,7 @@ from trace_check import freshness_check, race_check
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 DRY = jacc.INIT_DRYRUN | jacc.INIT_TRACE
+LAZY = DRY | jacc.INIT_LAZY
 
 
 def header_symbols():
@@ -45,8 +46,8 @@ def test_library_is_built_for_gfx950():
 
 
 # ------------------------------------------------------------------ plan
-def dry(K):
-    return jacc.Context(K, flags=DRY)
+def dry(K, lazy=False):
+    return jacc.Context(K, flags=LAZY if lazy else DRY)
 
 
 def _loop_trace(c, fn):
@@ -55,9 +56,10 @@ def _loop_trace(c, fn):
     return c.trace()
 
 
-def test_jacobi_k8_plan_matches_model_and_counts():
+@pytest.mark.parametrize("lazy", [True, False])
+def test_jacobi_k8_plan_matches_model_and_counts(lazy):
     E = 64
-    c = dry(8)
+    c = dry(8, lazy)
     a = np.zeros((E, 16))
     b = np.zeros((E, 16))
     c.enter(a, halo=(1, 1))
@@ -69,14 +71,20 @@ def test_jacobi_k8_plan_matches_model_and_counts():
     for step in range(4):
         tr = _loop_trace(c, lambda: c.jacobi2d(src, dst))
         full += tr
-        ps = P.plan_loop(model, 1, E - 1, [(names[id(src)], "r", -1, 1, False), (names[id(dst)], "w", 0, 0, False)])
+        ps = P.plan_loop(model, 1, E - 1, [(names[id(src)], "r", -1, 1, False), (names[id(dst)], "w", 0, 0, False)],
+                         refresh="pull" if lazy else "holders")
         kernels = [t for t in tr if t["op"] == "KERNEL"]
         assert [(t["dst"], t["lo"], t["hi"]) for t in kernels] == \
             [(p, min(pp["I"]), max(pp["I"]) + 1) for p, pp in enumerate(ps)]
         copies = sorted((t["dst"], t["src"], t["lo"], t["hi"]) for t in tr if t["op"] == "COPY")
         want = sorted((p, s, lo, hi) for p, pp in enumerate(ps) for (_, s, lo, hi) in pp["copies"])
         assert copies == want
-        assert len(copies) == (0 if step == 0 else 14)
+        assert len(copies) == (0 if (step == 0 or not lazy) else 14)
+        if not lazy:  # each boundary row is also written into the neighbour's slab
+            dst_id = 1 if src is a else 0
+            mirror_writes = [t for t in tr if t["op"] == "ACCESS" and t["kind"] == 2 and t["array"] == dst_id
+                             and not (P.block(E, 8, t["dst"])[0] <= t["lo"] < P.block(E, 8, t["dst"])[1])]
+            assert len(mirror_writes) == 14
         waits = [t for t in tr if t["op"] == "WAIT"]
         assert len(waits) <= 2 * 8
         src, dst = dst, src
@@ -89,7 +97,8 @@ def test_jacobi_k8_plan_matches_model_and_counts():
        steps=st.integers(1, 4), data=st.data())
 def test_random_loop_sequences_match_model(E, K, hl, hh, steps, data):
     K = min(K, E)
-    c = dry(K)
+    lazy = data.draw(st.booleans())
+    c = dry(K, lazy)
     a = np.zeros((E, 3))
     b = np.zeros((E, 3))
     c.enter(a, halo=(hl, hh))
@@ -129,7 +138,8 @@ def test_random_loop_sequences_match_model(E, K, hl, hh, steps, data):
             rc = c.loop(jacc.JACOBI2D, jacc.bounds((lb, ub), (1, 2)),
                         [(arrays[rd], jacc.READ, -1, 1, 0), (arrays[wr], jacc.WRITE, 0, 0, 0)], raw=True)
             try:
-                ps = P.plan_loop(model, lb, ub, [(rd, "r", -1, 1, False), (wr, "w", 0, 0, False)])
+                ps = P.plan_loop(model, lb, ub, [(rd, "r", -1, 1, False), (wr, "w", 0, 0, False)],
+                                 refresh="pull" if (lazy or K == 1) else "holders")
             except ValueError:
                 assert rc == jacc.ERR_RANGE
                 continue
@@ -301,7 +311,7 @@ def test_injected_device_fault_is_sticky():
 import numpy as np, sys
 sys.path.insert(0, sys.argv[1])
 from paper_2110_14340_amd import jacc
-c = jacc.Context(4, flags=jacc.INIT_DRYRUN | jacc.INIT_TRACE)
+c = jacc.Context(4, flags=jacc.INIT_DRYRUN | jacc.INIT_TRACE | jacc.INIT_LAZY)
 a = np.zeros((32, 8)); b = np.zeros((32, 8))
 c.enter(a, halo=(1, 1)); c.enter(b, halo=(1, 1))
 c.jacobi2d(a, b)
@@ -356,7 +366,7 @@ def test_batch_two_step_jacobi_is_replay_safe_and_race_free():
 
 
 def test_batch_not_replay_safe_is_refused():
-    c = dry(4)
+    c = dry(4, lazy=True)
     a = np.zeros((40, 8))
     b = np.zeros((40, 8))
     c.enter(a, halo=(1, 1))

@@ -107,12 +107,15 @@ def freshness_check(trace):
                         if have != want:
                             stale.append(f"kernel s{t['stream']}#{t['seq']} reads array {a['array']} row {row} "
                                          f"in slab {a['dst']}: version {have}, latest {want}")
+            written = {}   # one new value per (array, row), whichever slabs receive it
             for a in acc:
                 if a["kind"] == 2:
                     for row in range(a["lo"], a["hi"]):
-                        v = new_version()
-                        logical[(a["array"], row)] = v
-                        stored[(a["array"], a["dst"], row)] = v
+                        key = (a["array"], row)
+                        if key not in written:
+                            written[key] = new_version()
+                        logical[key] = written[key]
+                        stored[(a["array"], a["dst"], row)] = written[key]
         elif op == "D2H":
             for row in range(t["lo"], t["hi"]):
                 want = logical.get((t["array"], row))
