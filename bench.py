@@ -69,6 +69,32 @@ def run_jacobi(ctx_mod, torch, u0, K, steps, warmup, cfg=None):
     return t1 - t0, ev_s
 
 
+def run_jacobi_graph(jacc, torch, u0, K, steps, warmup, tile=16):
+    """The same partitioned sweeps captured once as a two-step graph (the K
+    partitions of a step are tasks of one persistent launch, halo rows
+    written through by the producing tiles) and replayed steps/2 times."""
+    a = u0.copy()
+    b = u0.copy()
+    c = jacc.Context(K)
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    cfg = jacc.config(tile=tile, vec=2, persistent=1)
+    c.batch_begin()
+    c.jacobi2d(a, b, cfg=cfg)
+    c.jacobi2d(b, a, cfg=cfg)
+    g = c.batch_end()
+    c.batch_launch(g, max(0, warmup // 2))
+    c.wait()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.batch_launch(g, steps // 2)
+    c.wait()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c.close()
+    return t1 - t0
+
+
 def cpu_baseline(u0, budget_s=12.0):
     import oracle
     ny, nx = u0.shape
@@ -183,6 +209,7 @@ def main():
     ap.add_argument("--k-list", default="1,2,4,8")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the partitions of this "
@@ -207,6 +234,14 @@ def main():
                     "gbps": round(step_bytes * args.steps / wall / 1e9, 1)}
         if K == 1:
             ev_k1 = ev
+    graph = {}
+    for K in ks:
+        if K == 1:
+            continue
+        log(f"jacobi K={K} as a replayed graph")
+        wall = run_jacobi_graph(jacc, torch, u0, K, args.steps, args.warmup)
+        graph[K] = {"ms_per_step": round(wall / args.steps * 1e3, 5),
+                    "gbps": round(step_bytes * args.steps / wall / 1e9, 1)}
     main_k = max(ks)
     wall_main = per_k[main_k]["ms_per_step"] / 1e3 * args.steps
     value = step_bytes * args.steps / wall_main / 1e9
@@ -228,6 +263,7 @@ def main():
                    "grid": [n, n], "K": main_k, "iterations": args.steps, "seed": 1},
         "frac_hbm_peak": round(value / HBM_PEAK_GBS, 4),
         "per_k": {str(k): v for k, v in per_k.items()},
+        "per_k_graph": {str(k): v for k, v in graph.items()},
     }
     if 1 in per_k and main_k != 1:
         result["k_overhead"] = round(per_k[main_k]["ms_per_step"] / per_k[1]["ms_per_step"] - 1.0, 4)
@@ -242,6 +278,10 @@ def main():
     if not args.no_extra:
         log("secondary workloads")
         result["extra"] = extra_workloads(jacc, torch, inputs)
+    if not args.no_learned:
+        log("batched / learned experiment")
+        from paper_2110_14340_amd import experiment
+        result["learned"], _ = experiment.run(log=log)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(u0)
