@@ -133,9 +133,13 @@ typedef struct {
  *   vec        1 or 2 consecutive FP64 elements per lane (2 needs an even row
  *              length)
  *   persistent 1 = run the loop inside the batched persistent kernel
+ *   order      workgroup-to-tile order: 1 = row-major, 2 = XCD-aware (the
+ *              chip hands consecutive workgroup ids to its 8 XCDs in turn; with
+ *              this order each XCD walks one contiguous band of tiles, so the
+ *              rows two neighbouring tiles share meet in that XCD's L2)
  * Fields equal to 0 take the default. */
 typedef struct {
-    int32_t bx, by, tile, vec, persistent;
+    int32_t bx, by, tile, vec, persistent, order;
 } jacc_config;
 
 /* Loop kinds (hand-written HIP loop bodies) and their arguments, in order:

@@ -149,11 +149,21 @@ __device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, doubl
     }
 }
 
+// Tile of a 1-D grid's workgroup: row-major (order 1), or XCD-aware (order
+// 2): workgroup b runs on XCD b mod 8, and XCD x takes the x-th contiguous
+// eighth of the tiles in row-major order.
+__device__ __forceinline__ int64_t tile_of(int order) {
+    const int64_t b = blockIdx.x, n = gridDim.x;
+    if (order == 2 && (n & 7) == 0) return (b & 7) * (n >> 3) + (b >> 3);
+    return b;
+}
+
 template <int VEC>
 __global__ void __launch_bounds__(1024)
 jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t nx, int64_t r_lo, int64_t r_hi,
-                int64_t c_lo, int64_t c_hi, int64_t col0, int tile, Mirrors mir) {
-    jacobi_tile<VEC>(in, out, nx, r_lo, r_hi, c_lo, c_hi, col0, tile, mir, blockIdx.x, blockIdx.y, threadIdx.x,
+                int64_t c_lo, int64_t c_hi, int64_t col0, int tile, Mirrors mir, int64_t gx, int order) {
+    const int64_t t = tile_of(order);
+    jacobi_tile<VEC>(in, out, nx, r_lo, r_hi, c_lo, c_hi, col0, tile, mir, t % gx, t / gx, threadIdx.x,
                      threadIdx.y, blockDim.x, blockDim.y);
 }
 
@@ -245,17 +255,16 @@ template <int VEC, bool RES>
 __global__ void __launch_bounds__(1024)
 heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t ny, int64_t nx, int64_t z_lo,
               int64_t z_hi, int64_t y_lo, int64_t y_hi, int64_t x_lo, int64_t x_hi, int64_t col0, int tile,
-              double alpha, double *__restrict__ wg_partials, Mirrors mir) {
+              double alpha, double *__restrict__ wg_partials, Mirrors mir, int64_t gx, int64_t gy, int order) {
     __shared__ double sh[16];
+    const int64_t t = tile_of(order);
+    const int64_t rest = t / gx;
     const double acc = heat_tile<VEC, RES>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, alpha,
-                                           mir, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, threadIdx.y,
-                                           blockDim.x, blockDim.y);
+                                           mir, t % gx, rest % gy, rest / gy, threadIdx.x, threadIdx.y, blockDim.x,
+                                           blockDim.y);
     if (RES) {
         const double s = block_sum(acc, sh);
-        if (threadIdx.x == 0 && threadIdx.y == 0) {
-            const int64_t b = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-            wg_partials[b] = s;
-        }
+        if (threadIdx.x == 0 && threadIdx.y == 0) wg_partials[t] = s;  // partials in tile order
     }
 }
 
@@ -316,15 +325,16 @@ hipError_t launch_jacobi2d(const Launch &L, hipStream_t s) {
     const int64_t nrows = L.hi[0] - L.lo[0];
     if (nrows <= 0 || L.hi[1] <= L.lo[1]) return hipSuccess;
     dim3 block(c.bx, c.by);
-    dim3 grid((unsigned)cdiv(ncols, (int64_t)c.bx * c.vec), (unsigned)cdiv(nrows, (int64_t)c.by * c.tile));
+    const int64_t gx = cdiv(ncols, (int64_t)c.bx * c.vec), gy = cdiv(nrows, (int64_t)c.by * c.tile);
+    dim3 grid((unsigned)(gx * gy));
     const double *in = (const double *)L.a[0].ptr;
     double *out = (double *)L.a[1].ptr;
     if (c.vec == 2)
         hipLaunchKernelGGL(jacobi2d_kernel<2>, grid, block, 0, s, in, out, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1],
-                           col0, c.tile, L.mir);
+                           col0, c.tile, L.mir, gx, c.order);
     else
         hipLaunchKernelGGL(jacobi2d_kernel<1>, grid, block, 0, s, in, out, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1],
-                           col0, c.tile, L.mir);
+                           col0, c.tile, L.mir, gx, c.order);
     return hipGetLastError();
 }
 
@@ -351,13 +361,16 @@ hipError_t launch_heat3d(const Launch &L, hipStream_t s) {
     const int64_t col0 = col_start(L.lo[2], c.vec);
     if (heat_empty(L)) return hipSuccess;
     dim3 block(c.bx, c.by);
-    dim3 grid = heat_grid(L, col0);
+    const dim3 g3 = heat_grid(L, col0);
+    const int64_t gx = g3.x, gy = g3.y;
+    dim3 grid((unsigned)((int64_t)g3.x * g3.y * g3.z));
     const double *in = (const double *)L.a[0].ptr;
     double *out = (double *)L.a[1].ptr;
     const double alpha = L.scalars[0];
     const bool res = L.wg_partials != nullptr;
-#define HEAT_ARGS \
-    in, out, ny, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1], L.lo[2], L.hi[2], col0, c.tile, alpha, L.wg_partials, L.mir
+#define HEAT_ARGS                                                                                                    \
+    in, out, ny, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1], L.lo[2], L.hi[2], col0, c.tile, alpha, L.wg_partials, L.mir, \
+        gx, gy, c.order
     if (c.vec == 2) {
         if (res)
             hipLaunchKernelGGL((heat3d_kernel<2, true>), grid, block, 0, s, HEAT_ARGS);

@@ -17,7 +17,7 @@ struct Arg {
 };
 
 struct Cfg {
-    int bx, by, tile, vec, persistent;
+    int bx, by, tile, vec, persistent, order;
 };
 
 // Write-through targets of a stencil launch: rows [lo, hi) of dim 0 that the
