@@ -25,42 +25,59 @@ constexpr int SB = BN + 16;  // LDS row stride of B (doubles)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// Tile of workgroup b: the 8 XCDs take consecutive workgroup ids in turn, so
+// XCD x is given the x-th contiguous eighth of the tiles; inside it, tiles
+// are walked in groups of 8 tile-rows (column by column), so the
+// workgroups resident on one XCD share few A row-panels and B column-panels
+// and most panel reads hit that XCD's L2.
+__device__ __forceinline__ void gemm_tile(int64_t tiles_m, int64_t tiles_n, int64_t *ti, int64_t *tj) {
+    const int64_t b = blockIdx.x, n = gridDim.x;
+    const int64_t t = (n & 7) == 0 ? (b & 7) * (n >> 3) + (b >> 3) : b;
+    constexpr int64_t G = 8;
+    const int64_t group = t / (G * tiles_n);
+    const int64_t first = group * G;
+    const int64_t rows = tiles_m - first < G ? tiles_m - first : G;
+    const int64_t in_group = t - group * G * tiles_n;
+    *ti = first + in_group % rows;
+    *tj = in_group / rows;
+}
+
 __global__ void __launch_bounds__(kGemmThreads)
 gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *__restrict__ C, int64_t m_lo,
             int64_t m_hi, int64_t N, int64_t L, int64_t lda, int64_t ldb, int64_t ldc, int64_t n_lo, int64_t n_hi,
-            int tiles_n) {
-    __shared__ double As[2][BM * SA];
-    __shared__ double Bs[2][BK * SB];
+            int64_t tiles_m, int64_t tiles_n) {
+    __shared__ __align__(16) double As[2][BM * SA];
+    __shared__ __align__(16) double Bs[2][BK * SB];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int64_t tile = blockIdx.x;
-    const int64_t row0 = m_lo + (tile / tiles_n) * BM;
-    const int64_t col0 = n_lo + (tile % tiles_n) * BN;
+    int64_t ti, tj;
+    gemm_tile(tiles_m, tiles_n, &ti, &tj);
+    const int64_t row0 = m_lo + ti * BM;
+    const int64_t col0 = n_lo + tj * BN;
+    const bool full_mn = row0 + BM <= m_hi && col0 + BN <= n_hi && (lda & 1) == 0 && (ldb & 1) == 0;
 
     // global -> register staging: A tile 128x16 and B tile 16x128 are 1024
-    // double2 each, 4 per thread
-    double2 ra[4], rb[4];
+    // double pairs each, 4 per thread (16-byte loads for full tiles)
+    dvec2 ra[4], rb[4];
     auto load_tiles = [&](int64_t k0) {
+        const bool full = full_mn && k0 + BK <= L;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int idx = tid + u * kGemmThreads;
-            {   // A: row = idx / 8, k pair = idx % 8
-                const int r = idx >> 3, kp = (idx & 7) * 2;
+            const int r = idx >> 3, kp = (idx & 7) * 2;     // A: row, k pair
+            const int kr = idx >> 6, cp = (idx & 63) * 2;   // B: k, column pair
+            if (full) {
+                ra[u] = *reinterpret_cast<const dvec2 *>(A + (row0 + r) * lda + k0 + kp);
+                rb[u] = *reinterpret_cast<const dvec2 *>(B + (k0 + kr) * ldb + col0 + cp);
+            } else {
                 const int64_t gi = row0 + r, gk = k0 + kp;
-                double2 v;
-                v.x = (gi < m_hi && gk < L) ? A[gi * lda + gk] : 0.0;
-                v.y = (gi < m_hi && gk + 1 < L) ? A[gi * lda + gk + 1] : 0.0;
-                ra[u] = v;
-            }
-            {   // B: k = idx / 64, column pair = idx % 64
-                const int kr = idx >> 6, cp = (idx & 63) * 2;
-                const int64_t gk = k0 + kr, gj = col0 + cp;
-                double2 v;
-                v.x = (gk < L && gj < n_hi) ? B[gk * ldb + gj] : 0.0;
-                v.y = (gk < L && gj + 1 < n_hi) ? B[gk * ldb + gj + 1] : 0.0;
-                rb[u] = v;
+                ra[u].x = (gi < m_hi && gk < L) ? A[gi * lda + gk] : 0.0;
+                ra[u].y = (gi < m_hi && gk + 1 < L) ? A[gi * lda + gk + 1] : 0.0;
+                const int64_t gkb = k0 + kr, gj = col0 + cp;
+                rb[u].x = (gkb < L && gj < n_hi) ? B[gkb * ldb + gj] : 0.0;
+                rb[u].y = (gkb < L && gj + 1 < n_hi) ? B[gkb * ldb + gj + 1] : 0.0;
             }
         }
     };
@@ -69,11 +86,9 @@ gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *
         for (int u = 0; u < 4; ++u) {
             const int idx = tid + u * kGemmThreads;
             const int r = idx >> 3, kp = (idx & 7) * 2;
-            As[buf][r * SA + kp] = ra[u].x;
-            As[buf][r * SA + kp + 1] = ra[u].y;
+            *reinterpret_cast<dvec2 *>(&As[buf][r * SA + kp]) = ra[u];
             const int kr = idx >> 6, cp = (idx & 63) * 2;
-            Bs[buf][kr * SB + cp] = rb[u].x;
-            Bs[buf][kr * SB + cp + 1] = rb[u].y;
+            *reinterpret_cast<dvec2 *>(&Bs[buf][kr * SB + cp]) = rb[u];
         }
     };
 
@@ -134,10 +149,10 @@ hipError_t launch_gemm(const Launch &L, hipStream_t s) {
     if (m <= 0 || n <= 0) return hipSuccess;
     const int64_t Lk = L.a[0].row_elems;
     const int64_t N = L.a[2].row_elems;
-    const int tiles_m = (int)((m + BM - 1) / BM), tiles_n = (int)((n + BN - 1) / BN);
-    hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)tiles_m * tiles_n), dim3(kGemmThreads), 0, s,
+    const int64_t tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
+    hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)(tiles_m * tiles_n)), dim3(kGemmThreads), 0, s,
                        (const double *)L.a[0].ptr, (const double *)L.a[1].ptr, (double *)L.a[2].ptr, L.lo[0], L.hi[0],
-                       N, Lk, Lk, L.a[1].row_elems, N, L.lo[1], L.hi[1], tiles_n);
+                       N, Lk, Lk, L.a[1].row_elems, N, L.lo[1], L.hi[1], tiles_m, tiles_n);
     return hipGetLastError();
 }
 
