@@ -107,7 +107,13 @@ enum { JACC_COPYOUT = 1, JACC_DELETE = 2 };
 /* update directions */
 enum { JACC_UPDATE_HOST = 1, JACC_UPDATE_DEVICE = 2 };
 /* argument access modes */
-enum { JACC_READ = 1, JACC_WRITE = 2, JACC_READWRITE = 3 };
+enum { JACC_READ = 1, JACC_WRITE = 2, JACC_READWRITE = 3,
+       /* with JACC_WRITE: the argument is written through data-dependent
+        * indices; every partition runs the whole iteration space and keeps
+        * only the writes that land in its owner block (the paper's
+        * predicate-based filtering: a write a[k] is guarded by
+        * a_lb <= k <= a_ub, Sec. "Predicate-Based Filtering") */
+       JACC_FILTERED = 4 };
 
 /* Loop argument: the base address of a declared array, its access mode and
  * the rows of dim 0 that outer iteration i touches, [i+off_lo, i+off_hi]
@@ -154,13 +160,18 @@ typedef struct {
  *             2-D bounds [0,M) x [0,N).  C = A*B (FP64 matrix cores)
  *   SPMV_CSR  row_ptr (int32, n+1) R [0,+1]; col (int32) R WHOLE; val (f64)
  *             R WHOLE; x R WHOLE; y W [0,0].  1-D bounds [0,n).
- *             y[i] = sum_{k=row_ptr[i]}^{row_ptr[i+1]-1} val[k]*x[col[k]] */
+ *             y[i] = sum_{k=row_ptr[i]}^{row_ptr[i+1]-1} val[k]*x[col[k]]
+ *   SCATTER_SQ in (f64) R WHOLE; idx (int32) R WHOLE; out (f64) W|FILTERED.
+ *             1-D bounds over i.  out[idx[i]] = in[i]*in[i] (the map of the
+ *             paper's OpenACC example with an indirect write); indices must be
+ *             distinct; an index outside [0, rows of out) is skipped. */
 enum {
     JACC_LOOP_JACOBI2D = 1,
     JACC_LOOP_HEAT3D = 2,
     JACC_LOOP_SUM = 3,
     JACC_LOOP_GEMM = 4,
-    JACC_LOOP_SPMV_CSR = 5
+    JACC_LOOP_SPMV_CSR = 5,
+    JACC_LOOP_SCATTER_SQ = 6
 };
 
 /* jacc_init flags */

@@ -78,6 +78,10 @@ def lib():
         L.oracle_gemm_rows.restype = None
         L.oracle_spmv_csr.argtypes = [_i32p, _i32p, _f64p, _f64p, _f64p, _i64, _i64]
         L.oracle_spmv_csr.restype = None
+        L.oracle_scatter_sq.argtypes = [_f64p, _i32p, _f64p, _i64, _i64, _i64]
+        L.oracle_scatter_sq.restype = None
+        L.oracle_scatter_sq_partitioned.argtypes = [_f64p, _i32p, _f64p, _i64, _i64, _i64, ctypes.c_int]
+        L.oracle_scatter_sq_partitioned.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -209,3 +213,25 @@ def spmv_csr(rp, col, val, x, rows=None):
     y = np.zeros(n, dtype=np.float64)
     lib().oracle_spmv_csr(rp, col, val, x, y, lo, hi)
     return y
+
+
+# --------------------------------------------------------------------------
+# Indirect write (predicate-filtered on partitions)
+# --------------------------------------------------------------------------
+def scatter_sq(inp, idx, out, rows=None):
+    """out[idx[i]] = in[i]^2 for i in rows (default all); returns a new array."""
+    inp = _c(inp)
+    idx = _c(idx, np.int32)
+    o = _c(out).copy()
+    lo, hi = rows if rows is not None else (0, inp.size)
+    lib().oracle_scatter_sq(inp, idx, o, o.size, lo, hi)
+    return o
+
+
+def scatter_sq_partitioned(inp, idx, out, K, rows=None):
+    inp = _c(inp)
+    idx = _c(idx, np.int32)
+    o = _c(out).copy()
+    lo, hi = rows if rows is not None else (0, inp.size)
+    assert lib().oracle_scatter_sq_partitioned(inp, idx, o, o.size, lo, hi, K) == 0
+    return o

@@ -441,3 +441,38 @@ void oracle_spmv_csr(const int32_t *rp, const int32_t *col, const double *val, c
         y[i] = s;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Indirect write: out[idx[i]] = in[i]*in[i] for i in [lo, hi) (distinct     */
+/* indices; an index outside [0, n_out) is skipped).                         */
+/* ------------------------------------------------------------------------ */
+void oracle_scatter_sq(const double *in, const int32_t *idx, double *out, int64_t n_out, int64_t lo, int64_t hi)
+{
+    for (int64_t i = lo; i < hi; ++i) {
+        int64_t k = idx[i];
+        if (k >= 0 && k < n_out) out[k] = in[i] * in[i];
+    }
+}
+
+/* K-way partitioned version with the paper's write filter: every partition
+ * runs all iterations and keeps the writes whose target lies in its owner
+ * block, into a private copy of that block; the blocks are then gathered. */
+int oracle_scatter_sq_partitioned(const double *in, const int32_t *idx, double *out, int64_t n_out, int64_t lo,
+                                  int64_t hi, int K)
+{
+    if (K < 1 || K > n_out) return -1;
+    for (int p = 0; p < K; ++p) {
+        int64_t b0 = block_lo(n_out, K, p), b1 = block_lo(n_out, K, p + 1);
+        double *mine = malloc((size_t)(b1 - b0 + 1) * sizeof(double));
+        if (!mine) return -1;
+        memcpy(mine, out + b0, (size_t)(b1 - b0) * sizeof(double));
+        for (int64_t i = lo; i < hi; ++i) {
+            int64_t k = idx[i];
+            double v = in[i] * in[i];
+            if (b0 <= k && k < b1) mine[k - b0] = v;
+        }
+        memcpy(out + b0, mine, (size_t)(b1 - b0) * sizeof(double));
+        free(mine);
+    }
+    return 0;
+}

@@ -56,6 +56,7 @@ int check_config(const Launch &L) {
         case JACC_LOOP_SUM:
         case JACC_LOOP_GEMM:
         case JACC_LOOP_SPMV_CSR:
+        case JACC_LOOP_SCATTER_SQ:
             return 0;  // fixed internal configurations; fields are ignored
         default:
             return 1;
@@ -81,6 +82,7 @@ hipError_t launch_loop(const Launch &L, hipStream_t s) {
         case JACC_LOOP_SUM: return launch_sum(L, s);
         case JACC_LOOP_GEMM: return launch_gemm(L, s);
         case JACC_LOOP_SPMV_CSR: return launch_spmv(L, s);
+        case JACC_LOOP_SCATTER_SQ: return launch_scatter(L, s);
         default: return hipErrorInvalidValue;
     }
 }

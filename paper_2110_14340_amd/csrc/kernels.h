@@ -43,6 +43,7 @@ struct Launch {
     double scalars[4];
     Cfg cfg;
     Mirrors mir;  // stencil kinds only
+    int64_t own_lo, own_hi;  // owner rows of a FILTERED output (writes elsewhere are dropped)
     // reductions: workgroup partials go to `wg_partials` (capacity
     // `wg_capacity` doubles); the finaliser writes their ordered sum to
     // `part_out`.  Both null when the loop reduces nothing.
@@ -109,6 +110,7 @@ int64_t sum_workgroups(const Launch &L);
 hipError_t launch_finalise(const double *partials, int64_t n, double *out, hipStream_t s);
 hipError_t launch_gemm(const Launch &L, hipStream_t s);
 hipError_t launch_spmv(const Launch &L, hipStream_t s);
+hipError_t launch_scatter(const Launch &L, hipStream_t s);
 
 // ---- learned cost model (k_mlp.hip) ----------------------------------------
 constexpr int kMlpHidden = 64;

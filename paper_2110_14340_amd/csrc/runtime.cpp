@@ -704,6 +704,7 @@ bool kind_info(int kind, KindInfo *k) {
         case JACC_LOOP_SUM: *k = {1, 1, 2}; return true;
         case JACC_LOOP_GEMM: *k = {3, 2, 0}; return true;
         case JACC_LOOP_SPMV_CSR: *k = {5, 1, 0}; return true;
+        case JACC_LOOP_SCATTER_SQ: *k = {3, 1, 0}; return true;
         default: return false;
     }
 }
@@ -741,7 +742,8 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
 
     int K = -1;
     for (int i = 0; i < nargs; ++i) {
-        if (args[i].mode < JACC_READ || args[i].mode > JACC_READWRITE)
+        if (args[i].mode < JACC_READ || args[i].mode > (JACC_READWRITE | JACC_FILTERED) ||
+            ((args[i].mode & JACC_FILTERED) && !(args[i].mode & JACC_WRITE)))
             return set_err(c, JACC_ERR_INVALID, "argument %d: bad mode", i);
         if (args[i].off_lo > args[i].off_hi) return set_err(c, JACC_ERR_INVALID, "argument %d: off_lo > off_hi", i);
         Array *A = lookup(c, args[i].host);
@@ -804,21 +806,39 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
             if (b->hi[0] > arr[4]->E) return set_err(c, JACC_ERR_RANGE, "SPMV_CSR bounds exceed y");
             primary = 4;
             break;
+        case JACC_LOOP_SCATTER_SQ:
+            if (!is(0, JACC_F64, 1) || !is(1, JACC_I32, 1) || !is(2, JACC_F64, 1))
+                return set_err(c, JACC_ERR_INVALID, "SCATTER_SQ takes f64 in, int32 idx, f64 out");
+            if (arr[0]->E != arr[1]->E) return set_err(c, JACC_ERR_INVALID, "SCATTER_SQ: in and idx differ in length");
+            if (!(args[2].mode & JACC_FILTERED))
+                return set_err(c, JACC_ERR_INVALID, "SCATTER_SQ writes out through indices: declare it FILTERED");
+            if (!args[0].whole || !args[1].whole)
+                return set_err(c, JACC_ERR_INVALID, "SCATTER_SQ reads in and idx whole");
+            if (b->hi[0] > arr[0]->E) return set_err(c, JACC_ERR_RANGE, "SCATTER_SQ bounds exceed in");
+            primary = 2;
+            break;
     }
     if (!(args[primary].mode & JACC_WRITE) && kind != JACC_LOOP_SUM)
         return set_err(c, JACC_ERR_INVALID, "the output argument must be declared writable");
 
     Array *P = arr[primary];
+    // A filtered output is written through data-dependent indices: every
+    // partition runs the whole iteration space (the write-index arithmetic is
+    // duplicated) and keeps the writes that land in its owner block.
+    const bool filtered = (args[primary].mode & JACC_FILTERED) != 0;
     plan.assign(K, PartPlan{});
     for (int p = 0; p < K; ++p) {
         Range own = P->whole ? (p == 0 ? Range{0, P->E} : Range{0, 0}) : P->block(p);
-        plan[p].iters = isect({b->lo[0], b->hi[0]}, own);
+        plan[p].iters = filtered ? Range{b->lo[0], b->hi[0]} : isect({b->lo[0], b->hi[0]}, own);
+        if (filtered && own.empty()) plan[p].iters = Range{};
         plan[p].rng.resize(nargs);
         for (int i = 0; i < nargs; ++i) {
             Range r{};
             if (!plan[p].iters.empty()) {
                 if (args[i].whole)
                     r = {0, arr[i]->E};
+                else if (args[i].mode & JACC_FILTERED)
+                    r = own;
                 else
                     r = isect({plan[p].iters.lo + args[i].off_lo, plan[p].iters.hi - 1 + args[i].off_hi + 1},
                               {0, arr[i]->E});
@@ -966,6 +986,10 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             LP.a[i].slab_lo = sl.rows.lo;
             LP.a[i].slab_hi = sl.rows.hi;
             LP.a[i].row_elems = arr[i]->row_elems;
+        }
+        if (args[primary].mode & JACC_FILTERED) {
+            LP.own_lo = pp.rng[primary].lo;
+            LP.own_hi = pp.rng[primary].hi;
         }
         LP.mir.n = (int)mirrors.size();
         for (size_t k = 0; k < mirrors.size(); ++k) {

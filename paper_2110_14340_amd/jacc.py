@@ -21,8 +21,8 @@ F64, F32, I32, I64 = 0, 1, 2, 3
 COPYIN, CREATE, COPY = 1, 2, 3
 COPYOUT, DELETE = 1, 2
 UPDATE_HOST, UPDATE_DEVICE = 1, 2
-READ, WRITE, READWRITE = 1, 2, 3
-JACOBI2D, HEAT3D, SUM, GEMM, SPMV_CSR = 1, 2, 3, 4, 5
+READ, WRITE, READWRITE, FILTERED = 1, 2, 3, 4
+JACOBI2D, HEAT3D, SUM, GEMM, SPMV_CSR, SCATTER_SQ = 1, 2, 3, 4, 5, 6
 INIT_DRYRUN, INIT_TRACE, INIT_SERIALIZE, INIT_LAZY = 1, 2, 4, 8
 OP_NAMES = {1: "ALLOC", 2: "FREE", 3: "H2D", 4: "D2H", 5: "COPY", 6: "KERNEL", 7: "RECORD", 8: "WAIT",
             9: "SYNC", 10: "COMBINE", 11: "ACCESS", 12: "JOIN"}
@@ -309,6 +309,12 @@ class Context:
         b = bounds((0, y.shape[0]))
         return self.loop(SPMV_CSR, b, [(rp, READ, 0, 1, 0), (col, READ, 0, 0, 1), (val, READ, 0, 0, 1),
                                        (x, READ, 0, 0, 1), (y, WRITE, 0, 0, 0)], raw=raw)
+
+    def scatter_sq(self, x, idx, out, rows=None, raw=False):
+        """out[idx[i]] = x[i]^2 with writes filtered to each partition's rows."""
+        b = bounds(rows or (0, x.shape[0]))
+        return self.loop(SCATTER_SQ, b, [(x, READ, 0, 0, 1), (idx, READ, 0, 0, 1),
+                                         (out, WRITE | FILTERED, 0, 0, 0)], raw=raw)
 
     # -- batches and timing ----------------------------------------------------
     def batch_begin(self):

@@ -137,3 +137,21 @@ def test_spmv_2_22_rows_k1_k4():
     for lo in (0, n // 4 - 3, n // 2, n - 100):
         ref = oracle.spmv_csr(rp, col, val, x, rows=(lo, lo + 100))
         assert np.all(np.abs(y4[lo:lo + 100] - ref[lo:lo + 100]) <= 1e-13 * bound[lo:lo + 100])
+
+
+# ------------------------------------------------------------------ predicate-filtered scatter
+@pytest.mark.parametrize("n,K", [(1000, 1), (1000, 3), (100_003, 4), (1 << 22, 8)])
+def test_filtered_scatter_matches_oracle(n, K):
+    say(f"scatter n={n} K={K}")
+    x = inputs.uniform(n, seed=n % 97, lo=-2, hi=2)
+    idx = np.random.default_rng(n % 89).permutation(n).astype(np.int32)
+    out = inputs.uniform(n, seed=5)
+    ref = oracle.scatter_sq(x, idx, out)
+    o = out.copy()
+    with context(K) as c:
+        c.enter(x, whole=True)
+        c.enter(idx, whole=True)
+        c.enter(o)
+        c.scatter_sq(x, idx, o)
+        c.exit(o)
+    assert np.array_equal(o, ref)

@@ -145,3 +145,33 @@ def test_csr_generator_structure():
         c = col[rp[i]:rp[i + 1]]
         assert np.all(np.diff(c) > 0) and 1 <= c.size <= 16
     assert x.size == 5000 and np.all((x >= -1) & (x < 1))
+
+
+# ------------------------------------------------------------------ scatter
+def test_scatter_permutation_against_numpy_fancy_indexing():
+    n = 1000
+    x = inputs.uniform(n, seed=11, lo=-2, hi=2)
+    perm = np.random.default_rng(12).permutation(n).astype(np.int32)
+    out = np.full(n, -7.0)
+    ref = out.copy()
+    ref[perm] = x * x
+    assert np.array_equal(oracle.scatter_sq(x, perm, out), ref)
+
+
+def test_scatter_partial_range_and_out_of_range_indices_skipped():
+    x = np.arange(10, dtype=np.float64)
+    idx = np.array([3, -1, 11, 0, 9, 4, 5, 6, 7, 8], dtype=np.int32)
+    out = np.zeros(10)
+    got = oracle.scatter_sq(x, idx, out, rows=(0, 5))
+    expect = np.zeros(10)
+    expect[3], expect[0], expect[9] = 0.0, 9.0, 16.0
+    assert np.array_equal(got, expect)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 5, 8])
+def test_scatter_filtered_partitions_equal_plain(K):
+    n = 257
+    x = inputs.uniform(n, seed=13)
+    idx = np.random.default_rng(14).permutation(n).astype(np.int32)
+    out = inputs.uniform(n, seed=15)
+    assert np.array_equal(oracle.scatter_sq_partitioned(x, idx, out, K), oracle.scatter_sq(x, idx, out))

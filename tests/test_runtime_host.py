@@ -441,3 +441,27 @@ def test_independent_k1_loops_spread_over_streams():
     streams = [t["stream"] for t in c.trace() if t["op"] == "KERNEL"]
     assert len(set(streams)) == 4
     assert race_check(c.trace()) == []
+
+
+# ------------------------------------------------------------------ predicate filtering
+def test_filtered_scatter_runs_whole_range_and_writes_owner_blocks():
+    c = dry(3)
+    n = 20
+    x = np.zeros(n)
+    idx = np.zeros(n, dtype=np.int32)
+    out = np.zeros(n)
+    c.enter(x, whole=True)
+    c.enter(idx, whole=True)
+    c.enter(out)
+    c.trace_clear()
+    c.scatter_sq(x, idx, out)
+    tr = c.trace()
+    assert [(t["dst"], t["lo"], t["hi"]) for t in tr if t["op"] == "KERNEL"] == [(p, 0, n) for p in range(3)]
+    writes = [(t["dst"], t["lo"], t["hi"]) for t in tr if t["op"] == "ACCESS" and t["kind"] == 2]
+    assert writes == [(p, *P.block(n, 3, p)) for p in range(3)]
+    # an unfiltered declaration of the indirect output is refused
+    rc = c.loop(jacc.SCATTER_SQ, jacc.bounds((0, n)), [(x, jacc.READ, 0, 0, 1), (idx, jacc.READ, 0, 0, 1),
+                                                       (out, jacc.WRITE, 0, 0, 0)], raw=True)
+    assert rc == jacc.ERR_INVALID
+    c.exit(out)
+    assert race_check(c.trace()) == []
