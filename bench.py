@@ -35,6 +35,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "jacobi2d_counters.json")
+STENCIL_SOURCES = [os.path.join(ROOT, "paper_2110_14340_amd", "csrc", f) for f in ("k_stencil.hip", "k_common.h")]
+
+
+def counted_traffic():
+    """HBM bytes per Jacobi launch from the committed FETCH_SIZE/WRITE_SIZE
+    counter record, or None when the kernel sources changed since then."""
+    import hashlib
+    try:
+        with open(COUNTERS) as f:
+            rec = json.load(f)
+        h = hashlib.sha1(b"".join(open(p, "rb").read() for p in STENCIL_SOURCES)).hexdigest()
+    except OSError:
+        return None
+    return int(rec["traffic_bytes_per_launch"]) if rec.get("source_sha1") == h else None
+
+
 def run_jacobi(ctx_mod, torch, u0, K, steps, warmup, cfg=None):
     """Times `steps` partitioned Jacobi sweeps after `warmup` untimed ones.
     Returns (seconds, stream-0 event seconds, final grid)."""
@@ -272,9 +289,10 @@ def main():
         ach = step_bytes / avg / 1e9
         result["roofline"] = {"kernel": "jacobi2d_kernel<2> (K=1, whole interior per launch)", "bound": "hbm",
                               "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counted_traffic(),
                               "avg_launch_us": round(avg * 1e6, 2),
-                              "bytes_per_launch": int(step_bytes)}
+                              "bytes_per_launch": int(step_bytes),
+                              "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)"}
     if not args.no_extra:
         log("secondary workloads")
         result["extra"] = extra_workloads(jacc, torch, inputs)
