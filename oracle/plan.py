@@ -85,7 +85,7 @@ class ArrayState:
         self.valid = [set(s) for s in self.slabs]
 
 
-def plan_loop(arrays, lb, ub, args, refresh="pull"):
+def plan_loop(arrays, lb, ub, args, refresh="pull", max_holders=2):
     """Plan one loop nest.
 
     arrays: dict name -> ArrayState (all partitioned arrays share E and K).
@@ -93,7 +93,10 @@ def plan_loop(arrays, lb, ub, args, refresh="pull"):
     refresh: "pull" copies stale rows before a read; "holders" has every
     write also refresh the other slabs that hold the written rows (the
     paper's send-updated-data-after-the-kernel, restricted to the holders),
-    so nothing is ever stale.
+    as long as at most `max_holders` other slabs hold any of them (a halo
+    no deeper than the blocks reaches one neighbour block on each side);
+    a write reaching more holders invalidates them instead, and their
+    readers pull.
     Returns a list, per partition p, of dicts with keys I (set), reads
     {name: rows}, writes {name: rows}, copies [(name, src, lo, hi)], and
     updates the states.  Raises ValueError on a range violation.
@@ -155,9 +158,11 @@ def plan_loop(arrays, lb, ub, args, refresh="pull"):
             for r in rows:
                 st.writer[r] = p
             st.valid[p] |= rows
+            holders = [q for q in range(K) if q != p and rows & st.slabs[q]]
+            mirror = refresh == "holders" and len(holders) <= max_holders
             for q in range(K):
                 if q != p:
-                    if refresh == "holders":
+                    if mirror:
                         st.valid[q] |= rows & st.slabs[q]
                     else:
                         st.valid[q] -= rows

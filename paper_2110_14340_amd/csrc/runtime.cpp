@@ -460,7 +460,9 @@ int hazard(jacc_ctx *c, Array *A, int p, Range r, bool write, int s) {
             pc.val.ws = s;
             pc.val.wseq = next;
             pc.val.reads.clear();
-        } else if (pc.val.ws != s) {
+        } else {
+            // recorded even when s is the last writer: a later write from
+            // another stream (a mirror store) must still wait for this read
             bool found = false;
             for (auto &rd : pc.val.reads)
                 if (rd.first == s) {
@@ -876,12 +878,12 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
         }
     }
     jk::Cfg cf{0, 0, 0, 0, 0, 0};
-    if (cfg) cf = {cfg->bx, cfg->by, cfg->tile, cfg->vec, cfg->persistent, cfg->order};
+    if (cfg) cf = {cfg->bx, cfg->by, cfg->tile, cfg->vec, cfg->persistent, cfg->order, cfg->march};
     L.cfg = jk::default_config(kind, L, cf);
     if (jk::check_config(L) != 0)
         return set_err(c, JACC_ERR_INVALID,
-                       "configuration bx=%d by=%d tile=%d vec=%d persistent=%d order=%d not valid for kind %d",
-                       L.cfg.bx, L.cfg.by, L.cfg.tile, L.cfg.vec, L.cfg.persistent, L.cfg.order, kind);
+                       "configuration bx=%d by=%d tile=%d vec=%d persistent=%d order=%d march=%d not valid for kind %d",
+                       L.cfg.bx, L.cfg.by, L.cfg.tile, L.cfg.vec, L.cfg.persistent, L.cfg.order, L.cfg.march, kind);
     if (L.cfg.persistent) {
         if (!c->cur) return set_err(c, JACC_ERR_INVALID, "persistent execution needs an open batch");
         if (want_red) return set_err(c, JACC_ERR_UNSUPPORTED, "persistent execution of a reduction");

@@ -92,7 +92,7 @@ def test_jacobi_k8_plan_matches_model_and_counts(lazy):
     assert freshness_check(full) == []
 
 
-@settings(max_examples=60, deadline=None)
+@settings(max_examples=int(os.environ.get("JACC_TEST_EXAMPLES", "60")), deadline=None)
 @given(E=st.integers(3, 24), K=st.integers(1, 6), hl=st.integers(0, 2), hh=st.integers(0, 2),
        steps=st.integers(1, 4), data=st.data())
 def test_random_loop_sequences_match_model(E, K, hl, hh, steps, data):
