@@ -134,7 +134,9 @@ def cpu_baseline(u0, budget_s=12.0):
 
 
 def extra_workloads(jacc, torch, inputs):
-    """Short secondary measurements of the other loop bodies (one GPU)."""
+    """Short secondary measurements of the other loop bodies (one GPU): the
+    cache-resident Jacobi 512^2 case, heat 512^3 with its residual, sum,
+    GEMM and SpMV, each at K=1 and at its partitioned K."""
     out = {}
 
     def timed(fn, reps):
@@ -146,74 +148,85 @@ def extra_workloads(jacc, torch, inputs):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps
 
-    # heat 512^3, K=4, residual every step
+    def stencil(u0, K, steps, sweep):
+        a, b = u0.copy(), u0.copy()
+        c = jacc.Context(K)
+        c.enter(a, halo=(1, 1))
+        c.enter(b, halo=(1, 1))
+
+        def run():
+            for t in range(steps):
+                s, d = (a, b) if t % 2 == 0 else (b, a)
+                sweep(c, s, d, t)
+            c.wait()
+
+        dt = timed(run, 1) / steps
+        c.close()
+        return dt
+
+    # Jacobi 512^2, T=100: 4 MiB, cache-resident, launch/latency bound
+    u0 = inputs.jacobi_grid(512, 512, seed=0)
+    for K in (1, 4):
+        dt = stencil(u0, K, 100, lambda c, s, d, t: c.jacobi2d(s, d))
+        out[f"jacobi2d_512_K{K}"] = {"us_per_step": round(dt * 1e6, 2),
+                                     "effective_gbps": round(16 * 510 * 510 / dt / 1e9, 1)}
+    # heat 512^3, T=100, residual every step into a device slot
     n = 512
     u0 = inputs.heat_field(n, n, n, seed=2)
-    a, b = u0.copy(), u0.copy()
-    c = jacc.Context(4)
-    c.enter(a, halo=(1, 1))
-    c.enter(b, halo=(1, 1))
-    state = {"t": 0}
-
-    def heat_step():
-        s, d = (a, b) if state["t"] % 2 == 0 else (b, a)
-        c.heat3d(s, d, 0.1, slot=state["t"] % 4000)
-        state["t"] += 1
-
-    def heat100():
-        for _ in range(100):
-            heat_step()
-        c.wait()
-
-    dt = timed(heat100, 1) / 100
     cells = (n - 2) ** 3
-    out["heat3d_512_K4_residual"] = {"gbps": round(16 * cells / dt / 1e9, 1), "ms_per_step": round(dt * 1e3, 4)}
-    c.close()
-    del a, b, u0
-    # sum over 512^3 (1 GiB), K=1
+    for K in (1, 4):
+        dt = stencil(u0, K, 100, lambda c, s, d, t: c.heat3d(s, d, 0.1, slot=t))
+        out[f"heat3d_512_K{K}_residual"] = {"gbps": round(16 * cells / dt / 1e9, 1), "ms_per_step": round(dt * 1e3, 4)}
+    out["heat3d_k4_overhead"] = round(out["heat3d_512_K1_residual"]["gbps"] / out["heat3d_512_K4_residual"]["gbps"] - 1, 4)
+    del u0
+    # sum over 512^3 (1 GiB)
     x = inputs.uniform((512, 512, 512), seed=7)
-    c = jacc.Context(1)
-    c.enter(x)
-    dt = timed(lambda: c.sum(x), 10)
-    out["sum_512cubed_K1"] = {"gbps": round(x.nbytes / dt / 1e9, 1), "ms": round(dt * 1e3, 4)}
-    c.close()
+    for K in (1, 4):
+        c = jacc.Context(K)
+        c.enter(x)
+        dt = timed(lambda: c.sum(x), 10)
+        out[f"sum_512cubed_K{K}"] = {"gbps": round(x.nbytes / dt / 1e9, 1), "ms": round(dt * 1e3, 4)}
+        c.close()
     del x
-    # GEMM 4096^3 FP64 MFMA, K=1
+    # GEMM 4096^3 FP64 MFMA
     A, B = inputs.gemm_inputs(4096, 4096, 4096, seed=3)
     C = np.zeros((4096, 4096))
-    c = jacc.Context(1)
-    c.enter(A)
-    c.enter(B, whole=True)
-    c.enter(C, clause=jacc.CREATE)
+    for K in (1, 4):
+        c = jacc.Context(K)
+        c.enter(A)
+        c.enter(B, whole=True)
+        c.enter(C, clause=jacc.CREATE)
 
-    def g():
-        c.gemm(A, B, C)
-        c.wait()
+        def g():
+            c.gemm(A, B, C)
+            c.wait()
 
-    dt = timed(g, 5)
-    out["gemm_4096_K1"] = {"tflops": round(2 * 4096 ** 3 / dt / 1e12, 2), "ms": round(dt * 1e3, 3),
-                           "frac_fp64_peak": round(2 * 4096 ** 3 / dt / 1e12 / FP64_MFMA_PEAK_TFLOPS, 3)}
-    c.close()
+        dt = timed(g, 5)
+        tf = 2 * 4096 ** 3 / dt / 1e12
+        out[f"gemm_4096_K{K}"] = {"tflops": round(tf, 2), "ms": round(dt * 1e3, 3),
+                                  "frac_fp64_peak": round(tf / FP64_MFMA_PEAK_TFLOPS, 3)}
+        c.close()
     del A, B, C
-    # SpMV 2^22 rows, ~16 nnz/row, K=1
+    # SpMV 2^22 rows, ~16 nnz/row
     nr = 1 << 22
     rp, col, val, xv = inputs.csr_matrix(nr, nr, 16, seed=4)
     y = np.zeros(nr)
-    c = jacc.Context(1)
-    c.enter(rp, halo=(1, 1))
-    c.enter(col, whole=True)
-    c.enter(val, whole=True)
-    c.enter(xv, whole=True)
-    c.enter(y, clause=jacc.CREATE)
-
-    def sp():
-        c.spmv(rp, col, val, xv, y)
-        c.wait()
-
-    dt = timed(sp, 10)
     alg = rp.nbytes + col.nbytes + val.nbytes + xv.nbytes + y.nbytes
-    out["spmv_2^22_K1"] = {"gbps": round(alg / dt / 1e9, 1), "ms": round(dt * 1e3, 4), "nnz": int(col.size)}
-    c.close()
+    for K in (1, 4):
+        c = jacc.Context(K)
+        c.enter(rp, halo=(1, 1))
+        c.enter(col, whole=True)
+        c.enter(val, whole=True)
+        c.enter(xv, whole=True)
+        c.enter(y, clause=jacc.CREATE)
+
+        def sp():
+            c.spmv(rp, col, val, xv, y)
+            c.wait()
+
+        dt = timed(sp, 10)
+        out[f"spmv_2^22_K{K}"] = {"gbps": round(alg / dt / 1e9, 1), "ms": round(dt * 1e3, 4), "nnz": int(col.size)}
+        c.close()
     return out
 
 

@@ -143,9 +143,13 @@ typedef struct {
  *              chip hands consecutive workgroup ids to its 8 XCDs in turn; with
  *              this order each XCD walks one contiguous band of tiles, so the
  *              rows two neighbouring tiles share meet in that XCD's L2)
+ *   march      stencil march direction: 1 = every tile toward higher rows
+ *              (planes), 2 = odd tiles toward lower ones, so that the
+ *              boundary rows two neighbouring tiles share are read by both at
+ *              the same time (a cache hit for the second)
  * Fields equal to 0 take the default. */
 typedef struct {
-    int32_t bx, by, tile, vec, persistent, order;
+    int32_t bx, by, tile, vec, persistent, order, march;
 } jacc_config;
 
 /* Loop kinds (hand-written HIP loop bodies) and their arguments, in order:

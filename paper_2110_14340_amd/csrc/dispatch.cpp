@@ -21,13 +21,15 @@ Cfg default_config(int kind, const Launch &L, Cfg c) {
             if (!c.tile) c.tile = 32;
             if (!c.vec) c.vec = even ? 2 : 1;
             if (!c.order) c.order = 2;
+            if (!c.march) c.march = 1;
             break;
         case JACC_LOOP_HEAT3D:
-            if (!c.bx) c.bx = 128;
-            if (!c.by) c.by = 2;
-            if (!c.tile) c.tile = 16;
+            if (!c.bx) c.bx = 256;
+            if (!c.by) c.by = 4;
+            if (!c.tile) c.tile = 4;
             if (!c.vec) c.vec = even ? 2 : 1;
-            if (!c.order) c.order = 2;
+            if (!c.order) c.order = 1;
+            if (!c.march) c.march = 1;
             break;
         default:
             if (!c.bx) c.bx = 256;
@@ -35,6 +37,7 @@ Cfg default_config(int kind, const Launch &L, Cfg c) {
             if (!c.tile) c.tile = 1;
             if (!c.vec) c.vec = 1;
             if (!c.order) c.order = 1;
+            if (!c.march) c.march = 1;
             break;
     }
     return c;
@@ -52,6 +55,7 @@ int check_config(const Launch &L) {
             if (c.vec != 1 && c.vec != 2) return 1;
             if (c.vec == 2 && inner_extent(L) % 2) return 1;
             if (c.order != 1 && c.order != 2) return 1;
+            if (c.march != 1 && c.march != 2) return 1;
             return 0;
         case JACC_LOOP_SUM:
         case JACC_LOOP_GEMM:

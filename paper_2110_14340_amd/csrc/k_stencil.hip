@@ -88,19 +88,31 @@ __device__ __forceinline__ void store_out(double *out, int64_t off, int64_t r, c
         if (r >= mir.m[k].lo && r < mir.m[k].hi) store_masked<VEC>(mir.m[k].ptr + off, o, all, comp);
 }
 
+// March direction of the wave's tile q: with march == 2 odd tiles run toward
+// lower rows, so the two rows a pair of neighbouring tiles share are read by
+// both at about the same time (both at their start or both at their end)
+// and the second read hits in L2.  The stencils are symmetric in the marched
+// dimension and the vertical pair sum is commutative, so the direction never
+// changes a result bit.
+__device__ __forceinline__ int64_t march_dir(int march, int64_t q) { return (march == 2 && (q & 1)) ? -1 : 1; }
+
 // ---------------------------------------------------------------------------
 // Jacobi-2D tile: lanes [tx] of row-group [ty] of workgroup tile (bxi, byi)
 // ---------------------------------------------------------------------------
 template <int VEC>
 __device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, double *__restrict__ out, int64_t nx,
                                             int64_t r_lo, int64_t r_hi, int64_t c_lo, int64_t c_hi, int64_t col0,
-                                            int tile, const Mirrors &mir, int64_t bxi, int64_t byi, int tx, int ty,
-                                            int bdx, int bdy) {
+                                            int tile, int march, const Mirrors &mir, int64_t bxi, int64_t byi, int tx,
+                                            int ty, int bdx, int bdy) {
     const int lane = tx & (kWave - 1);
     const int64_t j = col0 + (bxi * bdx + tx) * VEC;
-    const int64_t i0 = r_lo + (byi * bdy + ty) * tile;
+    const int64_t q = byi * bdy + ty;
+    const int64_t i0 = r_lo + q * tile;
     if (i0 >= r_hi) return;  // uniform across the wave (one ty per wave)
     const int64_t i1 = i0 + tile < r_hi ? i0 + tile : r_hi;
+    const int64_t n = i1 - i0;
+    const int64_t d = march_dir(march, q);
+    const int64_t a = d > 0 ? i0 : i1 - 1;  // first row computed
     const bool inb = j < c_hi + 1 && j < nx;  // lane holds columns the box needs
     bool comp[VEC];
     bool all = true;
@@ -112,30 +124,29 @@ __device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, doubl
     const bool need_l = comp[0];
     const bool need_r = comp[VEC - 1];
 
+    // ring entry k holds row a + (k-1)*d; loads k = 0 .. n+1
     Row<VEC> r[kU + 2];
 #pragma unroll
-    for (int k = 0; k < kU + 2; ++k) {
-        const int64_t row = i0 - 1 + k;
-        if (row <= i1) load_row<VEC>(in + row * nx + j, inb, lane, need_l, need_r, r[k]);
-    }
-    for (int64_t i = i0; i < i1; i += kU) {
+    for (int k = 0; k < kU + 2; ++k)
+        if (k <= n + 1) load_row<VEC>(in + (a + (k - 1) * d) * nx + j, inb, lane, need_l, need_r, r[k]);
+    for (int64_t m = 0; m < n; m += kU) {
         Row<VEC> nxt[kU];
 #pragma unroll
         for (int k = 0; k < kU; ++k) {
-            const int64_t row = i + kU + 1 + k;
-            if (row <= i1) load_row<VEC>(in + row * nx + j, inb, lane, need_l, need_r, nxt[k]);
+            const int64_t idx = m + kU + 2 + k;
+            if (idx <= n + 1) load_row<VEC>(in + (a + (idx - 1) * d) * nx + j, inb, lane, need_l, need_r, nxt[k]);
         }
 #pragma unroll
         for (int k = 0; k < kU; ++k) {
-            const int64_t row = i + k;
-            if (row < i1) {
-                const Row<VEC> &up = r[k], &mid = r[k + 1], &dn = r[k + 2];
+            if (m + k < n) {
+                const int64_t row = a + (m + k) * d;
+                const Row<VEC> &prev = r[k], &mid = r[k + 1], &next = r[k + 2];
                 double left[VEC], right[VEC];
                 horizontal<VEC>(mid, lane, left, right);
                 double o[VEC];
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {
-                    const double vert = up.v[v] + dn.v[v];
+                    const double vert = prev.v[v] + next.v[v];
                     const double horz = left[v] + right[v];
                     o[v] = 0.25 * (vert + horz);
                 }
@@ -161,9 +172,9 @@ __device__ __forceinline__ int64_t tile_of(int order) {
 template <int VEC>
 __global__ void __launch_bounds__(1024)
 jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t nx, int64_t r_lo, int64_t r_hi,
-                int64_t c_lo, int64_t c_hi, int64_t col0, int tile, Mirrors mir, int64_t gx, int order) {
+                int64_t c_lo, int64_t c_hi, int64_t col0, int tile, int march, Mirrors mir, int64_t gx, int order) {
     const int64_t t = tile_of(order);
-    jacobi_tile<VEC>(in, out, nx, r_lo, r_hi, c_lo, c_hi, col0, tile, mir, t % gx, t / gx, threadIdx.x,
+    jacobi_tile<VEC>(in, out, nx, r_lo, r_hi, c_lo, c_hi, col0, tile, march, mir, t % gx, t / gx, threadIdx.x,
                      threadIdx.y, blockDim.x, blockDim.y);
 }
 
@@ -174,7 +185,7 @@ jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t
 template <int VEC, bool RES>
 __device__ __forceinline__ double heat_tile(const double *__restrict__ in, double *__restrict__ out, int64_t ny,
                                             int64_t nx, int64_t z_lo, int64_t z_hi, int64_t y_lo, int64_t y_hi,
-                                            int64_t x_lo, int64_t x_hi, int64_t col0, int tile, double alpha,
+                                            int64_t x_lo, int64_t x_hi, int64_t col0, int tile, int march, double alpha,
                                             const Mirrors &mir, int64_t bxi, int64_t byi, int64_t bzi, int tx,
                                             int ty, int bdx, int bdy) {
     const int lane = tx & (kWave - 1);
@@ -184,6 +195,9 @@ __device__ __forceinline__ double heat_tile(const double *__restrict__ in, doubl
     const int64_t z1 = z0 + tile < z_hi ? z0 + tile : z_hi;
     double acc = 0.0;
     if (y >= y_hi || z0 >= z1) return acc;  // uniform across the wave
+    const int64_t n = z1 - z0;
+    const int64_t d = march_dir(march, bzi);
+    const int64_t a = d > 0 ? z0 : z1 - 1;  // first plane computed
     const bool inb = x < x_hi + 1 && x < nx;
     bool comp[VEC];
     bool all = true;
@@ -197,24 +211,23 @@ __device__ __forceinline__ double heat_tile(const double *__restrict__ in, doubl
     const int64_t plane = ny * nx;
     const double *base = in + y * nx + x;
 
+    // ring entry k holds plane a + (k-1)*d; loads k = 0 .. n+1
     Row<VEC> r[kU + 2];
 #pragma unroll
-    for (int k = 0; k < kU + 2; ++k) {
-        const int64_t z = z0 - 1 + k;
-        if (z <= z1) load_row<VEC>(base + z * plane, inb, lane, need_l, need_r, r[k]);
-    }
-    for (int64_t zb = z0; zb < z1; zb += kU) {
+    for (int k = 0; k < kU + 2; ++k)
+        if (k <= n + 1) load_row<VEC>(base + (a + (k - 1) * d) * plane, inb, lane, need_l, need_r, r[k]);
+    for (int64_t m = 0; m < n; m += kU) {
         Row<VEC> nxt[kU];
 #pragma unroll
         for (int k = 0; k < kU; ++k) {
-            const int64_t z = zb + kU + 1 + k;
-            if (z <= z1) load_row<VEC>(base + z * plane, inb, lane, need_l, need_r, nxt[k]);
+            const int64_t idx = m + kU + 2 + k;
+            if (idx <= n + 1) load_row<VEC>(base + (a + (idx - 1) * d) * plane, inb, lane, need_l, need_r, nxt[k]);
         }
 #pragma unroll
         for (int k = 0; k < kU; ++k) {
-            const int64_t z = zb + k;
-            if (z < z1) {
-                const Row<VEC> &zm = r[k], &c = r[k + 1], &zp = r[k + 2];
+            if (m + k < n) {
+                const int64_t z = a + (m + k) * d;
+                const Row<VEC> &zprev = r[k], &c = r[k + 1], &znext = r[k + 2];
                 // y neighbours: rows of the same plane (cache hits)
                 double ym[VEC], yp[VEC];
                 const double *pc = base + z * plane;
@@ -232,12 +245,12 @@ __device__ __forceinline__ double heat_tile(const double *__restrict__ in, doubl
                 for (int v = 0; v < VEC; ++v) {
                     const double px = xm[v] + xp[v];
                     const double py = ym[v] + yp[v];
-                    const double pz = zm.v[v] + zp.v[v];
+                    const double pz = zprev.v[v] + znext.v[v];
                     const double lap = ((px + py) + pz) - 6.0 * c.v[v];
                     o[v] = c.v[v] + alpha * lap;
                     if (RES && comp[v]) {
-                        const double d = o[v] - c.v[v];
-                        acc += d * d;
+                        const double dd = o[v] - c.v[v];
+                        acc += dd * dd;
                     }
                 }
                 store_out<VEC>(out, z * plane + y * nx + x, z, mir, o, all, comp);
@@ -255,12 +268,13 @@ template <int VEC, bool RES>
 __global__ void __launch_bounds__(1024)
 heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t ny, int64_t nx, int64_t z_lo,
               int64_t z_hi, int64_t y_lo, int64_t y_hi, int64_t x_lo, int64_t x_hi, int64_t col0, int tile,
-              double alpha, double *__restrict__ wg_partials, Mirrors mir, int64_t gx, int64_t gy, int order) {
+              int march, double alpha, double *__restrict__ wg_partials, Mirrors mir, int64_t gx, int64_t gy,
+              int order) {
     __shared__ double sh[16];
     const int64_t t = tile_of(order);
     const int64_t rest = t / gx;
-    const double acc = heat_tile<VEC, RES>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, alpha,
-                                           mir, t % gx, rest % gy, rest / gy, threadIdx.x, threadIdx.y, blockDim.x,
+    const double acc = heat_tile<VEC, RES>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, march,
+                                           alpha, mir, t % gx, rest % gy, rest / gy, threadIdx.x, threadIdx.y, blockDim.x,
                                            blockDim.y);
     if (RES) {
         const double s = block_sum(acc, sh);
@@ -289,20 +303,20 @@ persistent_kernel(const PTask *__restrict__ tasks, int ntasks, int64_t total) {
         const int64_t rest = local / T.gx;
         if (T.kind == JACC_LOOP_JACOBI2D) {
             if (T.vec == 2)
-                jacobi_tile<2>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.mir, bxi,
+                jacobi_tile<2>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, T.mir, bxi,
                                rest, threadIdx.x, 0, kPersistentThreads, 1);
             else
-                jacobi_tile<1>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.mir, bxi,
+                jacobi_tile<1>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, T.mir, bxi,
                                rest, threadIdx.x, 0, kPersistentThreads, 1);
         } else {
             const int64_t byi = rest % T.gy, bzi = rest / T.gy;
             if (T.vec == 2)
                 (void)heat_tile<2, false>(T.in, T.out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2],
-                                          T.hi[2], T.col0, T.tile, T.alpha, T.mir, bxi, byi, bzi, threadIdx.x, 0,
+                                          T.hi[2], T.col0, T.tile, T.march, T.alpha, T.mir, bxi, byi, bzi, threadIdx.x, 0,
                                           kPersistentThreads, 1);
             else
                 (void)heat_tile<1, false>(T.in, T.out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2],
-                                          T.hi[2], T.col0, T.tile, T.alpha, T.mir, bxi, byi, bzi, threadIdx.x, 0,
+                                          T.hi[2], T.col0, T.tile, T.march, T.alpha, T.mir, bxi, byi, bzi, threadIdx.x, 0,
                                           kPersistentThreads, 1);
         }
     }
@@ -331,10 +345,10 @@ hipError_t launch_jacobi2d(const Launch &L, hipStream_t s) {
     double *out = (double *)L.a[1].ptr;
     if (c.vec == 2)
         hipLaunchKernelGGL(jacobi2d_kernel<2>, grid, block, 0, s, in, out, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1],
-                           col0, c.tile, L.mir, gx, c.order);
+                           col0, c.tile, c.march, L.mir, gx, c.order);
     else
         hipLaunchKernelGGL(jacobi2d_kernel<1>, grid, block, 0, s, in, out, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1],
-                           col0, c.tile, L.mir, gx, c.order);
+                           col0, c.tile, c.march, L.mir, gx, c.order);
     return hipGetLastError();
 }
 
@@ -369,8 +383,8 @@ hipError_t launch_heat3d(const Launch &L, hipStream_t s) {
     const double alpha = L.scalars[0];
     const bool res = L.wg_partials != nullptr;
 #define HEAT_ARGS                                                                                                    \
-    in, out, ny, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1], L.lo[2], L.hi[2], col0, c.tile, alpha, L.wg_partials, L.mir, \
-        gx, gy, c.order
+    in, out, ny, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1], L.lo[2], L.hi[2], col0, c.tile, c.march, alpha,             \
+        L.wg_partials, L.mir, gx, gy, c.order
     if (c.vec == 2) {
         if (res)
             hipLaunchKernelGGL((heat3d_kernel<2, true>), grid, block, 0, s, HEAT_ARGS);
@@ -391,6 +405,7 @@ bool make_task(const Launch &L, PTask *t) {
     t->kind = L.kind;
     t->vec = L.cfg.vec;
     t->tile = L.cfg.tile;
+    t->march = L.cfg.march;
     t->in = (const double *)L.a[0].ptr;
     t->out = (double *)L.a[1].ptr;
     t->mir = L.mir;

@@ -17,7 +17,7 @@ struct Arg {
 };
 
 struct Cfg {
-    int bx, by, tile, vec, persistent, order;
+    int bx, by, tile, vec, persistent, order, march;
 };
 
 // Write-through targets of a stencil launch: rows [lo, hi) of dim 0 that the
@@ -76,7 +76,7 @@ hipError_t launch_combine(const double *partials, const CombineList &list, doubl
 // 256 threads (256*vec columns x `tile` rows, or x 1 row x `tile` planes).
 struct PTask {
     int32_t kind;  // JACC_LOOP_JACOBI2D or JACC_LOOP_HEAT3D
-    int32_t vec, tile, pad_;
+    int32_t vec, tile, march;
     const double *in;
     double *out;
     int64_t e1, e2;  // extents of dims 1 and 2 (2-D: e1 = row length)

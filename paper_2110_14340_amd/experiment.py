@@ -72,6 +72,8 @@ def run(n2d=128, n3d=128, train2d=24, train3d=24, epochs=300, tune_reps=5, graph
     t0 = time.perf_counter()
     for li, sh in enumerate(train_shapes):
         cands, meds, _ = tuner.tune(ctx, sh, _data(sh, 1000 + li), db=db, reps=tune_reps)
+        if li % 16 == 15:
+            log(f"  tuned {li + 1}/{len(train_shapes)} training shapes")
         for c, m in zip(cands, meds):
             X.append(tuner.features(sh, c))
             y.append(math.log(m))
@@ -101,6 +103,8 @@ def run(n2d=128, n3d=128, train2d=24, train3d=24, epochs=300, tune_reps=5, graph
         mlp.append(pick)
         dflt.append(dict(tuner.DEFAULT_CONFIG))
         regret_loop.append(meds[cands.index(pick)] / meds[best] - 1.0)
+        if li % 32 == 31:
+            log(f"  tuned {li + 1}/{len(test_shapes)} test shapes")
     t_test_tune = time.perf_counter() - t0
     db.save()
     model.close()

@@ -76,7 +76,7 @@ def _batch_members(seed, n2, n3):
 def test_persistent_group_of_uneven_sweeps_bit_exact():
     say("persistent group: 24 uneven 2-D/3-D sweeps")
     shapes = _batch_members(23, 16, 8)
-    cfgs = [jacc.config(tile=t, vec=v, persistent=1) for t in (1, 3, 8) for v in (1, 2)]
+    cfgs = [jacc.config(tile=t, vec=v, persistent=1, march=m) for t in (1, 3, 8) for v in (1, 2) for m in (1, 2)]
     ins, outs, refs = [], [], []
     with context(4) as c:
         for i, sh in enumerate(shapes):
@@ -96,7 +96,7 @@ def test_persistent_group_of_uneven_sweeps_bit_exact():
         for i, sh in enumerate(shapes):
             cf = cfgs[i % len(cfgs)]
             if cf.vec == 2 and sh[-1] % 2:
-                cf = jacc.config(tile=cf.tile, vec=1, persistent=1)
+                cf = jacc.config(tile=cf.tile, vec=1, persistent=1, march=cf.march)
             if len(sh) == 2:
                 c.jacobi2d(ins[i], outs[i], cfg=cf)
             else:

@@ -11,8 +11,8 @@ from gpu_util import run_heat, run_jacobi, say
 pytestmark = pytest.mark.gpu
 
 
-def _cfg(bx, by, tile, vec):
-    return jacc.config(bx=bx, by=by, tile=tile, vec=vec)
+def _cfg(bx, by, tile, vec, order=0, march=0):
+    return jacc.config(bx=bx, by=by, tile=tile, vec=vec, order=order, march=march)
 
 
 # ------------------------------------------------------------------ Jacobi
@@ -29,6 +29,8 @@ def test_jacobi_512_100_steps_bit_exact(K):
     ((37, 29), 1, None), ((37, 29), 3, None), ((130, 67), 5, _cfg(64, 2, 3, 1)),
     ((200, 258), 7, _cfg(128, 1, 5, 2)), ((64, 1030), 2, _cfg(64, 4, 1, 2)),
     ((9, 9), 7, _cfg(64, 1, 1, 1)), ((300, 130), 4, _cfg(256, 4, 64, 2)),
+    ((131, 258), 3, _cfg(128, 2, 5, 2, march=2)), ((77, 67), 1, _cfg(64, 1, 4, 1, order=2, march=2)),
+    ((1030, 1026), 4, _cfg(256, 1, 32, 2, order=2, march=2)), ((5, 130), 2, _cfg(64, 1, 3, 2, march=2)),
 ])
 def test_jacobi_ragged_shapes_partitions_configs(shape, K, cfg):
     say(f"jacobi ragged {shape} K={K}")
@@ -72,6 +74,7 @@ def _rel_close(a, b, tol=1e-13):
 @pytest.mark.parametrize("shape,K,cfg", [
     ((34, 29, 40), 1, None), ((34, 29, 40), 4, None), ((19, 17, 67), 3, _cfg(64, 2, 3, 1)),
     ((40, 12, 130), 2, _cfg(64, 1, 7, 2)), ((10, 70, 66), 4, _cfg(128, 4, 1, 2)),
+    ((41, 13, 130), 3, _cfg(64, 2, 5, 2, march=2)), ((23, 9, 67), 1, _cfg(64, 1, 4, 1, order=2, march=2)),
 ])
 def test_heat_small_bit_exact_and_residual(shape, K, cfg):
     say(f"heat {shape} K={K}")
