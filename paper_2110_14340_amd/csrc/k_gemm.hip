@@ -10,7 +10,8 @@
 // matrix cores.
 //
 // MFMA operand layout (16x16x4, FP64, wave64): lane l supplies A[l%16][l/16]
-// and B[l/16][l%16]; accumulator element r of lane l is D[4*(l/16)+r][l%16].
+// and B[l/16][l%16]; accumulator element r of lane l is D[4*r + l/16][l%16]
+// (rows interleave across the four 16-lane groups).
 #include "k_common.h"
 #include "kernels.h"
 
@@ -125,12 +126,12 @@ gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *
         }
         __syncthreads();
     }
-    // write back: acc[i][j][r] -> C[row0 + wm*64 + i*16 + 4*(lane/16) + r][col0 + wn*64 + j*16 + lane%16]
+    // write back: acc[i][j][r] -> C[row0 + wm*64 + i*16 + 4*r + lane/16][col0 + wn*64 + j*16 + lane%16]
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int64_t gi = row0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+            const int64_t gi = row0 + wm * 64 + i * 16 + 4 * r + (lane >> 4);
             if (gi >= m_hi) continue;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {

@@ -64,8 +64,8 @@ int check_config(const Launch &L);
 Cfg default_config(int kind, const Launch &L, Cfg c);
 
 // Reduction combine: out[0] = sum of partials[idx[k]] for k = 0..n-1 in
-// that order (idx lists the streams of the reducing partitions in partition
-// order).
+// that order (idx lists the reducing partitions in partition order; each
+// partition's finaliser writes partials[p]).
 struct CombineList {
     int n;
     int idx[64];

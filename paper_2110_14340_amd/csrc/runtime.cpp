@@ -268,9 +268,9 @@ struct jacc_ctx {
     uintptr_t fake_next = (uintptr_t)1 << 44;
     // reductions (buffers indexed by stream)
     double *slots = nullptr;             // kSlots doubles
-    double *partials = nullptr;          // kMaxK doubles, one per stream
+    double *partials = nullptr;          // kMaxK doubles, one per partition
     double *wg = nullptr;                // streams * kWgCapacity doubles
-    std::vector<SeqRef> partial_reader;  // last combine that read partials[s]
+    std::vector<SeqRef> partial_reader;  // last combine that read partials[p]
     std::vector<SeqRef> slot_src;        // op that produced each slot
     // batches
     std::vector<Batch *> batches;
@@ -956,7 +956,8 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     // other slabs hold as halo (at most one neighbour block on each side)
     const bool can_mirror =
         !c->lazy && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) && !P->whole && K > 1;
-    std::vector<int> order;  // streams of the partitions that reduce, in partition order
+    std::vector<int> order;       // partitions that reduce, in partition order
+    std::vector<int> red_streams;  // their streams
     for (int p = 0; p < K; ++p) {
         const PartPlan &pp = plan[p];
         if (pp.iters.empty()) continue;
@@ -1034,17 +1035,19 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             if (rc) return rc;
         }
         if (want_red) {
-            // partials[s] and the workgroup scratch of stream s are read by
-            // the last combine that used them
-            rc = ensure_wait(c, s, c->partial_reader[s].s, c->partial_reader[s].seq);
+            // partials[p] is read by the last combine that used it; the
+            // workgroup scratch of stream s is consumed by the finaliser that
+            // follows the kernel on the same stream
+            rc = ensure_wait(c, s, c->partial_reader[p].s, c->partial_reader[p].seq);
             if (rc) return rc;
             LP.wg_partials = c->wg + (size_t)s * kWgCapacity;
             LP.wg_capacity = kWgCapacity;
-            LP.part_out = c->partials + s;
+            LP.part_out = c->partials + p;
             if (jk::reduction_workgroups(LP) > kWgCapacity)
                 return set_err(c, JACC_ERR_UNSUPPORTED, "reduction needs more than %lld workgroups",
                                (long long)kWgCapacity);
-            order.push_back(s);
+            order.push_back(p);
+            red_streams.push_back(s);
         }
         if (inject_fault(c, 2)) {
             c->status = JACC_ERR_DEVICE;
@@ -1066,7 +1069,7 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     }
     if (want_red) {
         const int s0 = one_stream ? 0 : base % ns;
-        for (int s : order) {
+        for (int s : red_streams) {
             rc = ensure_wait(c, s0, s, c->st[s].seq);
             if (rc) return rc;
         }
@@ -1080,7 +1083,7 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             HIPCHK(c, jk::launch_combine(c->partials, cl, c->slots + sl, c->st[s0].s), "combine launch");
         }
         c->st[s0].seq++;
-        for (int s : order) c->partial_reader[s] = {s0, c->st[s0].seq};
+        for (int q : order) c->partial_reader[q] = {s0, c->st[s0].seq};
         c->slot_src[sl] = {s0, c->st[s0].seq};
         trace(c, JACC_OP_COMBINE, s0, -1, -1, -1, sl, 0, 0, c->st[s0].seq);
         rc = post_op(c);
@@ -1209,7 +1212,7 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
         const int ns = c->serialize ? 1 : K;
         c->st.resize(ns);
         c->own_streams = (streams == nullptr);
-        c->partial_reader.assign(ns, SeqRef{});
+        c->partial_reader.assign(kMaxK, SeqRef{});
         c->slot_src.assign(kSlots, SeqRef{});
         int rc = JACC_OK;
         for (int s = 0; s < ns && !rc; ++s) {
