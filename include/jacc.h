@@ -147,9 +147,14 @@ typedef struct {
  *              (planes), 2 = odd tiles toward lower ones, so that the
  *              boundary rows two neighbouring tiles share are read by both at
  *              the same time (a cache hit for the second)
+ *   rows       HEAT3D: consecutive rows (dim 1) each wave holds, 1, 2, 4 or 8;
+ *              the y neighbours of inner rows then come from registers.  A
+ *              workgroup covers bx*vec columns and by*rows rows, and with
+ *              rows > 1 has at most 256 threads.  Persistent execution takes
+ *              rows = 1; JACOBI2D takes rows = 1.
  * Fields equal to 0 take the default. */
 typedef struct {
-    int32_t bx, by, tile, vec, persistent, order, march;
+    int32_t bx, by, tile, vec, persistent, order, march, rows;
 } jacc_config;
 
 /* Loop kinds (hand-written HIP loop bodies) and their arguments, in order:

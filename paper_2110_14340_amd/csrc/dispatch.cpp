@@ -18,18 +18,23 @@ Cfg default_config(int kind, const Launch &L, Cfg c) {
         case JACC_LOOP_JACOBI2D:
             if (!c.bx) c.bx = 256;
             if (!c.by) c.by = 1;
-            if (!c.tile) c.tile = 32;
+            if (!c.tile) c.tile = 8;
             if (!c.vec) c.vec = even ? 2 : 1;
-            if (!c.order) c.order = 2;
-            if (!c.march) c.march = 1;
+            if (!c.order) c.order = 1;
+            if (!c.march) c.march = 2;
+            if (!c.rows) c.rows = 1;
             break;
         case JACC_LOOP_HEAT3D:
-            if (!c.bx) c.bx = 256;
-            if (!c.by) c.by = 4;
+            if (!c.rows) {  // multi-row waves need workgroups of at most 256 threads
+                const int bx = c.bx ? c.bx : 128, by = c.by ? c.by : 2;
+                c.rows = (c.persistent || bx * by > 256) ? 1 : 4;
+            }
+            if (!c.bx) c.bx = c.rows > 1 ? 128 : 256;
+            if (!c.by) c.by = c.rows > 1 ? 2 : 4;
             if (!c.tile) c.tile = 4;
             if (!c.vec) c.vec = even ? 2 : 1;
             if (!c.order) c.order = 1;
-            if (!c.march) c.march = 1;
+            if (!c.march) c.march = 2;
             break;
         default:
             if (!c.bx) c.bx = 256;
@@ -38,6 +43,7 @@ Cfg default_config(int kind, const Launch &L, Cfg c) {
             if (!c.vec) c.vec = 1;
             if (!c.order) c.order = 1;
             if (!c.march) c.march = 1;
+            if (!c.rows) c.rows = 1;
             break;
     }
     return c;
@@ -56,6 +62,9 @@ int check_config(const Launch &L) {
             if (c.vec == 2 && inner_extent(L) % 2) return 1;
             if (c.order != 1 && c.order != 2) return 1;
             if (c.march != 1 && c.march != 2) return 1;
+            if (c.rows != 1 && (L.kind != JACC_LOOP_HEAT3D || c.persistent)) return 1;
+            if (c.rows != 1 && c.rows != 2 && c.rows != 4 && c.rows != 8) return 1;
+            if (c.rows != 1 && c.bx * c.by > 256) return 1;  // multi-row waves: workgroups of at most 256
             return 0;
         case JACC_LOOP_SUM:
         case JACC_LOOP_GEMM:

@@ -264,8 +264,129 @@ __device__ __forceinline__ double heat_tile(const double *__restrict__ in, doubl
     return acc;
 }
 
-template <int VEC, bool RES>
-__global__ void __launch_bounds__(1024)
+// ---------------------------------------------------------------------------
+// Heat-3D tile with R rows per wave: the wave's lanes own VEC columns of R
+// consecutive rows y = yb .. yb+R-1 and march through the planes of the
+// tile.  The y neighbours of the inner rows are the lane's own registers;
+// only the rows yb-1 and yb+R are loaded beside them, so a plane of R
+// output rows costs R+2 row loads instead of 3R.  Rows past the box's last
+// row are clamped to the boundary row y_hi (in bounds, never stored).
+// Three planes are held per row; the z sums are formed first, which frees
+// the oldest plane, and its registers then receive the loads of the plane
+// after next while the rest of the current plane is computed.
+// ---------------------------------------------------------------------------
+template <int VEC, int R>
+struct Planes {
+    double v[R + 2][VEC];  // v[k]: row min(yb + k - 1, y_hi)
+    double edge[R];        // beside the wave's span, rows 1..R (edge lanes only)
+};
+
+template <int VEC, int R>
+__device__ __forceinline__ void load_plane(const double *__restrict__ p, int64_t nx, int64_t yb, int64_t y_hi, int rr,
+                                           bool inb, int lane, bool need_l, bool need_r, Planes<VEC, R> &P) {
+#pragma unroll
+    for (int k = 0; k < R + 2; ++k) {
+        const int64_t y = yb + k - 1 < y_hi ? yb + k - 1 : y_hi;
+        const double *q = p + y * nx;
+        if (inb) {
+            load_vec<VEC>(q, P.v[k]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) P.v[k][v] = 0.0;
+        }
+        if (k >= 1 && k <= R) {
+            P.edge[k - 1] = 0.0;
+            if (k - 1 < rr) {
+                if (lane == 0 && need_l) P.edge[k - 1] = q[-1];
+                if (lane == kWave - 1 && need_r) P.edge[k - 1] = q[VEC];
+            }
+        }
+    }
+}
+
+template <int VEC, int R, bool RES>
+__device__ __forceinline__ double heat_rows_tile(const double *__restrict__ in, double *__restrict__ out, int64_t ny,
+                                                 int64_t nx, int64_t z_lo, int64_t z_hi, int64_t y_lo, int64_t y_hi,
+                                                 int64_t x_lo, int64_t x_hi, int64_t col0, int tile, int march,
+                                                 double alpha, const Mirrors &mir, int64_t bxi, int64_t byi,
+                                                 int64_t bzi, int tx, int ty, int bdx, int bdy) {
+    const int lane = tx & (kWave - 1);
+    const int64_t x = col0 + (bxi * bdx + tx) * VEC;
+    const int64_t yb = y_lo + (byi * bdy + ty) * R;
+    const int64_t z0 = z_lo + bzi * tile;
+    const int64_t z1 = z0 + tile < z_hi ? z0 + tile : z_hi;
+    double acc = 0.0;
+    if (yb >= y_hi || z0 >= z1) return acc;  // uniform across the wave
+    const int rr = (int)(y_hi - yb < R ? y_hi - yb : R);
+    const int64_t n = z1 - z0;
+    const int64_t d = march_dir(march, bzi);
+    const int64_t a = d > 0 ? z0 : z1 - 1;  // first plane computed
+    const bool inb = x < x_hi + 1 && x < nx;
+    bool comp[VEC];
+    bool all = true;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        comp[v] = (x + v >= x_lo) && (x + v < x_hi);
+        all = all && comp[v];
+    }
+    const bool need_l = comp[0];
+    const bool need_r = comp[VEC - 1];
+    const int64_t plane = ny * nx;
+    const double *col = in + x;
+
+    // plane k (k = 0 .. n+1) is a + (k-1)*d
+    auto load = [&](int64_t k, Planes<VEC, R> &P) {
+        load_plane<VEC, R>(col + (a + (k - 1) * d) * plane, nx, yb, y_hi, rr, inb, lane, need_l, need_r, P);
+    };
+    // computes plane m from A (plane m-1), B (m), C (m+1), then refills A
+    // with plane m+2 (index k = m+3) when there is one
+    auto step = [&](Planes<VEC, R> &A, const Planes<VEC, R> &B, const Planes<VEC, R> &C, int64_t m) {
+        double pz[R][VEC];
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) pz[i][v] = A.v[i + 1][v] + C.v[i + 1][v];
+        if (m + 3 <= n + 1) load(m + 3, A);
+        const int64_t z = a + m * d;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (i < rr) {
+                Row<VEC> c;
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) c.v[v] = B.v[i + 1][v];
+                c.edge = B.edge[i];
+                double xm[VEC], xp[VEC];
+                horizontal<VEC>(c, lane, xm, xp);
+                double o[VEC];
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    const double px = xm[v] + xp[v];
+                    const double py = B.v[i][v] + B.v[i + 2][v];
+                    const double lap = ((px + py) + pz[i][v]) - 6.0 * c.v[v];
+                    o[v] = c.v[v] + alpha * lap;
+                    if (RES && comp[v]) {
+                        const double dd = o[v] - c.v[v];
+                        acc += dd * dd;
+                    }
+                }
+                store_out<VEC>(out, z * plane + (yb + i) * nx + x, z, mir, o, all, comp);
+            }
+        }
+    };
+    Planes<VEC, R> P0, P1, P2;
+    load(0, P0);
+    load(1, P1);
+    load(2, P2);
+    for (int64_t m = 0; m < n; m += 3) {
+        step(P0, P1, P2, m);
+        if (m + 1 < n) step(P1, P2, P0, m + 1);
+        if (m + 2 < n) step(P2, P0, P1, m + 2);
+    }
+    return acc;
+}
+
+template <int VEC, int R, bool RES>
+__global__ void __launch_bounds__(R == 1 ? 1024 : 256)
 heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t ny, int64_t nx, int64_t z_lo,
               int64_t z_hi, int64_t y_lo, int64_t y_hi, int64_t x_lo, int64_t x_hi, int64_t col0, int tile,
               int march, double alpha, double *__restrict__ wg_partials, Mirrors mir, int64_t gx, int64_t gy,
@@ -273,9 +394,14 @@ heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t n
     __shared__ double sh[16];
     const int64_t t = tile_of(order);
     const int64_t rest = t / gx;
-    const double acc = heat_tile<VEC, RES>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, march,
-                                           alpha, mir, t % gx, rest % gy, rest / gy, threadIdx.x, threadIdx.y, blockDim.x,
-                                           blockDim.y);
+    double acc;
+    if constexpr (R == 1)
+        acc = heat_tile<VEC, RES>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, march, alpha, mir,
+                                  t % gx, rest % gy, rest / gy, threadIdx.x, threadIdx.y, blockDim.x, blockDim.y);
+    else
+        acc = heat_rows_tile<VEC, R, RES>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, march,
+                                          alpha, mir, t % gx, rest % gy, rest / gy, threadIdx.x, threadIdx.y,
+                                          blockDim.x, blockDim.y);
     if (RES) {
         const double s = block_sum(acc, sh);
         if (threadIdx.x == 0 && threadIdx.y == 0) wg_partials[t] = s;  // partials in tile order
@@ -355,7 +481,7 @@ hipError_t launch_jacobi2d(const Launch &L, hipStream_t s) {
 static dim3 heat_grid(const Launch &L, int64_t col0) {
     const Cfg &c = L.cfg;
     const int64_t ncols = L.hi[2] - col0;
-    return dim3((unsigned)cdiv(ncols, (int64_t)c.bx * c.vec), (unsigned)cdiv(L.hi[1] - L.lo[1], c.by),
+    return dim3((unsigned)cdiv(ncols, (int64_t)c.bx * c.vec), (unsigned)cdiv(L.hi[1] - L.lo[1], (int64_t)c.by * c.rows),
                 (unsigned)cdiv(L.hi[0] - L.lo[0], c.tile));
 }
 
@@ -385,17 +511,29 @@ hipError_t launch_heat3d(const Launch &L, hipStream_t s) {
 #define HEAT_ARGS                                                                                                    \
     in, out, ny, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1], L.lo[2], L.hi[2], col0, c.tile, c.march, alpha,             \
         L.wg_partials, L.mir, gx, gy, c.order
+#define HEAT_LAUNCH(V, R)                                                                 \
+    do {                                                                                  \
+        if (res)                                                                          \
+            hipLaunchKernelGGL((heat3d_kernel<V, R, true>), grid, block, 0, s, HEAT_ARGS);  \
+        else                                                                              \
+            hipLaunchKernelGGL((heat3d_kernel<V, R, false>), grid, block, 0, s, HEAT_ARGS); \
+    } while (0)
     if (c.vec == 2) {
-        if (res)
-            hipLaunchKernelGGL((heat3d_kernel<2, true>), grid, block, 0, s, HEAT_ARGS);
-        else
-            hipLaunchKernelGGL((heat3d_kernel<2, false>), grid, block, 0, s, HEAT_ARGS);
+        switch (c.rows) {
+            case 1: HEAT_LAUNCH(2, 1); break;
+            case 2: HEAT_LAUNCH(2, 2); break;
+            case 4: HEAT_LAUNCH(2, 4); break;
+            default: HEAT_LAUNCH(2, 8); break;
+        }
     } else {
-        if (res)
-            hipLaunchKernelGGL((heat3d_kernel<1, true>), grid, block, 0, s, HEAT_ARGS);
-        else
-            hipLaunchKernelGGL((heat3d_kernel<1, false>), grid, block, 0, s, HEAT_ARGS);
+        switch (c.rows) {
+            case 1: HEAT_LAUNCH(1, 1); break;
+            case 2: HEAT_LAUNCH(1, 2); break;
+            case 4: HEAT_LAUNCH(1, 4); break;
+            default: HEAT_LAUNCH(1, 8); break;
+        }
     }
+#undef HEAT_LAUNCH
 #undef HEAT_ARGS
     return hipGetLastError();
 }
@@ -437,9 +575,32 @@ bool make_task(const Launch &L, PTask *t) {
     return true;
 }
 
+// Workgroups of the persistent kernel that are resident at once on the
+// current device (occupancy x compute units): a larger grid would leave a
+// second, partial generation of workgroups running after the first, with
+// part of the chip idle.  Queried once per device.
+static int64_t persistent_grid_cap() {
+    static int64_t cap[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
+    if (!cap[dev]) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel, kPersistentThreads, 0) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu <= 0 ||
+            cus <= 0) {
+            (void)hipGetLastError();
+            return 1024;
+        }
+        cap[dev] = (int64_t)per_cu * cus;
+    }
+    return cap[dev];
+}
+
 hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, hipStream_t s) {
     if (ntasks <= 0 || tiles <= 0) return hipSuccess;
-    const int64_t grid = tiles < 2048 ? tiles : 2048;  // 256 CUs x 8 workgroups of 256 threads
+    const int64_t cap = persistent_grid_cap();
+    const int64_t grid = tiles < cap ? tiles : cap;
     hipLaunchKernelGGL(persistent_kernel, dim3((unsigned)grid), dim3(kPersistentThreads), 0, s, tasks, ntasks, tiles);
     return hipGetLastError();
 }

@@ -17,7 +17,7 @@ struct Arg {
 };
 
 struct Cfg {
-    int bx, by, tile, vec, persistent, order, march;
+    int bx, by, tile, vec, persistent, order, march, rows;
 };
 
 // Write-through targets of a stencil launch: rows [lo, hi) of dim 0 that the

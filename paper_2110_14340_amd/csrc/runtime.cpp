@@ -878,12 +878,13 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
         }
     }
     jk::Cfg cf{0, 0, 0, 0, 0, 0};
-    if (cfg) cf = {cfg->bx, cfg->by, cfg->tile, cfg->vec, cfg->persistent, cfg->order, cfg->march};
+    if (cfg) cf = {cfg->bx, cfg->by, cfg->tile, cfg->vec, cfg->persistent, cfg->order, cfg->march, cfg->rows};
     L.cfg = jk::default_config(kind, L, cf);
     if (jk::check_config(L) != 0)
         return set_err(c, JACC_ERR_INVALID,
-                       "configuration bx=%d by=%d tile=%d vec=%d persistent=%d order=%d march=%d not valid for kind %d",
-                       L.cfg.bx, L.cfg.by, L.cfg.tile, L.cfg.vec, L.cfg.persistent, L.cfg.order, L.cfg.march, kind);
+                       "configuration bx=%d by=%d tile=%d vec=%d persistent=%d order=%d march=%d rows=%d not valid for kind %d",
+                       L.cfg.bx, L.cfg.by, L.cfg.tile, L.cfg.vec, L.cfg.persistent, L.cfg.order, L.cfg.march,
+                       L.cfg.rows, kind);
     if (L.cfg.persistent) {
         if (!c->cur) return set_err(c, JACC_ERR_INVALID, "persistent execution needs an open batch");
         if (want_red) return set_err(c, JACC_ERR_UNSUPPORTED, "persistent execution of a reduction");

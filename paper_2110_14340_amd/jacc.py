@@ -52,7 +52,7 @@ class Bounds(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("vec", ctypes.c_int32), ("persistent", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("march", ctypes.c_int32)]
+                ("march", ctypes.c_int32), ("rows", ctypes.c_int32)]
 
 
 class Allocator(ctypes.Structure):
@@ -135,8 +135,8 @@ class JaccError(RuntimeError):
         self.status = status
 
 
-def config(bx=0, by=0, tile=0, vec=0, persistent=0, order=0, march=0):
-    return Config(bx, by, tile, vec, persistent, order, march)
+def config(bx=0, by=0, tile=0, vec=0, persistent=0, order=0, march=0, rows=0):
+    return Config(bx, by, tile, vec, persistent, order, march, rows)
 
 
 def bounds(*pairs):

@@ -11,8 +11,8 @@ from gpu_util import run_heat, run_jacobi, say
 pytestmark = pytest.mark.gpu
 
 
-def _cfg(bx, by, tile, vec, order=0, march=0):
-    return jacc.config(bx=bx, by=by, tile=tile, vec=vec, order=order, march=march)
+def _cfg(bx, by, tile, vec, order=0, march=0, rows=0):
+    return jacc.config(bx=bx, by=by, tile=tile, vec=vec, order=order, march=march, rows=rows)
 
 
 # ------------------------------------------------------------------ Jacobi
@@ -75,6 +75,9 @@ def _rel_close(a, b, tol=1e-13):
     ((34, 29, 40), 1, None), ((34, 29, 40), 4, None), ((19, 17, 67), 3, _cfg(64, 2, 3, 1)),
     ((40, 12, 130), 2, _cfg(64, 1, 7, 2)), ((10, 70, 66), 4, _cfg(128, 4, 1, 2)),
     ((41, 13, 130), 3, _cfg(64, 2, 5, 2, march=2)), ((23, 9, 67), 1, _cfg(64, 1, 4, 1, order=2, march=2)),
+    ((21, 19, 130), 2, _cfg(64, 2, 4, 2, rows=2)), ((17, 30, 66), 3, _cfg(64, 4, 7, 2, march=2, rows=4)),
+    ((13, 21, 131), 1, _cfg(128, 2, 3, 1, rows=8)), ((33, 11, 258), 4, _cfg(128, 1, 16, 2, order=2, rows=8)),
+    ((9, 3, 64), 2, _cfg(64, 1, 2, 2, rows=4)), ((12, 37, 70), 2, _cfg(256, 1, 5, 2, march=2, rows=2)),
 ])
 def test_heat_small_bit_exact_and_residual(shape, K, cfg):
     say(f"heat {shape} K={K}")
