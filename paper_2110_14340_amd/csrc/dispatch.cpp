@@ -18,7 +18,9 @@ Cfg default_config(int kind, const Launch &L, Cfg c) {
         case JACC_LOOP_JACOBI2D:
             if (!c.bx) c.bx = 256;
             if (!c.by) c.by = 1;
-            if (!c.tile) c.tile = 8;
+            // measured on 8190-column grids: 8-row tiles for partitions of
+            // 2048 rows and more, 16-row tiles for shorter ones
+            if (!c.tile) c.tile = L.part_rows >= 2048 ? 8 : 16;
             if (!c.vec) c.vec = even ? 2 : 1;
             if (!c.order) c.order = 1;
             if (!c.march) c.march = 2;

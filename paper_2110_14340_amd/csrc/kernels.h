@@ -50,6 +50,7 @@ struct Launch {
     double *wg_partials;
     int64_t wg_capacity;
     double *part_out;
+    int64_t part_rows;  // iterations along dim 0 of the largest partition (for defaults)
 };
 
 // Launches the loop body (and, for reductions, the per-partition

@@ -877,7 +877,9 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
                 }
         }
     }
-    jk::Cfg cf{0, 0, 0, 0, 0, 0};
+    jk::Cfg cf{0, 0, 0, 0, 0, 0, 0, 0};
+    L.part_rows = 0;
+    for (const PartPlan &pp : plan) L.part_rows = std::max(L.part_rows, pp.iters.hi - pp.iters.lo);
     if (cfg) cf = {cfg->bx, cfg->by, cfg->tile, cfg->vec, cfg->persistent, cfg->order, cfg->march, cfg->rows};
     L.cfg = jk::default_config(kind, L, cf);
     if (jk::check_config(L) != 0)

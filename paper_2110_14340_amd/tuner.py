@@ -28,14 +28,15 @@ import numpy as np
 
 from . import jacc
 
-DEFAULT_CONFIG = {"bx": 256, "by": 1, "tile": 1, "vec": 1, "K": 1, "persistent": 0}
+DEFAULT_CONFIG = {"bx": 256, "by": 1, "tile": 1, "vec": 1, "K": 1, "persistent": 0, "rows": 1}
 
 BLOCKS = [(64, 1), (128, 1), (256, 1), (512, 1), (64, 4), (128, 2), (256, 2), (256, 4)]
 TILES = [1, 4, 16, 64]
 VECS = [1, 2]
 KS = [1, 2]
 PERSISTENT_TILES = [1, 4, 16]
-NFEAT = 12
+ROWS_3D = [1, 4]  # heat: rows per wave (4 needs workgroups of at most 256 threads)
+NFEAT = 13
 
 
 def candidates(shape):
@@ -47,21 +48,33 @@ def candidates(shape):
         if K > shape[0] - 2:
             continue
         for bx, by in BLOCKS:
-            for tile in TILES:
-                for vec in VECS:
-                    if vec == 2 and not even:
-                        continue
-                    out.append({"bx": bx, "by": by, "tile": tile, "vec": vec, "K": K, "persistent": 0})
+            for rows in (ROWS_3D if len(shape) == 3 else [1]):
+                if rows > 1 and bx * by > 256:
+                    continue
+                for tile in TILES:
+                    for vec in VECS:
+                        if vec == 2 and not even:
+                            continue
+                        out.append({"bx": bx, "by": by, "tile": tile, "vec": vec, "K": K, "persistent": 0,
+                                    "rows": rows})
         for tile in PERSISTENT_TILES:
             for vec in VECS:
                 if vec == 2 and not even:
                     continue
-                out.append({"bx": 256, "by": 1, "tile": tile, "vec": vec, "K": K, "persistent": 1})
+                out.append({"bx": 256, "by": 1, "tile": tile, "vec": vec, "K": K, "persistent": 1, "rows": 1})
     return out
 
 
 def config_key(cfg):
-    return f"bx{cfg['bx']}_by{cfg['by']}_t{cfg['tile']}_v{cfg['vec']}_K{cfg['K']}_p{cfg['persistent']}"
+    key = f"bx{cfg['bx']}_by{cfg['by']}_t{cfg['tile']}_v{cfg['vec']}_K{cfg['K']}_p{cfg['persistent']}"
+    return key + (f"_r{cfg['rows']}" if cfg.get("rows", 1) != 1 else "")
+
+
+def launch_config(cfg):
+    """The library configuration of a candidate (order and march take the
+    library's defaults)."""
+    return jacc.config(bx=cfg["bx"], by=cfg["by"], tile=cfg["tile"], vec=cfg["vec"], persistent=cfg["persistent"],
+                       rows=cfg.get("rows", 1))
 
 
 def workgroups(shape, cfg):
@@ -72,11 +85,11 @@ def workgroups(shape, cfg):
         return math.ceil(cols / (bx * cfg["vec"])) * math.ceil(rows / (by * cfg["tile"]))
     nz, ny, nx = shape[0] - 2, shape[1] - 2, shape[2] - 2
     bx, by = (256, 1) if cfg["persistent"] else (cfg["bx"], cfg["by"])
-    return math.ceil(nx / (bx * cfg["vec"])) * math.ceil(ny / by) * math.ceil(nz / cfg["tile"])
+    return math.ceil(nx / (bx * cfg["vec"])) * math.ceil(ny / (by * cfg.get("rows", 1))) * math.ceil(nz / cfg["tile"])
 
 
 def features(shape, cfg):
-    """The cost model's input: 12 numbers describing the loop and the
+    """The cost model's input: 13 numbers describing the loop and the
     configuration (logs of sizes so that the scale generalises)."""
     dims = list(shape) + [1] * (3 - len(shape))
     cells = float(np.prod([max(1, d - 2) for d in shape]))
@@ -86,7 +99,7 @@ def features(shape, cfg):
         math.log2(cells),
         math.log2(cfg["bx"]), math.log2(cfg["by"]), math.log2(cfg["tile"]),
         float(cfg["vec"]), math.log2(cfg["K"]), float(cfg["persistent"]),
-        math.log2(workgroups(shape, cfg)),
+        math.log2(workgroups(shape, cfg)), math.log2(cfg.get("rows", 1)),
     ], dtype=np.float64)
 
 
@@ -150,7 +163,7 @@ class TimingDB:
 
 
 def _loop(ctx, u, v, cfg):
-    c = jacc.config(bx=cfg["bx"], by=cfg["by"], tile=cfg["tile"], vec=cfg["vec"], persistent=cfg["persistent"])
+    c = launch_config(cfg)
     if u.ndim == 2:
         ctx.jacobi2d(u, v, cfg=c)
     else:
