@@ -376,6 +376,36 @@ int jacc_trace_clear(jacc_ctx *ctx);
 /* Library version string (static). */
 const char *jacc_version(void);
 
+/* ---- adaptive duplicate-vs-partition choice (Sec. "Adaptive Utilization",
+ * Eq. 1-3) ------------------------------------------------------------------
+ * A per-loop policy record, host memory only, independent of any context.
+ * It starts in JACC_ADAPT_DUPLICATE (the whole loop on one device, no
+ * exchange).  jacc_adapt_observe feeds one execution of the loop in the
+ * current mode: time_kernel_s (seconds of the loop body; in partitioned mode
+ * of one partition), time_comm_s (seconds of the exchange; 0 in duplicate
+ * mode) and write_bytes (bytes the loop writes, > 0), and returns the mode
+ * for the next execution.
+ *   duplicate: the first observation is a warm-up and ignored; later ones
+ *     add time/WriteSize to eff_dup (mean seconds per byte) and count Eq. 1,
+ *     t_k > t_k/n + WriteSize/peak; at five the mode becomes PARTITION.
+ *   partition: Eq. 2, t_k + t_c > n*t_k, and Eq. 3, t_k + t_c > eff_dup *
+ *     WriteSize, are counted; when either has held five times and the mean,
+ *     over the violating executions, of (t_k + t_c) minus the smaller right
+ *     side is positive, the mode becomes DUPLICATE_FINAL and stays there.
+ * n_parts >= 1 is the partition (device) count, peak_bytes_per_s > 0 the
+ * bandwidth of one link between partitions.  Returns JACC_ERR_INVALID on bad
+ * arguments, JACC_ERR_ALLOC if the record cannot be allocated.  The record
+ * is not thread-safe. */
+typedef struct jacc_adapt jacc_adapt;
+enum { JACC_ADAPT_DUPLICATE = 0, JACC_ADAPT_PARTITION = 1, JACC_ADAPT_DUPLICATE_FINAL = 2 };
+int jacc_adapt_create(jacc_adapt **out, int n_parts, double peak_bytes_per_s);
+int jacc_adapt_destroy(jacc_adapt *a);
+int jacc_adapt_observe(jacc_adapt *a, double time_kernel_s, double time_comm_s, double write_bytes, int *mode);
+/* Current mode, eff_dup (0 before any profiled duplicate run) and counts[5]
+ * = {profiled duplicate runs, Eq. 1 hits, Eq. 2 hits, Eq. 3 hits, violating
+ * partitioned runs}; any output pointer may be NULL. */
+int jacc_adapt_state(const jacc_adapt *a, int *mode, double *eff_dup, long long *counts);
+
 #ifdef __cplusplus
 }
 #endif

@@ -125,6 +125,11 @@ def lib():
     L.jacc_trace_len.argtypes = [vp]
     L.jacc_trace_get.argtypes = [vp, i32, ctypes.POINTER(TraceOp)]
     L.jacc_trace_clear.argtypes = [vp]
+    d = ctypes.c_double
+    L.jacc_adapt_create.argtypes = [ctypes.POINTER(vp), i32, d]
+    L.jacc_adapt_destroy.argtypes = [vp]
+    L.jacc_adapt_observe.argtypes = [vp, d, d, d, ctypes.POINTER(i32)]
+    L.jacc_adapt_state.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)]
     _lib = L
     return L
 
@@ -484,3 +489,47 @@ class Model:
         self.c._check(self.L.jacc_model_train(self.m, _fptr(X), _fptr(y), X.shape[0], epochs, batch,
                                               ctypes.c_float(lr), ctypes.c_uint64(seed), _fptr(losses)))
         return losses[:epochs]
+
+
+ADAPT_DUPLICATE, ADAPT_PARTITION, ADAPT_DUPLICATE_FINAL = 0, 1, 2
+
+
+class Adaptive:
+    """Duplicate-vs-partition policy of one loop nest (jacc_adapt_*)."""
+
+    def __init__(self, n_parts, peak_bytes_per_s):
+        self.L = lib()
+        h = ctypes.c_void_p()
+        rc = self.L.jacc_adapt_create(ctypes.byref(h), int(n_parts), float(peak_bytes_per_s))
+        if rc != OK:
+            raise JaccError(rc, "jacc_adapt_create")
+        self.h = h
+
+    def observe(self, time_kernel_s, time_comm_s, write_bytes, raw=False):
+        m = ctypes.c_int(-1)
+        rc = self.L.jacc_adapt_observe(self.h, float(time_kernel_s), float(time_comm_s), float(write_bytes),
+                                       ctypes.byref(m))
+        if raw:
+            return rc
+        if rc != OK:
+            raise JaccError(rc, "jacc_adapt_observe")
+        return m.value
+
+    def state(self):
+        m = ctypes.c_int(-1)
+        e = ctypes.c_double(0.0)
+        cnt = (ctypes.c_longlong * 5)()
+        self.L.jacc_adapt_state(self.h, ctypes.byref(m), ctypes.byref(e), cnt)
+        return {"mode": m.value, "eff_dup": e.value, "n_dup": cnt[0], "eq1": cnt[1], "eq2": cnt[2], "eq3": cnt[3],
+                "violations": cnt[4]}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.jacc_adapt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -66,6 +66,18 @@ def test_jacobi_8192_1000_steps_k8_equals_k1_and_sampled_oracle():
         assert np.array_equal(out8[r0:r0 + 8, c0:c0 + 8], ref)
 
 
+def test_jacobi_8192_1000_steps_full_oracle_hash_k4():
+    say("jacobi 8192^2 T=1000 K=4 against the full oracle run (about 45 s on one host core)")
+    import hashlib
+    u0 = inputs.jacobi_grid(8192, 8192, seed=1)
+    T = 1000
+    out4 = run_jacobi(u0, T, 4)
+    ref = oracle.jacobi2d(u0, T)
+    if hashlib.sha256(out4.tobytes()).digest() != hashlib.sha256(ref.tobytes()).digest():
+        bad = np.argwhere(out4 != ref)
+        raise AssertionError(f"{len(bad)} cells differ, first at {tuple(bad[0])}")
+
+
 # ------------------------------------------------------------------ Heat
 def _rel_close(a, b, tol=1e-13):
     return np.all(np.abs(a - b) <= tol * np.abs(b))
