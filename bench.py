@@ -227,6 +227,11 @@ def extra_workloads(jacc, torch, inputs):
         dt = timed(sp, 10)
         out[f"spmv_2^22_K{K}"] = {"gbps": round(alg / dt / 1e9, 1), "ms": round(dt * 1e3, 4), "nnz": int(col.size)}
         c.close()
+    del rp, col, val, xv, y
+    # 96 independent Jacobi grids (sides 64..1024), 2 sweeps each per pass:
+    # eager on 1, 4 and 16 streams (runtime-chosen), and as one graph
+    from paper_2110_14340_amd import experiment
+    out["independent_loops_ms_per_pass"], _ = experiment.independent_loops()
     return out
 
 

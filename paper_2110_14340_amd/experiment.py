@@ -134,3 +134,62 @@ def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=600, tune_reps=5, graph
         "seconds": round(time.perf_counter() - t_start, 1),
     }
     return result, (test_shapes, datas, out_m)
+
+
+def independent_loops(n_loops=96, streams=(1, 4, 16), steps=2, seed=11, reps=5, keep_outputs=False):
+    """Many independent small Jacobi sweeps issued eagerly, each array held
+    whole (one partition), on contexts with 1, 4 and 16 streams: the runtime
+    places each loop on a stream by its inputs' last writer or, for
+    independent loops, the least recently used stream, and orders dependent
+    loops by events (automated asynchronous execution of independent loop
+    nests).  The same loop sequence captured as one graph is timed beside
+    them.  Returns ({variant: ms per pass}, outputs or None); a pass is
+    `steps` ping-pong sweeps of every grid (sides log-uniform in [64, 1024])."""
+    import torch
+    r = inputs.rng(seed)
+    shapes = [tuple(int(v) for v in s) for s in inputs.log_uniform_int(r, 64, 1024, (n_loops, 2))]
+    out = {}
+    outputs = None
+
+    def make(ctx):
+        grids = []
+        for i, sh in enumerate(shapes):
+            a = inputs.jacobi_grid(*sh, seed=seed + i)
+            b = a.copy()
+            ctx.enter(a, halo=(1, 1), K=1)
+            ctx.enter(b, halo=(1, 1), K=1)
+            grids.append((a, b))
+        return grids
+
+    def one_pass(ctx, grids):
+        for t in range(steps):
+            for a, b in grids:
+                (ctx.jacobi2d(a, b) if t % 2 == 0 else ctx.jacobi2d(b, a))
+
+    for ns in streams:
+        ctx = jacc.Context(ns)
+        try:
+            grids = make(ctx)
+            one_pass(ctx, grids)
+            ctx.wait()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                one_pass(ctx, grids)
+            ctx.wait()
+            torch.cuda.synchronize()
+            out[f"eager_{ns}_streams"] = round((time.perf_counter() - t0) / reps * 1e3, 4)
+            if keep_outputs and ns == max(streams):
+                outputs = []
+                for a, b in grids:
+                    res = a if steps % 2 == 0 else b
+                    ctx.update(res, jacc.UPDATE_HOST)
+                    outputs.append(res.copy())
+            if ns == max(streams):
+                ctx.batch_begin()
+                one_pass(ctx, grids)
+                g = ctx.batch_end()
+                out["graph"] = round(float(np.median(ctx.batch_time(g, warmup=2, reps=reps))), 4)
+        finally:
+            ctx.close()
+    return out, (shapes, outputs)

@@ -121,3 +121,32 @@ def test_heat_512_100_steps_k4():
         ref = oracle.heat3d_window(u0, T, 0.1, (z0, z0 + 4), (y0, y0 + 4), (x0, x0 + 8))
         assert np.array_equal(out4[z0:z0 + 4, y0:y0 + 4, x0:x0 + 8], ref)
     assert np.all(np.diff(res4) <= 0)  # the explicit scheme is a contraction
+
+
+# ------------------------------------------------------------------ degenerate launches
+def test_empty_iteration_ranges_change_nothing():
+    say("empty iteration ranges (Jacobi rows, heat planes, sum)")
+    from gpu_util import context
+    u = inputs.jacobi_grid(40, 66, seed=5)
+    v = np.full_like(u, -3.0)
+    h = inputs.heat_field(12, 10, 34, seed=6)
+    g = np.full_like(h, -5.0)
+    with context(4) as c:
+        for arr in (u, v, h, g):
+            c.enter(arr, halo=(1, 1))
+        jargs = [(u, jacc.READ, -1, 1, 0), (v, jacc.WRITE, 0, 0, 0)]
+        c.loop(jacc.JACOBI2D, jacc.bounds((7, 7), (1, 65)), jargs)
+        c.loop(jacc.JACOBI2D, jacc.bounds((1, 39), (5, 5)), jargs)
+        hargs = [(h, jacc.READ, -1, 1, 0), (g, jacc.WRITE, 0, 0, 0)]
+        c.loop(jacc.HEAT3D, jacc.bounds((1, 11), (4, 4), (1, 33)), hargs, scalars=(0.1,), slot=3)
+        assert c.reductions(3, 1)[0] == 0.0
+        assert c.sum(u, rows=(9, 9)) == 0.0
+        c.exit(v)
+        c.exit(g)
+    assert np.all(v == -3.0) and np.all(g == -5.0)
+
+
+def test_more_partitions_than_interior_rows():
+    say("jacobi 5x70 with K=5 (partitions without interior rows)")
+    u0 = inputs.jacobi_grid(5, 70, seed=8)
+    assert np.array_equal(run_jacobi(u0, 4, 5), oracle.jacobi2d(u0, 4))
