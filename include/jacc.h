@@ -135,7 +135,8 @@ typedef struct {
 
 /* Launch configuration.  Never changes the arithmetic of any loop body.
  *   bx, by     workgroup shape in threads (bx a multiple of 64; bx*by <= 1024)
- *   tile       rows (2-D) or planes (3-D) each thread marches through
+ *   tile       rows (2-D) or planes (3-D) each thread marches through;
+ *              GEMM: k-slab depth staged through LDS, 16 or 32
  *   vec        1 or 2 consecutive FP64 elements per lane (2 needs an even row
  *              length)
  *   persistent 1 = run the loop inside the batched persistent kernel
@@ -188,8 +189,12 @@ enum {
     JACC_INIT_DRYRUN = 1u << 0, /* plan and trace only: no HIP call, fake device addresses */
     JACC_INIT_TRACE = 1u << 1,  /* record every planned operation (see jacc_trace_get) */
     JACC_INIT_SERIALIZE = 1u << 2, /* one stream for every partition, device sync after each op */
-    JACC_INIT_LAZY = 1u << 3       /* halo rows are pulled before each read (default: a stencil
+    JACC_INIT_LAZY = 1u << 3,      /* halo rows are pulled before each read (default: a stencil
                                       partition also writes the output rows other slabs hold) */
+    JACC_INIT_SPLIT = 1u << 4      /* stencil loops without a reduction: each partition first runs
+                                      the rows that read only its own block, then its edge rows
+                                      (which wait for the neighbours), so no partition's bulk
+                                      waits on another stream */
 };
 
 /* Create a context with K partitions (1 <= K <= 64).  streams: K hipStream_t

@@ -41,7 +41,7 @@ Cfg default_config(int kind, const Launch &L, Cfg c) {
         default:
             if (!c.bx) c.bx = 256;
             if (!c.by) c.by = 1;
-            if (!c.tile) c.tile = 1;
+            if (!c.tile) c.tile = kind == JACC_LOOP_GEMM ? 16 : 1;  // GEMM: 16-deep slabs measured faster
             if (!c.vec) c.vec = 1;
             if (!c.order) c.order = 1;
             if (!c.march) c.march = 1;
@@ -68,8 +68,9 @@ int check_config(const Launch &L) {
             if (c.rows != 1 && c.rows != 2 && c.rows != 4 && c.rows != 8) return 1;
             if (c.rows != 1 && c.bx * c.by > 256) return 1;  // multi-row waves: workgroups of at most 256
             return 0;
-        case JACC_LOOP_SUM:
         case JACC_LOOP_GEMM:
+            return (c.tile == 16 || c.tile == 32) ? 0 : 1;  // k-slab depth; other fields are ignored
+        case JACC_LOOP_SUM:
         case JACC_LOOP_SPMV_CSR:
         case JACC_LOOP_SCATTER_SQ:
             return 0;  // fixed internal configurations; fields are ignored

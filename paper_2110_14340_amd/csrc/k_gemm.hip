@@ -3,11 +3,11 @@
 //
 // Workgroup: 256 threads (4 waves) computing a 128x128 tile of C; each wave
 // owns a 64x64 sub-tile as 4x4 MFMA blocks of 16x16 (64 FP64 accumulators
-// per lane).  The k dimension is walked in slabs of 16 in increasing order
-// (no split-k, so every element's accumulation order is the same for every
-// partition count), staged through LDS with double buffering: the next
-// slab's global loads are in flight while the current slab feeds the
-// matrix cores.
+// per lane).  The k dimension is walked in slabs of 16 or 32 in increasing
+// order (no split-k, so every element's accumulation order is the same for
+// every partition count and slab depth), staged through LDS: the next
+// slab's global loads are in flight in registers while the current slab
+// feeds the matrix cores.
 //
 // MFMA operand layout (16x16x4, FP64, wave64): lane l supplies A[l%16][l/16]
 // and B[l/16][l%16]; accumulator element r of lane l is D[4*r + l/16][l%16]
@@ -19,9 +19,8 @@ namespace jk {
 
 namespace {
 
-constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int BM = 128, BN = 128;
 constexpr int kGemmThreads = 256;
-constexpr int SA = BK + 2;   // LDS row stride of A (doubles): conflict-free fragment reads
 constexpr int SB = BN + 16;  // LDS row stride of B (doubles)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -43,12 +42,20 @@ __device__ __forceinline__ void gemm_tile(int64_t tiles_m, int64_t tiles_n, int6
     *tj = in_group / rows;
 }
 
+// BK = 16: two LDS buffers, one barrier per k-slab.  BK = 32: one LDS
+// buffer (the register staging holds the next slab), two barriers per slab
+// of twice the work, so the next slab's loads have longer to arrive.
+template <int BK>
 __global__ void __launch_bounds__(kGemmThreads)
 gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *__restrict__ C, int64_t m_lo,
             int64_t m_hi, int64_t N, int64_t L, int64_t lda, int64_t ldb, int64_t ldc, int64_t n_lo, int64_t n_hi,
             int64_t tiles_m, int64_t tiles_n) {
-    __shared__ __align__(16) double As[2][BM * SA];
-    __shared__ __align__(16) double Bs[2][BK * SB];
+    constexpr int NBUF = BK == 16 ? 2 : 1;
+    constexpr int SA = BK + 2;           // LDS row stride of A (doubles): conflict-free fragment reads
+    constexpr int U = BK / 4;            // double pairs per thread per operand and slab
+    constexpr int KP = BK / 2;           // A: k pairs per row
+    __shared__ __align__(16) double As[NBUF][BM * SA];
+    __shared__ __align__(16) double Bs[NBUF][BK * SB];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -59,15 +66,16 @@ gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *
     const int64_t col0 = n_lo + tj * BN;
     const bool full_mn = row0 + BM <= m_hi && col0 + BN <= n_hi && (lda & 1) == 0 && (ldb & 1) == 0;
 
-    // global -> register staging: A tile 128x16 and B tile 16x128 are 1024
-    // double pairs each, 4 per thread (16-byte loads for full tiles)
-    dvec2 ra[4], rb[4];
+    // global -> register staging: the A tile (128 x BK) and the B tile
+    // (BK x 128) are 64*BK double pairs each, U per thread (16-byte loads for
+    // full tiles)
+    dvec2 ra[U], rb[U];
     auto load_tiles = [&](int64_t k0) {
         const bool full = full_mn && k0 + BK <= L;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int idx = tid + u * kGemmThreads;
-            const int r = idx >> 3, kp = (idx & 7) * 2;     // A: row, k pair
+            const int r = idx / KP, kp = (idx % KP) * 2;    // A: row, k pair
             const int kr = idx >> 6, cp = (idx & 63) * 2;   // B: k, column pair
             if (full) {
                 ra[u] = *reinterpret_cast<const dvec2 *>(A + (row0 + r) * lda + k0 + kp);
@@ -84,9 +92,9 @@ gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *
     };
     auto store_tiles = [&](int buf) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int idx = tid + u * kGemmThreads;
-            const int r = idx >> 3, kp = (idx & 7) * 2;
+            const int r = idx / KP, kp = (idx % KP) * 2;
             *reinterpret_cast<dvec2 *>(&As[buf][r * SA + kp]) = ra[u];
             const int kr = idx >> 6, cp = (idx & 63) * 2;
             *reinterpret_cast<dvec2 *>(&Bs[buf][kr * SB + cp]) = rb[u];
@@ -104,7 +112,7 @@ gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *
     store_tiles(0);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
+        const int buf = NBUF == 2 ? (kt & 1) : 0;
         if (kt + 1 < nk) load_tiles((int64_t)(kt + 1) * BK);
         const double *as = As[buf];
         const double *bs = Bs[buf];
@@ -122,7 +130,8 @@ gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *
                 for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         if (kt + 1 < nk) {
-            store_tiles(buf ^ 1);
+            if (NBUF == 1) __syncthreads();  // every wave is done reading the single buffer
+            store_tiles(NBUF == 2 ? (buf ^ 1) : 0);
         }
         __syncthreads();
     }
@@ -151,9 +160,15 @@ hipError_t launch_gemm(const Launch &L, hipStream_t s) {
     const int64_t Lk = L.a[0].row_elems;
     const int64_t N = L.a[2].row_elems;
     const int64_t tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
-    hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)(tiles_m * tiles_n)), dim3(kGemmThreads), 0, s,
-                       (const double *)L.a[0].ptr, (const double *)L.a[1].ptr, (double *)L.a[2].ptr, L.lo[0], L.hi[0],
-                       N, Lk, Lk, L.a[1].row_elems, N, L.lo[1], L.hi[1], tiles_m, tiles_n);
+    // configuration field `tile` selects the k-slab depth (16 or 32)
+    if (L.cfg.tile == 16)
+        hipLaunchKernelGGL(gemm_kernel<16>, dim3((unsigned)(tiles_m * tiles_n)), dim3(kGemmThreads), 0, s,
+                           (const double *)L.a[0].ptr, (const double *)L.a[1].ptr, (double *)L.a[2].ptr, L.lo[0],
+                           L.hi[0], N, Lk, Lk, L.a[1].row_elems, N, L.lo[1], L.hi[1], tiles_m, tiles_n);
+    else
+        hipLaunchKernelGGL(gemm_kernel<32>, dim3((unsigned)(tiles_m * tiles_n)), dim3(kGemmThreads), 0, s,
+                           (const double *)L.a[0].ptr, (const double *)L.a[1].ptr, (double *)L.a[2].ptr, L.lo[0],
+                           L.hi[0], N, Lk, Lk, L.a[1].row_elems, N, L.lo[1], L.hi[1], tiles_m, tiles_n);
     return hipGetLastError();
 }
 

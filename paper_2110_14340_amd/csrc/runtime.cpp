@@ -252,6 +252,7 @@ struct jacc_ctx {
     unsigned flags = 0;
     bool dry = false, tracing = false, serialize = false;
     bool lazy = false;       // pull halo rows before reads instead of mirroring them at writes
+    bool split = false;      // stencil partitions: own-block rows first, edge rows after
     bool plan_only = false;  // planning pass without device work (batch replay check)
     jacc_allocator alloc{};
     bool use_hipmalloc = true;
@@ -961,8 +962,50 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
         !c->lazy && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) && !P->whole && K > 1;
     std::vector<int> order;       // partitions that reduce, in partition order
     std::vector<int> red_streams;  // their streams
-    for (int p = 0; p < K; ++p) {
-        const PartPlan &pp = plan[p];
+    // pieces: one per partition, or (split mode) first every partition's
+    // rows whose reads stay inside its own block, then the edge rows that
+    // read a neighbour's rows
+    struct Piece {
+        int p;
+        PartPlan pp;
+    };
+    std::vector<Piece> pieces;
+    const bool split = c->split && !want_red && !persistent && !one_stream && K > 1 &&
+                       (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D);
+    if (split) {
+        int e = 0;  // halo depth of the reads along dim 0
+        for (int i = 0; i < nargs; ++i)
+            if ((args[i].mode & JACC_READ) && !args[i].whole)
+                e = std::max(e, std::max(-args[i].off_lo, args[i].off_hi));
+        auto piece = [&](int p, Range it) {
+            Piece pc{p, PartPlan{}};
+            pc.pp.iters = it;
+            pc.pp.rng.resize(nargs);
+            for (int i = 0; i < nargs; ++i)
+                pc.pp.rng[i] = args[i].whole ? Range{0, arr[i]->E}
+                                             : isect({it.lo + args[i].off_lo, it.hi + args[i].off_hi}, {0, arr[i]->E});
+            return pc;
+        };
+        std::vector<Piece> edges;
+        for (int p = 0; p < K; ++p) {
+            const Range it = plan[p].iters;
+            if (it.empty()) continue;
+            const int64_t top = p > 0 ? e : 0, bot = p < K - 1 ? e : 0;
+            if (it.hi - it.lo < top + bot + 8) {
+                edges.push_back(piece(p, it));  // too short to split: all of it waits
+                continue;
+            }
+            pieces.push_back(piece(p, {it.lo + top, it.hi - bot}));
+            if (top) edges.push_back(piece(p, {it.lo, it.lo + top}));
+            if (bot) edges.push_back(piece(p, {it.hi - bot, it.hi}));
+        }
+        pieces.insert(pieces.end(), edges.begin(), edges.end());
+    } else {
+        for (int p = 0; p < K; ++p) pieces.push_back({p, plan[p]});
+    }
+    for (const Piece &piece_ : pieces) {
+        const int p = piece_.p;
+        const PartPlan &pp = piece_.pp;
         if (pp.iters.empty()) continue;
         const int s = stream_for(p);
         std::vector<std::pair<int, Range>> mirrors;
@@ -1200,6 +1243,7 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
         c->tracing = (flags & JACC_INIT_TRACE) != 0;
         c->serialize = (flags & JACC_INIT_SERIALIZE) != 0;
         c->lazy = (flags & JACC_INIT_LAZY) != 0;
+        c->split = (flags & JACC_INIT_SPLIT) != 0;
         if (alloc) {
             c->alloc = *alloc;
             c->use_hipmalloc = false;

@@ -23,7 +23,7 @@ COPYOUT, DELETE = 1, 2
 UPDATE_HOST, UPDATE_DEVICE = 1, 2
 READ, WRITE, READWRITE, FILTERED = 1, 2, 3, 4
 JACOBI2D, HEAT3D, SUM, GEMM, SPMV_CSR, SCATTER_SQ = 1, 2, 3, 4, 5, 6
-INIT_DRYRUN, INIT_TRACE, INIT_SERIALIZE, INIT_LAZY = 1, 2, 4, 8
+INIT_DRYRUN, INIT_TRACE, INIT_SERIALIZE, INIT_LAZY, INIT_SPLIT = 1, 2, 4, 8, 16
 OP_NAMES = {1: "ALLOC", 2: "FREE", 3: "H2D", 4: "D2H", 5: "COPY", 6: "KERNEL", 7: "RECORD", 8: "WAIT",
             9: "SYNC", 10: "COMBINE", 11: "ACCESS", 12: "JOIN"}
 STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOT_PRESENT", -3: "ALREADY_PRESENT", -4: "RANGE", -5: "ALLOC",
@@ -307,9 +307,9 @@ class Context:
         return self.loop(SUM, b, [(x, READ, 0, 0, 0)], scalars=(1.0 if squares else 0.0,), slot=slot,
                          sync=sync, raw=raw)
 
-    def gemm(self, A, B, C, raw=False):
+    def gemm(self, A, B, C, cfg=None, raw=False):
         b = bounds((0, C.shape[0]), (0, C.shape[1]))
-        return self.loop(GEMM, b, [(A, READ, 0, 0, 0), (B, READ, 0, 0, 1), (C, WRITE, 0, 0, 0)], raw=raw)
+        return self.loop(GEMM, b, [(A, READ, 0, 0, 0), (B, READ, 0, 0, 1), (C, WRITE, 0, 0, 0)], cfg=cfg, raw=raw)
 
     def spmv(self, rp, col, val, x, y, raw=False):
         b = bounds((0, y.shape[0]))

@@ -54,13 +54,13 @@ def test_sum_integer_exact_and_deferred_slots():
 
 
 # ------------------------------------------------------------------ GEMM
-def _gemm_dev(A, B, K):
+def _gemm_dev(A, B, K, slab=0):
     C = np.zeros((A.shape[0], B.shape[1]))
     with context(K) as c:
         c.enter(A)
         c.enter(B, whole=True)
         c.enter(C, clause=jacc.CREATE)
-        c.gemm(A, B, C)
+        c.gemm(A, B, C, cfg=jacc.config(tile=slab) if slab else None)
         c.exit(C, jacc.COPYOUT)
     return C
 
@@ -71,10 +71,11 @@ def test_gemm_small_frobenius_and_integer_exact(M, N, L, K):
     say(f"gemm {M}x{N}x{L} K={K}")
     A, B = inputs.gemm_inputs(M, N, L, seed=3)
     ref = oracle.gemm(A, B)
-    C = _gemm_dev(A, B, K)
-    assert np.linalg.norm(C - ref) <= 1e-12 * np.linalg.norm(A) * np.linalg.norm(B)
     Ai, Bi = inputs.gemm_inputs(M, N, L, seed=4, integer=True)
-    assert np.array_equal(_gemm_dev(Ai, Bi, K), oracle.gemm(Ai, Bi))
+    for slab in (16, 32):
+        C = _gemm_dev(A, B, K, slab)
+        assert np.linalg.norm(C - ref) <= 1e-12 * np.linalg.norm(A) * np.linalg.norm(B)
+        assert np.array_equal(_gemm_dev(Ai, Bi, K, slab), oracle.gemm(Ai, Bi))
 
 
 def test_gemm_4096_sampled_rows():
@@ -84,6 +85,7 @@ def test_gemm_4096_sampled_rows():
     C1 = _gemm_dev(A, B, 1)
     C4 = _gemm_dev(A, B, 4)
     assert np.array_equal(C1, C4)  # no split-k: partitioning never changes an element's sum order
+    assert np.array_equal(C1, _gemm_dev(A, B, 1, 16))  # nor does the k-slab depth
     # one row of every residue mod 16 (the matrix-core output interleaves
     # rows across lane groups), block edges and the last row
     rows = sorted(set([1024 + r for r in range(16)] + [0, 1, 4, 2047, 2050, 4095]))

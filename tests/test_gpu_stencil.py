@@ -150,3 +150,10 @@ def test_more_partitions_than_interior_rows():
     say("jacobi 5x70 with K=5 (partitions without interior rows)")
     u0 = inputs.jacobi_grid(5, 70, seed=8)
     assert np.array_equal(run_jacobi(u0, 4, 5), oracle.jacobi2d(u0, 4))
+
+
+@pytest.mark.parametrize("shape,K,steps", [((512, 512), 4, 100), ((1030, 258), 8, 7), ((40, 66), 3, 5)])
+def test_jacobi_split_mode_bit_exact(shape, K, steps):
+    say(f"jacobi split mode {shape} K={K} T={steps}")
+    u0 = inputs.jacobi_grid(*shape, seed=12)
+    assert np.array_equal(run_jacobi(u0, steps, K, ctx_flags=jacc.INIT_SPLIT), oracle.jacobi2d(u0, steps))

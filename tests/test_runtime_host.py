@@ -465,3 +465,33 @@ def test_filtered_scatter_runs_whole_range_and_writes_owner_blocks():
     assert rc == jacc.ERR_INVALID
     c.exit(out)
     assert race_check(c.trace()) == []
+
+
+@pytest.mark.parametrize("K,E,lazy", [(8, 64, False), (4, 40, True), (3, 12, False), (5, 30, True)])
+def test_split_mode_pieces_cover_partitions_race_free(K, E, lazy):
+    flags = (LAZY if lazy else DRY) | jacc.INIT_SPLIT
+    c = jacc.Context(K, flags=flags)
+    a = np.zeros((E, 16))
+    b = np.zeros((E, 16))
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    full = c.trace()
+    src, dst = a, b
+    for step in range(4):
+        tr = _loop_trace(c, lambda: c.jacobi2d(src, dst))
+        full += tr
+        kernels = [t for t in tr if t["op"] == "KERNEL"]
+        # the pieces of each partition tile its iteration sub-range exactly
+        for p in range(K):
+            I = P.iter_range(1, E - 1, P.block(E, K, p))
+            rows = sorted(r for t in kernels if t["dst"] == p for r in range(t["lo"], t["hi"]))
+            assert rows == sorted(I)
+        # every partition's first piece (its own-block rows) is issued before any edge piece
+        firsts = {}
+        for i, t in enumerate(kernels):
+            firsts.setdefault(t["dst"], i)
+        assert sorted(firsts.values()) == list(range(K))
+        src, dst = dst, src
+    assert race_check(full) == []
+    assert freshness_check(full) == []
+    c.close()
