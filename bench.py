@@ -52,13 +52,13 @@ def counted_traffic():
     return int(rec["traffic_bytes_per_launch"]) if rec.get("source_sha1") == h else None
 
 
-def run_jacobi(ctx_mod, torch, u0, K, steps, warmup, cfg=None):
+def run_jacobi(ctx_mod, torch, u0, K, steps, warmup, cfg=None, flags=0):
     """Times `steps` partitioned Jacobi sweeps after `warmup` untimed ones.
-    Returns (seconds, stream-0 event seconds, final grid)."""
+    Returns (seconds, stream-0 event seconds)."""
     jacc = ctx_mod
     a = u0.copy()
     b = u0.copy()
-    c = jacc.Context(K)
+    c = jacc.Context(K, flags=flags)
     c.enter(a, halo=(1, 1))
     c.enter(b, halo=(1, 1))
     src, dst = a, b
@@ -274,6 +274,18 @@ def main():
                     "gbps": round(step_bytes * args.steps / wall / 1e9, 1)}
         if K == 1:
             ev_k1 = ev
+    # the other coherence and issue modes, at the partitioned K's: halo rows
+    # pulled by copies before each read (lazy) instead of written through by
+    # the producing kernels, and own-block rows issued before the edge rows
+    modes = {}
+    for K in ks:
+        if K == 1:
+            continue
+        for name, fl in (("lazy_pull", jacc.INIT_LAZY), ("split", jacc.INIT_SPLIT)):
+            log(f"jacobi K={K} {name}")
+            wall, _ = run_jacobi(jacc, torch, u0, K, args.steps, args.warmup, flags=fl)
+            modes.setdefault(name, {})[str(K)] = {"ms_per_step": round(wall / args.steps * 1e3, 5),
+                                                  "gbps": round(step_bytes * args.steps / wall / 1e9, 1)}
     graph = {}
     for K in ks:
         if K == 1:
@@ -304,6 +316,7 @@ def main():
         "frac_hbm_peak": round(value / HBM_PEAK_GBS, 4),
         "per_k": {str(k): v for k, v in per_k.items()},
         "per_k_graph": {str(k): v for k, v in graph.items()},
+        "per_k_modes": modes,
     }
     if 1 in per_k and main_k != 1:
         result["k_overhead"] = round(per_k[main_k]["ms_per_step"] / per_k[1]["ms_per_step"] - 1.0, 4)

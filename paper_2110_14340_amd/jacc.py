@@ -218,6 +218,7 @@ class Context:
         if st != OK:
             raise JaccError(st, "jacc_init failed: " + self.L.jacc_last_error(None).decode())
         self.arrays = {}
+        self._calls = {}
 
     # -- helpers ---------------------------------------------------------
     def _check(self, st):
@@ -231,7 +232,7 @@ class Context:
 
     @staticmethod
     def _ptr(a):
-        return a.ctypes.data
+        return a.__array_interface__["data"][0]
 
     def close(self):
         if self.ctx:
@@ -290,17 +291,40 @@ class Context:
         self._check(st)
         return out.value if sync else None
 
+    def _stencil_call(self, kind, u_in, u_out, pairs, scalars, slot, sync, cfg, raw):
+        """Marshalled arguments of a stencil call, cached per (arrays, box)
+        so that a time-stepping loop pays the ctypes construction once."""
+        key = (kind, self._ptr(u_in), self._ptr(u_out), pairs)
+        ent = self._calls.get(key)
+        if ent is None:
+            if len(self._calls) > 512:
+                self._calls.clear()
+            A = (Arg * 2)()
+            A[0] = Arg(key[1], READ, -1, 1, 0)
+            A[1] = Arg(key[2], WRITE, 0, 0, 0)
+            b = bounds(*pairs)
+            ent = self._calls[key] = (A, b, ctypes.byref(b))
+        A, _, bref = ent
+        S = (ctypes.c_double * max(1, len(scalars)))(*scalars)
+        out = ctypes.c_double(0.0) if sync else None
+        st = self.L.jacc_parallel_loop(self.ctx, kind, bref, 2, A, S, len(scalars), slot,
+                                       ctypes.byref(out) if sync else None,
+                                       ctypes.byref(cfg) if cfg is not None else None)
+        if raw:
+            return st
+        self._check(st)
+        return out.value if sync else None
+
     # convenience wrappers for the loop kinds (declared access ranges)
     def jacobi2d(self, u_in, u_out, rows=None, cols=None, cfg=None, raw=False):
         ny, nx = u_in.shape
-        b = bounds(rows or (1, ny - 1), cols or (1, nx - 1))
-        return self.loop(JACOBI2D, b, [(u_in, READ, -1, 1, 0), (u_out, WRITE, 0, 0, 0)], cfg=cfg, raw=raw)
+        pairs = (tuple(rows or (1, ny - 1)), tuple(cols or (1, nx - 1)))
+        return self._stencil_call(JACOBI2D, u_in, u_out, pairs, (), -1, False, cfg, raw)
 
     def heat3d(self, u_in, u_out, alpha, slot=-1, sync=False, cfg=None, raw=False):
         nz, ny, nx = u_in.shape
-        b = bounds((1, nz - 1), (1, ny - 1), (1, nx - 1))
-        return self.loop(HEAT3D, b, [(u_in, READ, -1, 1, 0), (u_out, WRITE, 0, 0, 0)], scalars=(alpha,),
-                         slot=slot, sync=sync, cfg=cfg, raw=raw)
+        return self._stencil_call(HEAT3D, u_in, u_out, ((1, nz - 1), (1, ny - 1), (1, nx - 1)), (alpha,), slot, sync,
+                                  cfg, raw)
 
     def sum(self, x, squares=False, slot=-1, sync=True, rows=None, raw=False):
         b = bounds(rows or (0, x.shape[0]))
