@@ -276,12 +276,14 @@ def main():
             ev_k1 = ev
     # the other coherence and issue modes, at the partitioned K's: halo rows
     # pulled by copies before each read (lazy) instead of written through by
-    # the producing kernels, and own-block rows issued before the edge rows
+    # the producing kernels; one launch per partition (the default splits
+    # 2-4 partitions into own-block rows first and edge rows after); split
+    # forced at every K
     modes = {}
     for K in ks:
         if K == 1:
             continue
-        for name, fl in (("lazy_pull", jacc.INIT_LAZY), ("split", jacc.INIT_SPLIT)):
+        for name, fl in (("lazy_pull", jacc.INIT_LAZY), ("no_split", jacc.INIT_NO_SPLIT), ("split", jacc.INIT_SPLIT)):
             log(f"jacobi K={K} {name}")
             wall, _ = run_jacobi(jacc, torch, u0, K, args.steps, args.warmup, flags=fl)
             modes.setdefault(name, {})[str(K)] = {"ms_per_step": round(wall / args.steps * 1e3, 5),

@@ -191,10 +191,12 @@ enum {
     JACC_INIT_SERIALIZE = 1u << 2, /* one stream for every partition, device sync after each op */
     JACC_INIT_LAZY = 1u << 3,      /* halo rows are pulled before each read (default: a stencil
                                       partition also writes the output rows other slabs hold) */
-    JACC_INIT_SPLIT = 1u << 4      /* stencil loops without a reduction: each partition first runs
+    JACC_INIT_SPLIT = 1u << 4,     /* stencil loops without a reduction: each partition first runs
                                       the rows that read only its own block, then its edge rows
                                       (which wait for the neighbours), so no partition's bulk
-                                      waits on another stream */
+                                      waits on another stream; default for 2 to 4 partitions,
+                                      this flag asks for it at any partition count */
+    JACC_INIT_NO_SPLIT = 1u << 5   /* never split (one launch per partition) */
 };
 
 /* Create a context with K partitions (1 <= K <= 64).  streams: K hipStream_t

@@ -43,14 +43,31 @@ sum_kernel(const double *__restrict__ x, int64_t begin, int64_t n, double *__res
     if (threadIdx.x == 0) wg_partials[blockIdx.x] = s;
 }
 
-// out = ordered sum of p[0..n): thread t adds p[t], p[t+256], ... then the
+// out = ordered sum of p[0..n): thread t keeps 8 running sums, sum u taking
+// p[t + (8j+u)*1024] for j = 0, 1, ... (eight independent loads in flight
+// per step instead of one dependent chain), adds them pairwise, then the
 // workgroup sum.
-__global__ void __launch_bounds__(256)
+constexpr int kFinThreads = 1024;
+constexpr int kFinUnroll = 8;
+
+__global__ void __launch_bounds__(kFinThreads)
 finalise_kernel(const double *__restrict__ p, int64_t n, double *__restrict__ out) {
-    __shared__ double sh[256 / kWave];
-    double a = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) a += p[i];
-    const double s = block_sum(a, sh);
+    __shared__ double sh[kFinThreads / kWave];
+    double a[kFinUnroll];
+#pragma unroll
+    for (int u = 0; u < kFinUnroll; ++u) a[u] = 0.0;
+    for (int64_t base = threadIdx.x; base < n; base += (int64_t)kFinThreads * kFinUnroll) {
+        double v[kFinUnroll];
+#pragma unroll
+        for (int u = 0; u < kFinUnroll; ++u) {
+            const int64_t i = base + (int64_t)u * kFinThreads;
+            v[u] = i < n ? p[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kFinUnroll; ++u) a[u] += v[u];
+    }
+    const double t = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    const double s = block_sum(t, sh);
     if (threadIdx.x == 0) *out = s;
 }
 
@@ -86,7 +103,7 @@ hipError_t launch_sum(const Launch &L, hipStream_t s) {
 }
 
 hipError_t launch_finalise(const double *partials, int64_t n, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(finalise_kernel, dim3(1), dim3(256), 0, s, partials, n, out);
+    hipLaunchKernelGGL(finalise_kernel, dim3(1), dim3(kFinThreads), 0, s, partials, n, out);
     return hipGetLastError();
 }
 

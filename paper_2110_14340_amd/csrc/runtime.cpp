@@ -252,7 +252,8 @@ struct jacc_ctx {
     unsigned flags = 0;
     bool dry = false, tracing = false, serialize = false;
     bool lazy = false;       // pull halo rows before reads instead of mirroring them at writes
-    bool split = false;      // stencil partitions: own-block rows first, edge rows after
+    bool split = false;      // stencil partitions: own-block rows first, edge rows after (any K)
+    bool no_split = false;   // never split (default: split at K <= 4)
     bool plan_only = false;  // planning pass without device work (batch replay check)
     jacc_allocator alloc{};
     bool use_hipmalloc = true;
@@ -970,7 +971,9 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
         PartPlan pp;
     };
     std::vector<Piece> pieces;
-    const bool split = c->split && !want_red && !persistent && !one_stream && K > 1 &&
+    // measured: splitting pays at 2-4 partitions; at 8 the extra launches
+    // make the host the bottleneck, so it is then only taken on request
+    const bool split = (c->split || (K <= 4 && !c->no_split)) && !want_red && !persistent && !one_stream && K > 1 &&
                        (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D);
     if (split) {
         int e = 0;  // halo depth of the reads along dim 0
@@ -1244,6 +1247,7 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
         c->serialize = (flags & JACC_INIT_SERIALIZE) != 0;
         c->lazy = (flags & JACC_INIT_LAZY) != 0;
         c->split = (flags & JACC_INIT_SPLIT) != 0;
+        c->no_split = (flags & JACC_INIT_NO_SPLIT) != 0;
         if (alloc) {
             c->alloc = *alloc;
             c->use_hipmalloc = false;
