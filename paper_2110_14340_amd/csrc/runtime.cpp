@@ -973,7 +973,12 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     std::vector<Piece> pieces;
     // measured: splitting pays at 2-4 partitions; at 8 the extra launches
     // make the host the bottleneck, so it is then only taken on request
-    const bool split = (c->split || (K <= 4 && !c->no_split)) && !want_red && !persistent && !one_stream && K > 1 &&
+    // (and only for partitions of at least 2^22 cells, whose kernels outlast
+    // the host cost of the extra launches)
+    int64_t part_cells = L.part_rows;
+    for (int d = 1; d < b->ndim; ++d) part_cells *= std::max<int64_t>(0, b->hi[d] - b->lo[d]);
+    const bool auto_split = K <= 4 && !c->no_split && part_cells >= ((int64_t)1 << 22);
+    const bool split = (c->split || auto_split) && !want_red && !persistent && !one_stream && K > 1 &&
                        (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D);
     if (split) {
         int e = 0;  // halo depth of the reads along dim 0

@@ -60,7 +60,7 @@ def graph_time(shapes, datas, configs, reps=10, keep_outputs=False):
         ctx.close()
 
 
-def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=600, tune_reps=5, graph_reps=10, log=print,
+def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=600, members=3, tune_reps=5, graph_reps=10, log=print,
         test_shapes=None, train_shapes=None):
     t_start = time.perf_counter()
     test_shapes = test_shapes or inputs.batch_shapes(5, n2d, n3d)
@@ -83,7 +83,7 @@ def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=600, tune_reps=5, graph
     log(f"training set: {len(y)} timings from {len(train_shapes)} shapes ({t_train_tune:.1f} s)")
     # 2. train the GPU network (80/20 split by loop for a held-out loss)
     val = group % 5 == 4
-    model = tuner.CostModel(ctx, init_params=inputs.mlp_init(tuner.NFEAT, seed=8))
+    model = tuner.CostModel(ctx, init_params=[inputs.mlp_init(tuner.NFEAT, seed=8 + m) for m in range(members)])
     t0 = time.perf_counter()
     losses = model.fit(X[~val], y[~val], epochs=epochs, batch=256, lr=1e-3, seed=9)
     t_fit = time.perf_counter() - t0

@@ -219,26 +219,38 @@ class CostModel:
     the library's GPU network (jacc.Model) for training and inference."""
 
     def __init__(self, ctx, init_params=None):
+        """init_params: one parameter set, or a list of them for an ensemble
+        of networks (trained on the same data with different initial weights
+        and sample orders; the prediction is their mean)."""
         self.ctx = ctx
-        self.net = jacc.Model(ctx, NFEAT)
-        if init_params is not None:
-            self.net.set_params(init_params)
+        inits = init_params if isinstance(init_params, list) else [init_params]
+        self.nets = []
+        for p in inits:
+            net = jacc.Model(ctx, NFEAT)
+            if p is not None:
+                net.set_params(p)
+            self.nets.append(net)
+        self.net = self.nets[0]
         self.mu = np.zeros(NFEAT)
         self.sd = np.ones(NFEAT)
         self.trained = False
 
     def fit(self, X, y, epochs=300, batch=256, lr=1e-3, seed=0):
+        """Trains every member; returns the first member's loss curve."""
         X = np.asarray(X, dtype=np.float64)
         self.mu = X.mean(axis=0)
         sd = X.std(axis=0)
         self.sd = np.where(sd > 0, sd, 1.0)
-        self.net.set_scaler(self.mu, self.sd)
-        losses = self.net.train(X, np.asarray(y), epochs=epochs, batch=batch, lr=lr, seed=seed)
+        curves = []
+        for m, net in enumerate(self.nets):
+            net.set_scaler(self.mu, self.sd)
+            curves.append(net.train(X, np.asarray(y), epochs=epochs, batch=batch, lr=lr, seed=seed + m))
         self.trained = True
-        return losses
+        return curves[0]
 
     def predict(self, X):
-        return self.net.predict(np.asarray(X, dtype=np.float64))
+        X = np.asarray(X, dtype=np.float64)
+        return np.mean([net.predict(X) for net in self.nets], axis=0)
 
     def pick(self, shape, cands=None):
         """Configuration with the smallest predicted log time (ties to the
@@ -248,7 +260,8 @@ class CostModel:
         return cands[int(np.argmin(pred))], pred
 
     def close(self):
-        self.net.close()
+        for net in self.nets:
+            net.close()
 
 
 def choose(shape, model=None, ctx=None, u0=None, db=None):
