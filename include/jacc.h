@@ -143,7 +143,9 @@ typedef struct {
  *   order      workgroup-to-tile order: 1 = row-major, 2 = XCD-aware (the
  *              chip hands consecutive workgroup ids to its 8 XCDs in turn; with
  *              this order each XCD walks one contiguous band of tiles, so the
- *              rows two neighbouring tiles share meet in that XCD's L2)
+ *              rows two neighbouring tiles share meet in that XCD's L2);
+ *              HEAT3D also 3 = XCD-aware with y-blocks of 8 tile rows walked
+ *              through all z tiles (compact bricks per XCD)
  *   march      stencil march direction: 1 = every tile toward higher rows
  *              (planes), 2 = odd tiles toward lower ones, so that the
  *              boundary rows two neighbouring tiles share are read by both at

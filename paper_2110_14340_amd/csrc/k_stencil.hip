@@ -385,6 +385,33 @@ __device__ __forceinline__ double heat_rows_tile(const double *__restrict__ in, 
     return acc;
 }
 
+// Heat tile coordinates of tile t.  Orders 1 and 2: x fastest, then y, then
+// z.  Order 3 (t taken XCD-aware as in order 2): y-blocks of 8 tile rows
+// walked through all z tiles before the next y-block, so the workgroups
+// resident on one XCD at a time form a compact (x, 8 y, few z) brick and
+// both the y-halo rows and the z-halo planes they share meet in its L2.
+constexpr int64_t kHeatYBlock = 8;
+__device__ __forceinline__ void heat_coords(int64_t t, int64_t gx, int64_t gy, int64_t gz, int order, int64_t &bxi,
+                                            int64_t &byi, int64_t &bzi) {
+    bxi = t % gx;
+    const int64_t r = t / gx;
+    if (order != 3) {
+        byi = r % gy;
+        bzi = r / gy;
+        return;
+    }
+    const int64_t full = gy / kHeatYBlock;  // complete y-blocks
+    if (r < full * kHeatYBlock * gz) {
+        const int64_t blk = r / (kHeatYBlock * gz), q = r % (kHeatYBlock * gz);
+        bzi = q / kHeatYBlock;
+        byi = blk * kHeatYBlock + q % kHeatYBlock;
+    } else {
+        const int64_t r2 = r - full * kHeatYBlock * gz, rem = gy - full * kHeatYBlock;
+        bzi = r2 / rem;
+        byi = full * kHeatYBlock + r2 % rem;
+    }
+}
+
 template <int VEC, int R, bool RES>
 __global__ void __launch_bounds__(R == 1 ? 1024 : 256)
 heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t ny, int64_t nx, int64_t z_lo,
@@ -392,16 +419,18 @@ heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t n
               int march, double alpha, double *__restrict__ wg_partials, Mirrors mir, int64_t gx, int64_t gy,
               int order) {
     __shared__ double sh[16];
-    const int64_t t = tile_of(order);
-    const int64_t rest = t / gx;
+    const int64_t t = tile_of(order == 3 ? 2 : order);
+    const int64_t gz = (int64_t)gridDim.x / (gx * gy);
+    int64_t bxi, byi, bzi;
+    heat_coords(t, gx, gy, gz, order, bxi, byi, bzi);
     double acc;
     if constexpr (R == 1)
         acc = heat_tile<VEC, RES>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, march, alpha, mir,
-                                  t % gx, rest % gy, rest / gy, threadIdx.x, threadIdx.y, blockDim.x, blockDim.y);
+                                  bxi, byi, bzi, threadIdx.x, threadIdx.y, blockDim.x, blockDim.y);
     else
         acc = heat_rows_tile<VEC, R, RES>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, march,
-                                          alpha, mir, t % gx, rest % gy, rest / gy, threadIdx.x, threadIdx.y,
-                                          blockDim.x, blockDim.y);
+                                          alpha, mir, bxi, byi, bzi, threadIdx.x, threadIdx.y, blockDim.x,
+                                          blockDim.y);
     if (RES) {
         const double s = block_sum(acc, sh);
         if (threadIdx.x == 0 && threadIdx.y == 0) wg_partials[t] = s;  // partials in tile order

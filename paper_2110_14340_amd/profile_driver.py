@@ -13,7 +13,7 @@ import sys
 import numpy as np
 
 
-def main(which="jacobi", launches=20):
+def main(which="jacobi", launches=20, cfg=None):
     import torch
     from . import inputs, jacc
     x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
@@ -40,7 +40,7 @@ def main(which="jacobi", launches=20):
             c.enter(a, halo=(1, 1))
             c.enter(b, halo=(1, 1))
             for t in range(launches):
-                (c.heat3d(a, b, 0.1, slot=t) if t % 2 == 0 else c.heat3d(b, a, 0.1, slot=t))
+                (c.heat3d(a, b, 0.1, slot=t, cfg=cfg) if t % 2 == 0 else c.heat3d(b, a, 0.1, slot=t, cfg=cfg))
             c.wait()
     elif which == "gemm":
         A, B = inputs.gemm_inputs(4096, 4096, 4096, seed=3)
@@ -72,4 +72,11 @@ def main(which="jacobi", launches=20):
 
 
 if __name__ == "__main__":
-    main(*(sys.argv[1:2] or ["jacobi"]))
+    # optional launch configuration after the workload name:
+    # bx by tile order march rows (heat only)
+    cfg = None
+    if len(sys.argv) > 2:
+        from . import jacc
+        bx, by, tile, order, march, rows = (int(v) for v in sys.argv[2:8])
+        cfg = jacc.config(bx=bx, by=by, tile=tile, order=order, march=march, rows=rows)
+    main(*(sys.argv[1:2] or ["jacobi"]), cfg=cfg)

@@ -90,6 +90,8 @@ def _rel_close(a, b, tol=1e-13):
     ((21, 19, 130), 2, _cfg(64, 2, 4, 2, rows=2)), ((17, 30, 66), 3, _cfg(64, 4, 7, 2, march=2, rows=4)),
     ((13, 21, 131), 1, _cfg(128, 2, 3, 1, rows=8)), ((33, 11, 258), 4, _cfg(128, 1, 16, 2, order=2, rows=8)),
     ((9, 3, 64), 2, _cfg(64, 1, 2, 2, rows=4)), ((12, 37, 70), 2, _cfg(256, 1, 5, 2, march=2, rows=2)),
+    ((30, 75, 130), 2, _cfg(64, 2, 3, 2, order=3, march=2, rows=4)), ((19, 9, 66), 1, _cfg(128, 1, 4, 1, order=3)),
+    ((26, 140, 258), 3, _cfg(128, 2, 8, 2, order=3, rows=4)),
 ])
 def test_heat_small_bit_exact_and_residual(shape, K, cfg):
     say(f"heat {shape} K={K}")
