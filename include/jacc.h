@@ -90,7 +90,9 @@ typedef enum { JACC_F64 = 0, JACC_F32 = 1, JACC_I32 = 2, JACC_I64 = 3 } jacc_dty
  * holds extent[1]*...*extent[ndim-1] elements.  halo_lo/halo_hi are the
  * largest distances (in rows) below and above the owner block that loops
  * will read.  whole != 0 keeps a full replica in every partition.
- * num_partitions: K of this array (0 = the context's K). */
+ * num_partitions: K of this array (0 = the context's K; at most 64; with more
+ * partitions than the context has streams, partition p runs on stream p mod
+ * the stream count). */
 typedef struct {
     int32_t dtype;
     int32_t ndim;            /* 1..4 */

@@ -1384,7 +1384,9 @@ int jacc_data_enter(jacc_ctx *c, void *host, const jacc_array_desc *d, int claus
         }
         if (d->halo_lo < 0 || d->halo_hi < 0) return set_err(c, JACC_ERR_INVALID, "negative halo");
         int K = d->num_partitions ? d->num_partitions : c->K;
-        if (K < 1 || K > c->K) return set_err(c, JACC_ERR_INVALID, "num_partitions %d not in [1,%d]", K, c->K);
+        // more partitions than streams is allowed: partition p then runs on
+        // stream p mod the stream count
+        if (K < 1 || K > kMaxK) return set_err(c, JACC_ERR_INVALID, "num_partitions %d not in [1,%d]", K, kMaxK);
         if (!d->whole && K > d->extent[0])
             return set_err(c, JACC_ERR_INVALID, "K=%d exceeds the %lld rows of dim 0", K, (long long)d->extent[0]);
         size_t bytes = (size_t)d->extent[0] * (size_t)row * es;
