@@ -70,7 +70,7 @@ typedef enum {
     JACC_ERR_RANGE = -4,           /* access outside a slab, or partitions writing the same rows */
     JACC_ERR_ALLOC = -5,           /* the allocator returned NULL */
     JACC_ERR_DEVICE = -6,          /* a HIP call failed (sticky) */
-    JACC_ERR_UNSUPPORTED = -7      /* a legal request this build does not implement */
+    JACC_ERR_UNSUPPORTED = -7      /* a legal request the library does not implement */
 } jacc_status;
 
 /* Device-memory allocator.  alloc returns device memory of at least `bytes`
