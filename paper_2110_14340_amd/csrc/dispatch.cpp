@@ -39,7 +39,7 @@ Cfg default_config(int kind, const Launch &L, Cfg c) {
             if (!c.march) c.march = 2;
             break;
         default:
-            if (!c.bx) c.bx = 256;
+            if (!c.bx) c.bx = kind == JACC_LOOP_GEMM ? 512 : 256;  // GEMM: 8 waves of 64x32 measured faster
             if (!c.by) c.by = 1;
             if (!c.tile) c.tile = kind == JACC_LOOP_GEMM ? 16 : 1;  // GEMM: 16-deep slabs measured faster
             if (!c.vec) c.vec = 1;
@@ -69,7 +69,8 @@ int check_config(const Launch &L) {
             if (c.rows != 1 && c.bx * c.by > 256) return 1;  // multi-row waves: workgroups of at most 256
             return 0;
         case JACC_LOOP_GEMM:
-            return (c.tile == 16 || c.tile == 32) ? 0 : 1;  // k-slab depth; other fields are ignored
+            // k-slab depth and workgroup size; other fields are ignored
+            return ((c.tile == 16 || c.tile == 32) && (c.bx == 256 || c.bx == 512)) ? 0 : 1;
         case JACC_LOOP_SUM:
         case JACC_LOOP_SPMV_CSR:
         case JACC_LOOP_SCATTER_SQ:

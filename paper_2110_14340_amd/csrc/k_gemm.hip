@@ -45,21 +45,27 @@ __device__ __forceinline__ void gemm_tile(int64_t tiles_m, int64_t tiles_n, int6
 // BK = 16: two LDS buffers, one barrier per k-slab.  BK = 32: one LDS
 // buffer (the register staging holds the next slab), two barriers per slab
 // of twice the work, so the next slab's loads have longer to arrive.
-template <int BK>
-__global__ void __launch_bounds__(kGemmThreads)
+// WN = waves along N: 2 (256 threads, 64x64 per wave) or 4 (512 threads,
+// 64x32 per wave: half the accumulators per lane, twice the waves).
+// (the 512-thread form asks for four waves per SIMD, i.e. at most 128
+// registers, so that two of its workgroups fit on a compute unit)
+template <int BK, int WN>
+__global__ void __launch_bounds__(kGemmThreads * WN / 2, (WN == 4 && BK == 16) ? 4 : 1)
 gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *__restrict__ C, int64_t m_lo,
             int64_t m_hi, int64_t N, int64_t L, int64_t lda, int64_t ldb, int64_t ldc, int64_t n_lo, int64_t n_hi,
             int64_t tiles_m, int64_t tiles_n) {
+    constexpr int NT = kGemmThreads * WN / 2;  // threads
+    constexpr int JT = 4 * 2 / WN;             // 16-column MFMA blocks per wave
     constexpr int NBUF = BK == 16 ? 2 : 1;
     constexpr int SA = BK + 2;           // LDS row stride of A (doubles): conflict-free fragment reads
-    constexpr int U = BK / 4;            // double pairs per thread per operand and slab
+    constexpr int U = 64 * BK / NT;      // double pairs per thread per operand and slab
     constexpr int KP = BK / 2;           // A: k pairs per row
     __shared__ __align__(16) double As[NBUF][BM * SA];
     __shared__ __align__(16) double Bs[NBUF][BK * SB];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WN, wn = wave % WN;
     int64_t ti, tj;
     gemm_tile(tiles_m, tiles_n, &ti, &tj);
     const int64_t row0 = m_lo + ti * BM;
@@ -74,7 +80,7 @@ gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *
         const bool full = full_mn && k0 + BK <= L;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int idx = tid + u * kGemmThreads;
+            const int idx = tid + u * NT;
             const int r = idx / KP, kp = (idx % KP) * 2;    // A: row, k pair
             const int kr = idx >> 6, cp = (idx & 63) * 2;   // B: k, column pair
             if (full) {
@@ -93,7 +99,7 @@ gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *
     auto store_tiles = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int idx = tid + u * kGemmThreads;
+            const int idx = tid + u * NT;
             const int r = idx / KP, kp = (idx % KP) * 2;
             *reinterpret_cast<dvec2 *>(&As[buf][r * SA + kp]) = ra[u];
             const int kr = idx >> 6, cp = (idx & 63) * 2;
@@ -101,11 +107,11 @@ gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *
         }
     };
 
-    d4 acc[4][4];
+    d4 acc[4][JT];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < JT; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
     const int nk = (int)((L + BK - 1) / BK);
     load_tiles(0);
@@ -118,16 +124,17 @@ gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *
         const double *bs = Bs[buf];
 #pragma unroll
         for (int kk = 0; kk < BK / 4; ++kk) {
-            double a[4], b[4];
+            double a[4], b[JT];
             const int kq = kk * 4 + (lane >> 4);
 #pragma unroll
             for (int i = 0; i < 4; ++i) a[i] = as[(wm * 64 + i * 16 + (lane & 15)) * SA + kq];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = bs[kq * SB + wn * 64 + j * 16 + (lane & 15)];
+            for (int j = 0; j < JT; ++j) b[j] = bs[kq * SB + wn * (16 * JT) + j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < JT; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         if (kt + 1 < nk) {
             if (NBUF == 1) __syncthreads();  // every wave is done reading the single buffer
@@ -135,7 +142,7 @@ gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *
         }
         __syncthreads();
     }
-    // write back: acc[i][j][r] -> C[row0 + wm*64 + i*16 + 4*r + lane/16][col0 + wn*64 + j*16 + lane%16]
+    // write back: acc[i][j][r] -> C[row0 + wm*64 + i*16 + 4*r + lane/16][col0 + wn*16*JT + j*16 + lane%16]
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -143,8 +150,8 @@ gemm_kernel(const double *__restrict__ A, const double *__restrict__ B, double *
             const int64_t gi = row0 + wm * 64 + i * 16 + 4 * r + (lane >> 4);
             if (gi >= m_hi) continue;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t gj = col0 + wn * 64 + j * 16 + (lane & 15);
+            for (int j = 0; j < JT; ++j) {
+                const int64_t gj = col0 + wn * (16 * JT) + j * 16 + (lane & 15);
                 if (gj < n_hi) C[gi * ldc + gj] = acc[i][j][r];
             }
         }
@@ -160,15 +167,25 @@ hipError_t launch_gemm(const Launch &L, hipStream_t s) {
     const int64_t Lk = L.a[0].row_elems;
     const int64_t N = L.a[2].row_elems;
     const int64_t tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
-    // configuration field `tile` selects the k-slab depth (16 or 32)
-    if (L.cfg.tile == 16)
-        hipLaunchKernelGGL(gemm_kernel<16>, dim3((unsigned)(tiles_m * tiles_n)), dim3(kGemmThreads), 0, s,
-                           (const double *)L.a[0].ptr, (const double *)L.a[1].ptr, (double *)L.a[2].ptr, L.lo[0],
-                           L.hi[0], N, Lk, Lk, L.a[1].row_elems, N, L.lo[1], L.hi[1], tiles_m, tiles_n);
-    else
-        hipLaunchKernelGGL(gemm_kernel<32>, dim3((unsigned)(tiles_m * tiles_n)), dim3(kGemmThreads), 0, s,
-                           (const double *)L.a[0].ptr, (const double *)L.a[1].ptr, (double *)L.a[2].ptr, L.lo[0],
-                           L.hi[0], N, Lk, Lk, L.a[1].row_elems, N, L.lo[1], L.hi[1], tiles_m, tiles_n);
+    // configuration fields: `tile` = k-slab depth (16 or 32), `bx` = threads
+    // (256: 4 waves of 64x64, 512: 8 waves of 64x32)
+    const dim3 grid((unsigned)(tiles_m * tiles_n));
+#define GEMM_ARGS                                                                                                 \
+    (const double *)L.a[0].ptr, (const double *)L.a[1].ptr, (double *)L.a[2].ptr, L.lo[0], L.hi[0], N, Lk, Lk, \
+        L.a[1].row_elems, N, L.lo[1], L.hi[1], tiles_m, tiles_n
+    const bool wide = L.cfg.bx == 512;
+    if (L.cfg.tile == 16) {
+        if (wide)
+            hipLaunchKernelGGL((gemm_kernel<16, 4>), grid, dim3(512), 0, s, GEMM_ARGS);
+        else
+            hipLaunchKernelGGL((gemm_kernel<16, 2>), grid, dim3(256), 0, s, GEMM_ARGS);
+    } else {
+        if (wide)
+            hipLaunchKernelGGL((gemm_kernel<32, 4>), grid, dim3(512), 0, s, GEMM_ARGS);
+        else
+            hipLaunchKernelGGL((gemm_kernel<32, 2>), grid, dim3(256), 0, s, GEMM_ARGS);
+    }
+#undef GEMM_ARGS
     return hipGetLastError();
 }
 

@@ -54,13 +54,13 @@ def test_sum_integer_exact_and_deferred_slots():
 
 
 # ------------------------------------------------------------------ GEMM
-def _gemm_dev(A, B, K, slab=0):
+def _gemm_dev(A, B, K, slab=0, threads=0):
     C = np.zeros((A.shape[0], B.shape[1]))
     with context(K) as c:
         c.enter(A)
         c.enter(B, whole=True)
         c.enter(C, clause=jacc.CREATE)
-        c.gemm(A, B, C, cfg=jacc.config(tile=slab) if slab else None)
+        c.gemm(A, B, C, cfg=jacc.config(tile=slab, bx=threads) if (slab or threads) else None)
         c.exit(C, jacc.COPYOUT)
     return C
 
@@ -72,10 +72,10 @@ def test_gemm_small_frobenius_and_integer_exact(M, N, L, K):
     A, B = inputs.gemm_inputs(M, N, L, seed=3)
     ref = oracle.gemm(A, B)
     Ai, Bi = inputs.gemm_inputs(M, N, L, seed=4, integer=True)
-    for slab in (16, 32):
-        C = _gemm_dev(A, B, K, slab)
+    for slab, threads in ((16, 256), (32, 256), (16, 512), (32, 512)):
+        C = _gemm_dev(A, B, K, slab, threads)
         assert np.linalg.norm(C - ref) <= 1e-12 * np.linalg.norm(A) * np.linalg.norm(B)
-        assert np.array_equal(_gemm_dev(Ai, Bi, K, slab), oracle.gemm(Ai, Bi))
+        assert np.array_equal(_gemm_dev(Ai, Bi, K, slab, threads), oracle.gemm(Ai, Bi))
 
 
 def test_gemm_4096_sampled_rows():
@@ -85,7 +85,8 @@ def test_gemm_4096_sampled_rows():
     C1 = _gemm_dev(A, B, 1)
     C4 = _gemm_dev(A, B, 4)
     assert np.array_equal(C1, C4)  # no split-k: partitioning never changes an element's sum order
-    assert np.array_equal(C1, _gemm_dev(A, B, 1, 16))  # nor does the k-slab depth
+    assert np.array_equal(C1, _gemm_dev(A, B, 1, 32))  # nor does the k-slab depth
+    assert np.array_equal(C1, _gemm_dev(A, B, 1, 16, 512))  # nor the workgroup size
     # one row of every residue mod 16 (the matrix-core output interleaves
     # rows across lane groups), block edges and the last row
     rows = sorted(set([1024 + r for r in range(16)] + [0, 1, 4, 2047, 2050, 4095]))
