@@ -270,9 +270,9 @@ struct jacc_ctx {
     uintptr_t fake_next = (uintptr_t)1 << 44;
     // reductions (buffers indexed by stream)
     double *slots = nullptr;             // kSlots doubles
-    double *partials = nullptr;          // kMaxK doubles, one per partition
+    double *partials = nullptr;          // kSlots * kMaxK doubles: per slot, one per partition
     double *wg = nullptr;                // streams * kWgCapacity doubles
-    std::vector<SeqRef> partial_reader;  // last combine that read partials[p]
+    std::vector<SeqRef> partial_reader;  // last combine that read partials[slot][p]
     std::vector<SeqRef> slot_src;        // op that produced each slot
     // batches
     std::vector<Batch *> batches;
@@ -961,6 +961,7 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     // other slabs hold as halo (at most one neighbour block on each side)
     const bool can_mirror =
         !c->lazy && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) && !P->whole && K > 1;
+    const int red_slot = slot >= 0 ? slot : kSlots - 1;  // a synchronous-only reduction uses the last slot
     std::vector<int> order;       // partitions that reduce, in partition order
     std::vector<int> red_streams;  // their streams
     // pieces: one per partition, or (split mode) first every partition's
@@ -1089,14 +1090,17 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             if (rc) return rc;
         }
         if (want_red) {
-            // partials[p] is read by the last combine that used it; the
-            // workgroup scratch of stream s is consumed by the finaliser that
-            // follows the kernel on the same stream
-            rc = ensure_wait(c, s, c->partial_reader[p].s, c->partial_reader[p].seq);
+            // partials[slot][p] is read by the last combine of that slot
+            // (loops reducing into different slots never wait on each
+            // other's combines); the workgroup scratch of stream s is
+            // consumed by the finaliser that follows the kernel on the same
+            // stream
+            const size_t pi = (size_t)red_slot * kMaxK + p;
+            rc = ensure_wait(c, s, c->partial_reader[pi].s, c->partial_reader[pi].seq);
             if (rc) return rc;
             LP.wg_partials = c->wg + (size_t)s * kWgCapacity;
             LP.wg_capacity = kWgCapacity;
-            LP.part_out = c->partials + p;
+            LP.part_out = c->partials + pi;
             if (jk::reduction_workgroups(LP) > kWgCapacity)
                 return set_err(c, JACC_ERR_UNSUPPORTED, "reduction needs more than %lld workgroups",
                                (long long)kWgCapacity);
@@ -1127,17 +1131,18 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             rc = ensure_wait(c, s0, s, c->st[s].seq);
             if (rc) return rc;
         }
-        const int sl = slot >= 0 ? slot : kSlots - 1;  // a synchronous-only reduction uses the last slot
+        const int sl = red_slot;
         rc = ensure_wait(c, s0, c->slot_src[sl].s, c->slot_src[sl].seq);  // earlier writer of the slot
         if (rc) return rc;
         if (live(c)) {
             jk::CombineList cl{};
             cl.n = (int)order.size();
             for (size_t k = 0; k < order.size(); ++k) cl.idx[k] = order[k];
-            HIPCHK(c, jk::launch_combine(c->partials, cl, c->slots + sl, c->st[s0].s), "combine launch");
+            HIPCHK(c, jk::launch_combine(c->partials + (size_t)sl * kMaxK, cl, c->slots + sl, c->st[s0].s),
+                   "combine launch");
         }
         c->st[s0].seq++;
-        for (int q : order) c->partial_reader[q] = {s0, c->st[s0].seq};
+        for (int q : order) c->partial_reader[(size_t)sl * kMaxK + q] = {s0, c->st[s0].seq};
         c->slot_src[sl] = {s0, c->st[s0].seq};
         trace(c, JACC_OP_COMBINE, s0, -1, -1, -1, sl, 0, 0, c->st[s0].seq);
         rc = post_op(c);
@@ -1268,7 +1273,7 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
         const int ns = c->serialize ? 1 : K;
         c->st.resize(ns);
         c->own_streams = (streams == nullptr);
-        c->partial_reader.assign(kMaxK, SeqRef{});
+        c->partial_reader.assign((size_t)kSlots * kMaxK, SeqRef{});
         c->slot_src.assign(kSlots, SeqRef{});
         int rc = JACC_OK;
         for (int s = 0; s < ns && !rc; ++s) {
@@ -1293,7 +1298,7 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
             if (e != hipSuccess) rc = dev_fail(c, e, "event creation");
         }
         if (!rc) rc = dev_alloc(c, kSlots * sizeof(double), (void **)&c->slots);
-        if (!rc) rc = dev_alloc(c, kMaxK * sizeof(double), (void **)&c->partials);
+        if (!rc) rc = dev_alloc(c, (size_t)kSlots * kMaxK * sizeof(double), (void **)&c->partials);
         if (!rc) rc = dev_alloc(c, (size_t)ns * kWgCapacity * sizeof(double), (void **)&c->wg);
         if (!rc && !c->dry) {
             hipError_t e = hipMemset(c->slots, 0, kSlots * sizeof(double));
