@@ -60,7 +60,7 @@ def graph_time(shapes, datas, configs, reps=10, keep_outputs=False):
         ctx.close()
 
 
-def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=600, members=3, tune_reps=5, graph_reps=10, log=print,
+def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=600, members=3, tune_reps=5, graph_reps=30, log=print,
         test_shapes=None, train_shapes=None):
     t_start = time.perf_counter()
     test_shapes = test_shapes or inputs.batch_shapes(5, n2d, n3d)
