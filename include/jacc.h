@@ -164,7 +164,9 @@ typedef struct {
 } jacc_config;
 
 /* Loop kinds (hand-written HIP loop bodies) and their arguments, in order:
- *   JACOBI2D  u_in R [-1,+1]; u_out W [0,0].  2-D bounds (normally [1,N-1)^2).
+ *   JACOBI2D  u_in R [-1,+1]; u_out W [0,0] (or W|FILTERED with u_in entered
+ *             whole: every partition sweeps the whole box and keeps its
+ *             owner rows).  2-D bounds (normally [1,N-1)^2).
  *             u_out[i][j] = 0.25*((u_in[i-1][j]+u_in[i+1][j]) + (u_in[i][j-1]+u_in[i][j+1]))
  *   HEAT3D    u_in R [-1,+1]; u_out W [0,0].  3-D bounds; scalars[0] = alpha.
  *             lap = (((x-1 + x+1) + (y-1 + y+1)) + (z-1 + z+1)) - 6*u;  u' = u + alpha*lap

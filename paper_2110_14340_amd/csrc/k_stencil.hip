@@ -103,7 +103,8 @@ template <int VEC>
 __device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, double *__restrict__ out, int64_t nx,
                                             int64_t r_lo, int64_t r_hi, int64_t c_lo, int64_t c_hi, int64_t col0,
                                             int tile, int march, const Mirrors &mir, int64_t bxi, int64_t byi, int tx,
-                                            int ty, int bdx, int bdy) {
+                                            int ty, int bdx, int bdy, int64_t own_lo = INT64_MIN,
+                                            int64_t own_hi = INT64_MAX) {
     const int lane = tx & (kWave - 1);
     const int64_t j = col0 + (bxi * bdx + tx) * VEC;
     const int64_t q = byi * bdy + ty;
@@ -150,7 +151,9 @@ __device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, doubl
                     const double horz = left[v] + right[v];
                     o[v] = 0.25 * (vert + horz);
                 }
-                store_out<VEC>(out, row * nx + j, row, mir, o, all, comp);
+                // write guard of a filtered loop (every partition computes the
+                // whole box and keeps its owner rows); uniform per row
+                if (row >= own_lo && row < own_hi) store_out<VEC>(out, row * nx + j, row, mir, o, all, comp);
             }
         }
 #pragma unroll
@@ -172,10 +175,11 @@ __device__ __forceinline__ int64_t tile_of(int order) {
 template <int VEC>
 __global__ void __launch_bounds__(1024)
 jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t nx, int64_t r_lo, int64_t r_hi,
-                int64_t c_lo, int64_t c_hi, int64_t col0, int tile, int march, Mirrors mir, int64_t gx, int order) {
+                int64_t c_lo, int64_t c_hi, int64_t col0, int tile, int march, Mirrors mir, int64_t gx, int order,
+                int64_t own_lo, int64_t own_hi) {
     const int64_t t = tile_of(order);
     jacobi_tile<VEC>(in, out, nx, r_lo, r_hi, c_lo, c_hi, col0, tile, march, mir, t % gx, t / gx, threadIdx.x,
-                     threadIdx.y, blockDim.x, blockDim.y);
+                     threadIdx.y, blockDim.x, blockDim.y, own_lo, own_hi);
 }
 
 // ---------------------------------------------------------------------------
@@ -498,12 +502,14 @@ hipError_t launch_jacobi2d(const Launch &L, hipStream_t s) {
     dim3 grid((unsigned)(gx * gy));
     const double *in = (const double *)L.a[0].ptr;
     double *out = (double *)L.a[1].ptr;
+    const bool filtered = L.own_hi > L.own_lo;  // FILTERED output: keep the owner rows only
+    const int64_t own_lo = filtered ? L.own_lo : INT64_MIN, own_hi = filtered ? L.own_hi : INT64_MAX;
     if (c.vec == 2)
         hipLaunchKernelGGL(jacobi2d_kernel<2>, grid, block, 0, s, in, out, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1],
-                           col0, c.tile, c.march, L.mir, gx, c.order);
+                           col0, c.tile, c.march, L.mir, gx, c.order, own_lo, own_hi);
     else
         hipLaunchKernelGGL(jacobi2d_kernel<1>, grid, block, 0, s, in, out, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1],
-                           col0, c.tile, c.march, L.mir, gx, c.order);
+                           col0, c.tile, c.march, L.mir, gx, c.order, own_lo, own_hi);
     return hipGetLastError();
 }
 

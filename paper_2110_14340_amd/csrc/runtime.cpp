@@ -892,6 +892,8 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
     if (L.cfg.persistent) {
         if (!c->cur) return set_err(c, JACC_ERR_INVALID, "persistent execution needs an open batch");
         if (want_red) return set_err(c, JACC_ERR_UNSUPPORTED, "persistent execution of a reduction");
+        if (args[primary].mode & JACC_FILTERED)
+            return set_err(c, JACC_ERR_UNSUPPORTED, "persistent execution of a filtered loop");
     }
     *primary_out = primary;
     return JACC_OK;
@@ -980,6 +982,7 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     for (int d = 1; d < b->ndim; ++d) part_cells *= std::max<int64_t>(0, b->hi[d] - b->lo[d]);
     const bool auto_split = K <= 4 && !c->no_split && part_cells >= ((int64_t)1 << 22);
     const bool split = (c->split || auto_split) && !want_red && !persistent && !one_stream && K > 1 &&
+                       !(args[primary].mode & JACC_FILTERED) &&
                        (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D);
     if (split) {
         int e = 0;  // halo depth of the reads along dim 0

@@ -159,3 +159,31 @@ def test_jacobi_split_mode_bit_exact(shape, K, steps):
     say(f"jacobi split mode {shape} K={K} T={steps}")
     u0 = inputs.jacobi_grid(*shape, seed=12)
     assert np.array_equal(run_jacobi(u0, steps, K, ctx_flags=jacc.INIT_SPLIT), oracle.jacobi2d(u0, steps))
+
+
+@pytest.mark.parametrize("shape,K", [((64, 130), 1), ((131, 258), 3), ((1030, 514), 4)])
+def test_filtered_jacobi_equals_hoisted_form(shape, K):
+    """Predicate-filtered form (every partition sweeps the whole box from a
+    whole replica and keeps its owner rows) against the hoisted form and the
+    oracle, then a hoisted sweep that reads the filtered output's halo rows."""
+    say(f"filtered jacobi {shape} K={K}")
+    from gpu_util import context
+    u0 = inputs.jacobi_grid(*shape, seed=21)
+    ny, nx = shape
+    a = u0.copy()
+    b = u0.copy()
+    d = u0.copy()
+    with context(K) as c:
+        c.enter(a, whole=True)
+        c.enter(b, halo=(1, 1))
+        c.enter(d, halo=(1, 1))
+        c.loop(jacc.JACOBI2D, jacc.bounds((1, ny - 1), (1, nx - 1)),
+               [(a, jacc.READ, -1, 1, 0), (b, jacc.WRITE | jacc.FILTERED, 0, 0, 0)])
+        c.jacobi2d(b, d)
+        c.exit(d)
+        c.exit(b)
+    one = u0.copy()
+    oracle.jacobi2d_sweep(u0, one)
+    assert np.array_equal(b, one)
+    assert np.array_equal(b, run_jacobi(u0, 1, K))
+    assert np.array_equal(d, oracle.jacobi2d(u0, 2))

@@ -495,3 +495,25 @@ def test_split_mode_pieces_cover_partitions_race_free(K, E, lazy):
     assert race_check(full) == []
     assert freshness_check(full) == []
     c.close()
+
+
+def test_filtered_jacobi_plan_every_partition_sweeps_the_box_writes_its_block():
+    E, K = 40, 4
+    c = dry(K)
+    a = np.zeros((E, 16))
+    b = np.zeros((E, 16))
+    c.enter(a, whole=True)
+    c.enter(b, halo=(1, 1))
+    tr = _loop_trace(c, lambda: c.loop(jacc.JACOBI2D, jacc.bounds((1, E - 1), (1, 15)),
+                                       [(a, jacc.READ, -1, 1, 0), (b, jacc.WRITE | jacc.FILTERED, 0, 0, 0)]))
+    kernels = [(t["dst"], t["lo"], t["hi"]) for t in tr if t["op"] == "KERNEL"]
+    assert kernels == [(p, 1, E - 1) for p in range(K)]
+    own_writes = [t for t in tr if t["op"] == "ACCESS" and t["kind"] == 2 and t["array"] == 1
+                  and P.block(E, K, t["dst"])[0] <= t["lo"] < P.block(E, K, t["dst"])[1]]
+    assert sorted((t["dst"], t["lo"], t["hi"]) for t in own_writes) == [(p, *P.block(E, K, p)) for p in range(K)]
+    # a persistent filtered loop is refused
+    c.batch_begin()
+    assert c.loop(jacc.JACOBI2D, jacc.bounds((1, E - 1), (1, 15)),
+                  [(a, jacc.READ, -1, 1, 0), (b, jacc.WRITE | jacc.FILTERED, 0, 0, 0)],
+                  cfg=jacc.config(persistent=1), raw=True) == jacc.ERR_UNSUPPORTED
+    c.close()
