@@ -30,3 +30,34 @@ def test_small_batched_learned_experiment():
         assert np.array_equal(o, ref), sh
     assert res["model_loss_first_last"][1] < res["model_loss_first_last"][0]
     assert np.isfinite(res["regret_learned_vs_exhaustive"])
+
+
+def test_full_batch_of_256_sweeps_in_one_graph_equals_oracle():
+    """The benchmark's batch (128 2-D + 128 3-D single sweeps, sides
+    log-uniform in [64, 4096] and [32, 512]) captured in one graph, small
+    loops as persistent tasks and large ones as partitioned launches: every
+    output equals its own oracle sweep bit for bit."""
+    say("full 256-loop batch in one graph vs oracle")
+    from paper_2110_14340_amd import tuner
+    shapes = inputs.batch_shapes(5, 128, 128)
+    datas = [inputs.jacobi_grid(*sh, seed=6000 + i) if len(sh) == 2 else inputs.heat_field(*sh, seed=6000 + i)
+             for i, sh in enumerate(shapes)]
+    cfgs = []
+    for sh in shapes:
+        cells = float(np.prod([d - 2 for d in sh]))
+        cfg = dict(tuner.DEFAULT_CONFIG)
+        if cells < 2 ** 18:
+            cfg.update(persistent=1, tile=4, vec=2 if sh[-1] % 2 == 0 else 1)
+        elif len(sh) == 2:
+            cfg.update(K=2, tile=8, vec=2 if sh[-1] % 2 == 0 else 1)
+        cfgs.append(cfg)
+    ms, info, outs = experiment.graph_time(shapes, datas, cfgs, reps=2, keep_outputs=True)
+    say(f"  graph {ms:.3f} ms, {info}")
+    assert info["persistent_groups"] >= 1
+    for sh, d, o in zip(shapes, datas, outs):
+        ref = d.copy()
+        if len(sh) == 2:
+            oracle.jacobi2d_sweep(d, ref)
+        else:
+            oracle.heat3d_sweep(d, ref, 0.1)
+        assert np.array_equal(o, ref), sh
