@@ -420,6 +420,19 @@ int jacc_adapt_observe(jacc_adapt *a, double time_kernel_s, double time_comm_s, 
  * partitioned runs}; any output pointer may be NULL. */
 int jacc_adapt_state(const jacc_adapt *a, int *mode, double *eff_dup, long long *counts);
 
+/* ---- parallel dimension of an updated array (Sec. "Division of
+ * Multidimensional Arrays") ----------------------------------------------------
+ * For an array of ndim (1..16) dimensions, parallel_iters[d] and
+ * sequential_iters[d] count the parallel and sequential loop iterators that
+ * appear in its index expression of dimension d (>= 0).  *dim receives the
+ * dimension with the most parallel iterators, then the fewest sequential
+ * ones, ties going to the leftmost dimension (column_major == 0, C order) or
+ * the rightmost (column_major != 0, Fortran order); -1 when no dimension has
+ * a parallel iterator (the loop would have to be duplicated).  Host-only
+ * planning helper: the runtime partitions dimension 0.  Returns
+ * JACC_ERR_INVALID on bad arguments. */
+int jacc_parallel_dim(int ndim, const int *parallel_iters, const int *sequential_iters, int column_major, int *dim);
+
 #ifdef __cplusplus
 }
 #endif

@@ -167,3 +167,19 @@ def plan_loop(arrays, lb, ub, args, refresh="pull", max_holders=2):
                     else:
                         st.valid[q] -= rows
     return plans
+
+
+def parallel_dim(par, seq, column_major=False):
+    """Parallel dimension of an updated array (Sec. "Division of
+    Multidimensional Arrays"): among the dimensions indexed by at least one
+    parallel iterator, those with the most parallel iterators; among them
+    those with the fewest sequential iterators; then the leftmost (C) or the
+    rightmost (Fortran) one.  None when no dimension qualifies."""
+    cands = [d for d in range(len(par)) if par[d] > 0]
+    if not cands:
+        return None
+    most = max(par[d] for d in cands)
+    cands = [d for d in cands if par[d] == most]
+    fewest = min(seq[d] for d in cands)
+    cands = [d for d in cands if seq[d] == fewest]
+    return max(cands) if column_major else min(cands)

@@ -130,6 +130,7 @@ def lib():
     L.jacc_adapt_destroy.argtypes = [vp]
     L.jacc_adapt_observe.argtypes = [vp, d, d, d, ctypes.POINTER(i32)]
     L.jacc_adapt_state.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)]
+    L.jacc_parallel_dim.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
     _lib = L
     return L
 
@@ -557,3 +558,17 @@ class Adaptive:
             self.close()
         except Exception:
             pass
+
+
+def parallel_dim(parallel_iters, sequential_iters, column_major=False):
+    """jacc_parallel_dim: the dimension an updated array is divided along, or
+    -1 when no dimension is indexed by a parallel iterator."""
+    L = lib()
+    n = len(parallel_iters)
+    P = (ctypes.c_int * max(1, n))(*parallel_iters)
+    S = (ctypes.c_int * max(1, n))(*sequential_iters)
+    out = ctypes.c_int(-2)
+    rc = L.jacc_parallel_dim(n, P, S, int(bool(column_major)), ctypes.byref(out))
+    if rc != OK:
+        raise JaccError(rc, "jacc_parallel_dim")
+    return out.value
