@@ -86,7 +86,7 @@ def run_jacobi(ctx_mod, torch, u0, K, steps, warmup, cfg=None, flags=0):
     return t1 - t0, ev_s
 
 
-def run_jacobi_graph(jacc, torch, u0, K, steps, warmup, tile=16, per_graph=2):
+def run_jacobi_graph(jacc, torch, u0, K, steps, warmup, tile=8, per_graph=2):
     """The same partitioned sweeps captured once as a graph of `per_graph`
     steps (the K partitions of a step are tasks of one persistent launch,
     halo rows written through by the producing tiles) and replayed

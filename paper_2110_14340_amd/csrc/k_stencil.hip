@@ -443,8 +443,11 @@ heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t n
 
 // ---------------------------------------------------------------------------
 // Persistent kernel: a fixed grid walks the tiles of all tasks in order
-// (workgroup b takes tiles b, b + grid, b + 2*grid, ...).
+// (workgroup b takes tiles b, b + grid, b + 2*grid, ...).  JONLY: a group of
+// Jacobi tasks only; without the heat bodies the kernel needs fewer
+// registers, so more workgroups are resident at once.
 // ---------------------------------------------------------------------------
+template <bool JONLY>
 __global__ void __launch_bounds__(kPersistentThreads)
 persistent_kernel(const PTask *__restrict__ tasks, int ntasks, int64_t total) {
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
@@ -460,14 +463,14 @@ persistent_kernel(const PTask *__restrict__ tasks, int ntasks, int64_t total) {
         const int64_t local = t - T.tile_begin;
         const int64_t bxi = local % T.gx;
         const int64_t rest = local / T.gx;
-        if (T.kind == JACC_LOOP_JACOBI2D) {
+        if (JONLY || T.kind == JACC_LOOP_JACOBI2D) {
             if (T.vec == 2)
                 jacobi_tile<2>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, T.mir, bxi,
                                rest, threadIdx.x, 0, kPersistentThreads, 1);
             else
                 jacobi_tile<1>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, T.mir, bxi,
                                rest, threadIdx.x, 0, kPersistentThreads, 1);
-        } else {
+        } else if constexpr (!JONLY) {
             const int64_t byi = rest % T.gy, bzi = rest / T.gy;
             if (T.vec == 2)
                 (void)heat_tile<2, false>(T.in, T.out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2],
@@ -613,14 +616,15 @@ bool make_task(const Launch &L, PTask *t) {
 // Workgroups of the persistent kernel that are resident at once on the
 // current device (occupancy x compute units): a larger grid would leave a
 // second, partial generation of workgroups running after the first, with
-// part of the chip idle.  Queried once per device.
+// part of the chip idle.  Queried once per device and kernel variant.
+template <bool JONLY>
 static int64_t persistent_grid_cap() {
     static int64_t cap[64] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
     if (!cap[dev]) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel, kPersistentThreads, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<JONLY>, kPersistentThreads, 0) !=
                 hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu <= 0 ||
             cus <= 0) {
@@ -632,11 +636,16 @@ static int64_t persistent_grid_cap() {
     return cap[dev];
 }
 
-hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, hipStream_t s) {
+hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, bool jacobi_only, hipStream_t s) {
     if (ntasks <= 0 || tiles <= 0) return hipSuccess;
-    const int64_t cap = persistent_grid_cap();
+    const int64_t cap = jacobi_only ? persistent_grid_cap<true>() : persistent_grid_cap<false>();
     const int64_t grid = tiles < cap ? tiles : cap;
-    hipLaunchKernelGGL(persistent_kernel, dim3((unsigned)grid), dim3(kPersistentThreads), 0, s, tasks, ntasks, tiles);
+    if (jacobi_only)
+        hipLaunchKernelGGL(persistent_kernel<true>, dim3((unsigned)grid), dim3(kPersistentThreads), 0, s, tasks, ntasks,
+                           tiles);
+    else
+        hipLaunchKernelGGL(persistent_kernel<false>, dim3((unsigned)grid), dim3(kPersistentThreads), 0, s, tasks,
+                           ntasks, tiles);
     return hipGetLastError();
 }
 

@@ -95,8 +95,9 @@ constexpr int kPersistentThreads = 256;
 bool make_task(const Launch &L, PTask *t);
 
 // Launches the persistent kernel over `ntasks` device task records whose
-// tiles total `tiles`.
-hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, hipStream_t s);
+// tiles total `tiles` (jacobi_only: every task is a Jacobi sweep, which
+// selects the variant without the heat bodies).
+hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, bool jacobi_only, hipStream_t s);
 
 // Number of workgroups the loop's reduction writes partials for (for
 // sizing; <= wg_capacity is required).

@@ -668,15 +668,18 @@ int flush_group(jacc_ctx *c) {
         if (rc) return rc;
     }
     int64_t tiles = 0;
+    bool jacobi_only = true;
     for (auto &t : c->ptasks) {
         t.tile_begin = tiles;
         tiles += t.ntiles;
+        jacobi_only = jacobi_only && t.kind == JACC_LOOP_JACOBI2D;
     }
     if (live(c)) {
         // the table is written to pinned memory now and uploaded once when
         // the batch closes, before the graph first runs
         std::memcpy(B->host_tasks + B->tasks_used, c->ptasks.data(), (size_t)n * sizeof(jk::PTask));
-        HIPCHK(c, jk::launch_persistent(B->dev_tasks + B->tasks_used, n, tiles, c->st[s].s), "persistent kernel launch");
+        HIPCHK(c, jk::launch_persistent(B->dev_tasks + B->tasks_used, n, tiles, jacobi_only, c->st[s].s),
+               "persistent kernel launch");
     }
     B->tasks_used += n;
     B->groups++;
