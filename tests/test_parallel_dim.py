@@ -1,11 +1,26 @@
 """Choice of the parallel dimension of an updated array (Sec. "Division of
 Multidimensional Arrays"): the oracle pinned by the paper's NPB-BT example
 and hand cases, and the library's helper equal to the oracle."""
+import json
+import os
+
 import pytest
 from hypothesis import given, settings, strategies as st
 
 from oracle import plan as P
 from paper_2110_14340_amd import jacc
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "npb_bt_lhsY_parallel_dim.json")
+
+
+def test_golden_npb_bt_fixture():
+    g = json.load(open(GOLDEN))
+    par = [sum(1 for it in d if it in g["parallel_iterators"]) for d in g["dims_index_iterators"]]
+    seq = [sum(1 for it in d if it in g["sequential_iterators"]) for d in g["dims_index_iterators"]]
+    assert P.parallel_dim(par, seq) == g["expected_dim_row_major"]
+    assert P.parallel_dim(par, seq, column_major=True) == g["expected_dim_column_major"]
+    assert jacc.parallel_dim(par, seq) == g["expected_dim_row_major"]
 
 
 def test_npb_bt_example_chooses_the_i_dimension():
