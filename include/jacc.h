@@ -135,7 +135,9 @@ typedef struct {
     int64_t lo[3], hi[3];
 } jacc_bounds;
 
-/* Launch configuration.  Never changes the arithmetic of any loop body.
+/* Launch configuration.  Never changes the arithmetic of a loop body's
+ * outputs (fields are bit-identical under every configuration); the order in
+ * which a reduction adds its terms does depend on it.
  *   bx, by     workgroup shape in threads (bx a multiple of 64; bx*by <= 1024)
  *   tile       rows (2-D) or planes (3-D) each thread marches through;
  *              GEMM: k-slab depth staged through LDS, 16 or 32 (with bx =
