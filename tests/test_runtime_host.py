@@ -290,17 +290,20 @@ def test_error_statuses():
 
 def test_allocator_failure_returns_alloc():
     class Failing:
-        def __init__(self):
+        def __init__(self, limit):
             self.n = 0
+            self.limit = limit
             self._a = jacc.Allocator.ALLOC(self._alloc)
             self._f = jacc.Allocator.FREE(lambda p, u: None)
             self.struct = jacc.Allocator(self._a, self._f, None)
 
         def _alloc(self, nbytes, user):
             self.n += 1
-            return None if self.n > 3 else 4096 * self.n
+            return None if self.n > self.limit else 4096 * self.n
 
-    c = jacc.Context(2, allocator=Failing(), flags=DRY)
+    probe = Failing(1 << 30)  # counts the context's own allocations
+    jacc.Context(2, allocator=probe, flags=DRY).close()
+    c = jacc.Context(2, allocator=Failing(probe.n), flags=DRY)
     a = np.zeros((10, 4))
     assert c.enter(a, raw=True) == jacc.ERR_ALLOC
     assert c.close() == jacc.OK
