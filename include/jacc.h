@@ -141,7 +141,8 @@ typedef struct {
  *   bx, by     workgroup shape in threads (bx a multiple of 64; bx*by <= 1024)
  *   tile       rows (2-D) or planes (3-D) each thread marches through;
  *              GEMM: k-slab depth staged through LDS, 16 or 32 (with bx =
- *              256 or 512 threads per 128x128 tile)
+ *              256 or 512 threads per 128x128 tile); SPMV_CSR: lanes per
+ *              row, 4, 8 or 16 (order 2 = non-temporal col/val loads)
  *   vec        1 or 2 consecutive FP64 elements per lane (2 needs an even row
  *              length)
  *   persistent 1 = run the loop inside the batched persistent kernel

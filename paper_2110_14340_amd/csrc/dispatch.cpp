@@ -41,9 +41,11 @@ Cfg default_config(int kind, const Launch &L, Cfg c) {
         default:
             if (!c.bx) c.bx = kind == JACC_LOOP_GEMM ? 512 : 256;  // GEMM: 8 waves of 64x32 measured faster
             if (!c.by) c.by = 1;
-            if (!c.tile) c.tile = kind == JACC_LOOP_GEMM ? 16 : 1;  // GEMM: 16-deep slabs measured faster
+            // measured: GEMM 16-deep slabs; SpMV 16 lanes per row (one gather
+            // per lane for ~16 non-zeros) with non-temporal col/val loads
+            if (!c.tile) c.tile = kind == JACC_LOOP_GEMM ? 16 : kind == JACC_LOOP_SPMV_CSR ? 16 : 1;
             if (!c.vec) c.vec = 1;
-            if (!c.order) c.order = 1;
+            if (!c.order) c.order = kind == JACC_LOOP_SPMV_CSR ? 2 : 1;
             if (!c.march) c.march = 1;
             if (!c.rows) c.rows = 1;
             break;
@@ -71,8 +73,9 @@ int check_config(const Launch &L) {
         case JACC_LOOP_GEMM:
             // k-slab depth and workgroup size; other fields are ignored
             return ((c.tile == 16 || c.tile == 32) && (c.bx == 256 || c.bx == 512)) ? 0 : 1;
-        case JACC_LOOP_SUM:
         case JACC_LOOP_SPMV_CSR:
+            return ((c.tile == 4 || c.tile == 8 || c.tile == 16) && (c.order == 1 || c.order == 2)) ? 0 : 1;
+        case JACC_LOOP_SUM:
         case JACC_LOOP_SCATTER_SQ:
             return 0;  // fixed internal configurations; fields are ignored
         default:

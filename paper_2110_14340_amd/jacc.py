@@ -336,10 +336,10 @@ class Context:
         b = bounds((0, C.shape[0]), (0, C.shape[1]))
         return self.loop(GEMM, b, [(A, READ, 0, 0, 0), (B, READ, 0, 0, 1), (C, WRITE, 0, 0, 0)], cfg=cfg, raw=raw)
 
-    def spmv(self, rp, col, val, x, y, raw=False):
+    def spmv(self, rp, col, val, x, y, cfg=None, raw=False):
         b = bounds((0, y.shape[0]))
         return self.loop(SPMV_CSR, b, [(rp, READ, 0, 1, 0), (col, READ, 0, 0, 1), (val, READ, 0, 0, 1),
-                                       (x, READ, 0, 0, 1), (y, WRITE, 0, 0, 0)], raw=raw)
+                                       (x, READ, 0, 0, 1), (y, WRITE, 0, 0, 0)], cfg=cfg, raw=raw)
 
     def scatter_sq(self, x, idx, out, rows=None, raw=False):
         """out[idx[i]] = x[i]^2 with writes filtered to each partition's rows."""

@@ -100,7 +100,7 @@ def test_gemm_4096_sampled_rows():
 
 
 # ------------------------------------------------------------------ SpMV
-def _spmv_dev(rp, col, val, x, K):
+def _spmv_dev(rp, col, val, x, K, cfg=None):
     y = np.zeros(rp.size - 1)
     with context(K) as c:
         c.enter(rp, halo=(1, 1))
@@ -108,7 +108,7 @@ def _spmv_dev(rp, col, val, x, K):
         c.enter(val, whole=True)
         c.enter(x, whole=True)
         c.enter(y, clause=jacc.CREATE)
-        c.spmv(rp, col, val, x, y)
+        c.spmv(rp, col, val, x, y, cfg=cfg)
         c.exit(y, jacc.COPYOUT)
     return y
 
@@ -128,7 +128,12 @@ def test_spmv_small(n, K):
     assert np.all(np.abs(y - ref) <= 1e-13 * _row_bound(rp, col, val, x))
     rpi, coli, vali, _ = inputs.csr_matrix(n, n, 16, seed=9, integer_values=True)
     xi = inputs.int_valued(n, seed=10, lo=-10, hi=10)
-    assert np.array_equal(_spmv_dev(rpi, coli, vali, xi, K), oracle.spmv_csr(rpi, coli, vali, xi))
+    ref_i = oracle.spmv_csr(rpi, coli, vali, xi)
+    assert np.array_equal(_spmv_dev(rpi, coli, vali, xi, K), ref_i)
+    for lanes, order in ((4, 1), (16, 1), (8, 2), (4, 2)):  # lanes per row; non-temporal col/val loads
+        cfg = jacc.config(tile=lanes, order=order)
+        assert np.all(np.abs(_spmv_dev(rp, col, val, x, K, cfg) - ref) <= 1e-13 * _row_bound(rp, col, val, x))
+        assert np.array_equal(_spmv_dev(rpi, coli, vali, xi, K, cfg), ref_i)
 
 
 def test_spmv_2_22_rows_k1_k4():
