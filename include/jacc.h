@@ -287,7 +287,11 @@ const char *jacc_last_error(const jacc_ctx *ctx);
  * plan issues the same copies, waits and launches, the graph is replay-safe
  * and jacc_batch_launch may replay it `repeats` more times (otherwise it
  * returns JACC_ERR_UNSUPPORTED).  Every launch joins all streams into
- * stream 0 before the graph and forks them after it. */
+ * stream 0 before the graph and forks them after it.  A graph addresses the
+ * device slabs of the arrays its loops use: once one of those arrays leaves
+ * the data region (jacc_data_exit down to a reference count of zero), the
+ * graph is stale and jacc_batch_launch / jacc_batch_time return
+ * JACC_ERR_INVALID for it (re-entering the array does not revive it). */
 int jacc_batch_begin(jacc_ctx *ctx);
 int jacc_batch_end(jacc_ctx *ctx, int *graph_id);
 int jacc_batch_launch(jacc_ctx *ctx, int graph_id, int repeats);
@@ -309,6 +313,21 @@ int jacc_batch_time(jacc_ctx *ctx, int graph_id, int warmup, int reps, double *m
 int jacc_time_loop(jacc_ctx *ctx, int kind, const jacc_bounds *bounds, int nargs, const jacc_arg *args,
                    const double *scalars, int nscalars, const jacc_config *cfg, int warmup, int reps,
                    double *ms);
+
+/* One timed execution of a loop call, split into its parts (the measurement
+ * the adaptive rule of Sec. "Adaptive Utilization" takes: the kernel time of
+ * a partition and the communication around it).  *step_ms receives the time
+ * from a start event on stream 0 (every partition stream waits for it) to
+ * the join of all partition streams into stream 0; kernel_ms[p], p <
+ * nkernel (at most 64), the time of partition p's kernel alone, from HIP
+ * events recorded on its stream right before and right after its launch
+ * (after the copies and waits it needed), or 0 when partition p has no
+ * iterations.  Stencil loops are not split into interior and edge launches
+ * here.  JACC_ERR_UNSUPPORTED for persistent configurations and in dry-run
+ * contexts. */
+int jacc_time_loop_parts(jacc_ctx *ctx, int kind, const jacc_bounds *bounds, int nargs, const jacc_arg *args,
+                         const double *scalars, int nscalars, const jacc_config *cfg, double *step_ms,
+                         double *kernel_ms, int nkernel);
 
 /* Device pointer of partition p's slab of the array containing `host`, and
  * the slab's first and one-past-last rows.  For callers that run their own
@@ -398,17 +417,21 @@ const char *jacc_version(void);
  * A per-loop policy record, host memory only, independent of any context.
  * It starts in JACC_ADAPT_DUPLICATE (the whole loop on one device, no
  * exchange).  jacc_adapt_observe feeds one execution of the loop in the
- * current mode: time_kernel_s (seconds of the loop body; in partitioned mode
- * of one partition), time_comm_s (seconds of the exchange; 0 in duplicate
- * mode) and write_bytes (bytes the loop writes, > 0), and returns the mode
- * for the next execution.
+ * current mode: time_kernel_s (seconds of the loop body: in duplicate mode
+ * the whole loop, in partitioned mode the kernel of one partition — the
+ * longest one when they differ), time_comm_s (seconds of the rest of a
+ * partitioned execution: exchange and synchronisation; 0 in duplicate mode)
+ * and write_bytes (bytes the loop writes, > 0), and returns the mode for the
+ * next execution.
  *   duplicate: the first observation is a warm-up and ignored; later ones
  *     add time/WriteSize to eff_dup (mean seconds per byte) and count Eq. 1,
  *     t_k > t_k/n + WriteSize/peak; at five the mode becomes PARTITION.
  *   partition: Eq. 2, t_k + t_c > n*t_k, and Eq. 3, t_k + t_c > eff_dup *
  *     WriteSize, are counted; when either has held five times and the mean,
- *     over the violating executions, of (t_k + t_c) minus the smaller right
- *     side is positive, the mode becomes DUPLICATE_FINAL and stays there.
+ *     over every partitioned execution since the switch, of (t_k + t_c)
+ *     minus the smaller right side is above zero, the mode becomes
+ *     DUPLICATE_FINAL and stays there.  (Executions faster than both bounds
+ *     lower that mean, so violations alone do not switch a loop off.)
  * n_parts >= 1 is the partition (device) count, peak_bytes_per_s > 0 the
  * bandwidth of one link between partitions.  Returns JACC_ERR_INVALID on bad
  * arguments, JACC_ERR_ALLOC if the record cannot be allocated.  The record
@@ -422,6 +445,9 @@ int jacc_adapt_observe(jacc_adapt *a, double time_kernel_s, double time_comm_s, 
  * = {profiled duplicate runs, Eq. 1 hits, Eq. 2 hits, Eq. 3 hits, violating
  * partitioned runs}; any output pointer may be NULL. */
 int jacc_adapt_state(const jacc_adapt *a, int *mode, double *eff_dup, long long *counts);
+/* Mean of (t_k + t_c) - min(n*t_k, eff_dup*WriteSize) over the partitioned
+ * executions observed so far (0 before any), and their number. */
+int jacc_adapt_mean_diff(const jacc_adapt *a, double *mean_diff, long long *n_partitioned);
 
 /* ---- parallel dimension of an updated array (Sec. "Division of
  * Multidimensional Arrays") ----------------------------------------------------

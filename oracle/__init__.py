@@ -82,6 +82,17 @@ def lib():
         L.oracle_scatter_sq.restype = None
         L.oracle_scatter_sq_partitioned.argtypes = [_f64p, _i32p, _f64p, _i64, _i64, _i64, ctypes.c_int]
         L.oracle_scatter_sq_partitioned.restype = ctypes.c_int
+        L.oracle_threads.argtypes = [ctypes.c_int]
+        L.oracle_threads.restype = ctypes.c_int
+        L.oracle_jacobi2d_mt.argtypes = [_f64p, _f64p, _i64, _i64, _i64, ctypes.c_int]
+        L.oracle_jacobi2d_mt.restype = ctypes.c_int
+        L.oracle_heat3d_mt.argtypes = [_f64p, _f64p, _i64, _i64, _i64, _i64, ctypes.c_double, _f64p,
+                                       ctypes.c_int]
+        L.oracle_heat3d_mt.restype = ctypes.c_int
+        L.oracle_gemm_mt.argtypes = [_f64p, _f64p, _f64p, _i64, _i64, _i64, ctypes.c_int]
+        L.oracle_gemm_mt.restype = None
+        L.oracle_spmv_csr_mt.argtypes = [_i32p, _i32p, _f64p, _f64p, _f64p, _i64, _i64, ctypes.c_int]
+        L.oracle_spmv_csr_mt.restype = None
         _lib = L
     return _lib
 
@@ -235,3 +246,52 @@ def scatter_sq_partitioned(inp, idx, out, K, rows=None):
     lo, hi = rows if rows is not None else (0, inp.size)
     assert lib().oracle_scatter_sq_partitioned(inp, idx, o, o.size, lo, hi, K) == 0
     return o
+
+
+# --------------------------------------------------------------------------
+# Multi-threaded full-grid forms (same per-element arithmetic; fields and
+# products bit-identical to the sequential routines, the heat residual a
+# per-plane compensated order of the same terms).  threads <= 0: the OpenMP
+# default (OMP_NUM_THREADS, else every core).
+# --------------------------------------------------------------------------
+def threads(requested=0):
+    """Threads the multi-threaded routines run with for a request."""
+    return lib().oracle_threads(int(requested))
+
+
+def jacobi2d_mt(u0, steps, threads=0):
+    a = _c(u0).copy()
+    b = a.copy()
+    which = lib().oracle_jacobi2d_mt(a, b, a.shape[0], a.shape[1], steps, int(threads))
+    return a if which == 0 else b
+
+
+def heat3d_mt(u0, steps, alpha, threads=0):
+    a = _c(u0).copy()
+    b = a.copy()
+    res = np.zeros(max(steps, 1), dtype=np.float64)
+    which = lib().oracle_heat3d_mt(a, b, *a.shape, steps, alpha, res, int(threads))
+    assert which >= 0
+    return (a if which == 0 else b), res[:steps]
+
+
+def gemm_mt(A, B, threads=0):
+    A = _c(A)
+    B = _c(B)
+    M, L = A.shape
+    L2, N = B.shape
+    assert L == L2
+    C = np.empty((M, N), dtype=np.float64)
+    lib().oracle_gemm_mt(A, B, C, M, N, L, int(threads))
+    return C
+
+
+def spmv_csr_mt(rp, col, val, x, threads=0):
+    rp = _c(rp, np.int32)
+    col = _c(col, np.int32)
+    val = _c(val)
+    x = _c(x)
+    n = rp.size - 1
+    y = np.zeros(n, dtype=np.float64)
+    lib().oracle_spmv_csr_mt(rp, col, val, x, y, 0, n, int(threads))
+    return y

@@ -8,9 +8,13 @@ Readings (the paper's text is ambiguous here):
   write size to obtain a time, so it is the mean of time/WriteSize over the
   profiled duplicate runs (the warm-up run excluded).
 * "five executions" are counted cumulatively (not consecutively).
-* the switch-off average is taken over the partitioned executions that
-  violated Eq. 2 or Eq. 3, of (t_k + t_c) minus the smaller of the two
-  right sides; once switched off the loop stays duplicated.
+* the switch-off average is taken over every partitioned execution since
+  the switch to partitioned mode, of (t_k + t_c) minus the smaller of the two
+  right sides (n * t_k and eff_dup * WriteSize); so runs that beat both
+  bounds pull it below zero and can keep the loop partitioned even after
+  five violations.  Once switched off the loop stays duplicated.
+* t_k is the kernel time of one partition and t_c the rest of the
+  partitioned execution (exchange and synchronisation).
 
 Parity pinned by hand-computed streams in tests/test_adapt.py.
 """
@@ -26,7 +30,7 @@ def run(observations, n, peak):
     ratios = []          # time / WriteSize of profiled duplicate runs
     eq1_hits = 0
     eq2_hits = eq3_hits = 0
-    diffs = []           # left - min(right) of violating partitioned runs
+    diffs = []           # left - min(right) of every partitioned run
     out = []
     for tk, tc, ws in observations:
         if mode == PARTITION:
@@ -38,8 +42,7 @@ def run(observations, n, peak):
                 eq2_hits += 1
             if left > right3:
                 eq3_hits += 1
-            if left > right2 or left > right3:
-                diffs.append(left - min(right2, right3))
+            diffs.append(left - min(right2, right3))
             if (eq2_hits >= 5 or eq3_hits >= 5) and sum(diffs) / len(diffs) > 0:
                 mode = DUPLICATE_FINAL
         elif not warmed:

@@ -26,6 +26,7 @@
  * pairwise sums, explicit 7-point heat step u + alpha*lap).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -475,4 +476,68 @@ int oracle_scatter_sq_partitioned(const double *in, const int32_t *idx, double *
         free(mine);
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Multi-threaded forms of the full-grid runs, for full-size references and  */
+/* the all-core CPU timing.  Threads split the rows (planes) of each sweep;  */
+/* every element is computed by the same expression as in the sequential     */
+/* routine and no element's arithmetic depends on which thread runs it, so   */
+/* the fields are bit-identical to oracle_jacobi2d / oracle_heat3d /         */
+/* oracle_gemm.  nthreads <= 0 takes the OpenMP default.                     */
+/* ------------------------------------------------------------------------ */
+static int team(int nthreads) { return nthreads > 0 ? nthreads : omp_get_max_threads(); }
+
+/* Threads a multi-threaded routine uses for a given request. */
+int oracle_threads(int nthreads) { return team(nthreads); }
+
+int oracle_jacobi2d_mt(double *a, double *b, int64_t ny, int64_t nx, int64_t steps, int nthreads)
+{
+    double *src = a, *dst = b;
+    for (int64_t t = 0; t < steps; ++t) {
+#pragma omp parallel for schedule(static) num_threads(team(nthreads))
+        for (int64_t i = 1; i < ny - 1; ++i)
+            oracle_jacobi2d_sweep(src, dst, ny, nx, i, i + 1, 1, nx - 1);
+        double *tmp = src; src = dst; dst = tmp;
+    }
+    return src == a ? 0 : 1;
+}
+
+/* The residual of a step is formed per plane (a compensated sum over the
+ * plane's interior cells in x-fastest order), and the plane sums are then
+ * added in plane order with compensation.  The field is bit-identical to
+ * oracle_heat3d; the residual is another correctly compensated summation
+ * order of the same terms (within a few units in the last place of it). */
+int oracle_heat3d_mt(double *a, double *b, int64_t nz, int64_t ny, int64_t nx, int64_t steps,
+                     double alpha, double *residuals, int nthreads)
+{
+    double *plane_sum = malloc((size_t)(nz > 0 ? nz : 1) * sizeof(double));
+    if (!plane_sum) return -1;
+    double *src = a, *dst = b;
+    for (int64_t t = 0; t < steps; ++t) {
+#pragma omp parallel for schedule(static) num_threads(team(nthreads))
+        for (int64_t z = 1; z < nz - 1; ++z)
+            oracle_heat3d_sweep(src, dst, nz, ny, nx, z, z + 1, 1, ny - 1, 1, nx - 1, alpha, &plane_sum[z]);
+        if (residuals) {
+            neum_t acc = {0.0, 0.0};
+            for (int64_t z = 1; z < nz - 1; ++z) neum_add(&acc, plane_sum[z]);
+            residuals[t] = neum_value(&acc);
+        }
+        double *tmp = src; src = dst; dst = tmp;
+    }
+    free(plane_sum);
+    return src == a ? 0 : 1;
+}
+
+void oracle_gemm_mt(const double *A, const double *B, double *C, int64_t M, int64_t N, int64_t L, int nthreads)
+{
+#pragma omp parallel for schedule(dynamic, 8) num_threads(team(nthreads))
+    for (int64_t i = 0; i < M; ++i) oracle_gemm_rows(A, B, C + i * N, N, L, i, i + 1);
+}
+
+void oracle_spmv_csr_mt(const int32_t *rp, const int32_t *col, const double *val, const double *x, double *y,
+                        int64_t row_lo, int64_t row_hi, int nthreads)
+{
+#pragma omp parallel for schedule(static, 4096) num_threads(team(nthreads))
+    for (int64_t i = row_lo; i < row_hi; ++i) oracle_spmv_csr(rp, col, val, x, y, i, i + 1);
 }

@@ -10,9 +10,11 @@
 // mode.  In partitioned mode each observation (kernel time of a partition,
 // exchange time) is tested against Eq. 2, t_k + t_c > n * t_k, and Eq. 3,
 // t_k + t_c > eff_dup * WriteSize; once either has held five times and the
-// mean, over the executions that violated one of them, of the left side
+// mean, over every partitioned execution since the switch, of the left side
 // minus the smaller right side is above zero, the loop returns to duplicate
-// mode for good.
+// mode for good.  Executions that beat both bounds contribute negative
+// differences, so a loop that is mostly faster partitioned stays partitioned
+// through occasional violations.
 //
 // Host-only bookkeeping; it launches nothing and allocates one small record.
 #include <cmath>
@@ -25,7 +27,7 @@ struct jacc_adapt {
     double peak = 0.0;
     int mode = JACC_ADAPT_DUPLICATE;
     bool warmed = false;
-    long long n_dup = 0, n_eq1 = 0, c2 = 0, c3 = 0, n_viol = 0;
+    long long n_dup = 0, n_eq1 = 0, c2 = 0, c3 = 0, n_viol = 0, n_part = 0;
     double sum_ratio = 0.0, sum_diff = 0.0;
 };
 
@@ -60,11 +62,10 @@ int jacc_adapt_observe(jacc_adapt *a, double time_kernel_s, double time_comm_s, 
         const bool v2 = left > r2, v3 = left > r3;
         if (v2) ++a->c2;
         if (v3) ++a->c3;
-        if (v2 || v3) {
-            ++a->n_viol;
-            a->sum_diff += left - (r2 < r3 ? r2 : r3);
-        }
-        if ((a->c2 >= 5 || a->c3 >= 5) && a->sum_diff / (double)a->n_viol > 0.0) a->mode = JACC_ADAPT_DUPLICATE_FINAL;
+        if (v2 || v3) ++a->n_viol;
+        ++a->n_part;
+        a->sum_diff += left - (r2 < r3 ? r2 : r3);
+        if ((a->c2 >= 5 || a->c3 >= 5) && a->sum_diff / (double)a->n_part > 0.0) a->mode = JACC_ADAPT_DUPLICATE_FINAL;
     } else if (!a->warmed) {
         a->warmed = true;  // the warm-up run is not profiled
     } else if (a->mode == JACC_ADAPT_DUPLICATE) {
@@ -88,6 +89,13 @@ int jacc_adapt_state(const jacc_adapt *a, int *mode, double *eff_dup, long long 
         counts[3] = a->c3;
         counts[4] = a->n_viol;
     }
+    return JACC_OK;
+}
+
+int jacc_adapt_mean_diff(const jacc_adapt *a, double *mean_diff, long long *n_partitioned) {
+    if (!a) return JACC_ERR_INVALID;
+    if (mean_diff) *mean_diff = a->n_part ? a->sum_diff / (double)a->n_part : 0.0;
+    if (n_partitioned) *n_partitioned = a->n_part;
     return JACC_OK;
 }
 

@@ -229,6 +229,10 @@ struct Batch {
     std::vector<LoopCall> calls;
     std::vector<jacc_trace_op> captured;  // ops planned while capturing
     bool replay_safe = false;
+    // arrays whose device slabs the graph's nodes address; when one of them
+    // leaves the data region the graph is stale and is never replayed again
+    std::vector<int> array_ids;
+    bool stale = false;
     jk::PTask *dev_tasks = nullptr;   // kTaskCapacity device task records
     jk::PTask *host_tasks = nullptr;  // pinned staging of the same size
     int tasks_used = 0;
@@ -281,6 +285,11 @@ struct jacc_ctx {
     std::vector<PendingAccess> paccs;
     std::vector<Array *> parrays;
     hipEvent_t fork_ev = nullptr, t0 = nullptr, t1 = nullptr;
+    // per-partition kernel timing (jacc_time_loop_parts): events around each
+    // partition's launch; kev[2p] before, kev[2p+1] after
+    bool time_parts = false;
+    std::vector<hipEvent_t> kev;
+    uint64_t kev_used = 0;  // bit p: partition p launched in the timed call
     // fault injection (tests): fail the n-th op of a kind
     int fault_kind = 0;  // 1 copy, 2 launch
     int64_t fault_n = -1, fault_count = 0;
@@ -923,6 +932,9 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
         if (rc) return rc;
     }
     if (c->cur && !c->plan_only) {
+        for (int i = 0; i < nargs; ++i)
+            if (std::find(c->cur->array_ids.begin(), c->cur->array_ids.end(), arr[i]->id) == c->cur->array_ids.end())
+                c->cur->array_ids.push_back(arr[i]->id);
         LoopCall lc;
         lc.kind = kind;
         lc.b = *b;
@@ -984,7 +996,7 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     int64_t part_cells = L.part_rows;
     for (int d = 1; d < b->ndim; ++d) part_cells *= std::max<int64_t>(0, b->hi[d] - b->lo[d]);
     const bool auto_split = K <= 4 && !c->no_split && part_cells >= ((int64_t)1 << 22);
-    const bool split = (c->split || auto_split) && !want_red && !persistent && !one_stream && K > 1 &&
+    const bool split = (c->split || auto_split) && !c->time_parts && !want_red && !persistent && !one_stream && K > 1 &&
                        !(args[primary].mode & JACC_FILTERED) &&
                        (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D);
     if (split) {
@@ -1117,7 +1129,13 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             c->status = JACC_ERR_DEVICE;
             return set_err(c, JACC_ERR_DEVICE, "injected fault in launch %lld", (long long)c->fault_count);
         }
+        const bool timed = c->time_parts && live(c) && p < kMaxK;
+        if (timed) HIPCHK(c, hipEventRecord(c->kev[2 * p], c->st[s].s), "hipEventRecord");
         if (live(c)) HIPCHK(c, jk::launch_loop(LP, c->st[s].s), "kernel launch");
+        if (timed) {
+            HIPCHK(c, hipEventRecord(c->kev[2 * p + 1], c->st[s].s), "hipEventRecord");
+            c->kev_used |= (uint64_t)1 << p;
+        }
         c->st[s].seq++;
         trace(c, JACC_OP_KERNEL, s, -1, -1, p, kind, pp.iters.lo, pp.iters.hi, c->st[s].seq);
         rc = post_op(c);
@@ -1369,6 +1387,8 @@ int jacc_finalize(jacc_ctx *c) {
                 if (S.join_ev) (void)hipEventDestroy(S.join_ev);
                 if (c->own_streams && S.s) (void)hipStreamDestroy(S.s);
             }
+            for (hipEvent_t e : c->kev)
+                if (e) (void)hipEventDestroy(e);
             if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
             if (c->t0) (void)hipEventDestroy(c->t0);
             if (c->t1) (void)hipEventDestroy(c->t1);
@@ -1476,6 +1496,8 @@ int jacc_data_exit(jacc_ctx *c, void *host, int clause) {
         if (--A->refs > 0) return JACC_OK;
         rc = sync_all(c);
         if (rc) return rc;
+        for (Batch *B : c->batches)
+            if (B && std::find(B->array_ids.begin(), B->array_ids.end(), A->id) != B->array_ids.end()) B->stale = true;
         c->present.erase(A->host);
         free_array(c, A);
         return JACC_OK;
@@ -1640,6 +1662,8 @@ int jacc_batch_launch(jacc_ctx *c, int graph_id, int repeats) {
         return set_err(c, JACC_ERR_INVALID, "unknown graph %d", graph_id);
     if (repeats < 0) return set_err(c, JACC_ERR_INVALID, "negative repeats");
     Batch *B = c->batches[graph_id];
+    if (B->stale)
+        return set_err(c, JACC_ERR_INVALID, "graph %d uses an array that has left the data region", graph_id);
     if (!B->replay_safe)
         return set_err(c, JACC_ERR_UNSUPPORTED, "graph %d is not replay-safe (a later pass plans other copies)",
                        graph_id);
@@ -1654,7 +1678,7 @@ int jacc_batch_info(jacc_ctx *c, int graph_id, int *loops, int *persistent_group
     Batch *B = c->batches[graph_id];
     if (loops) *loops = (int)B->calls.size();
     if (persistent_groups) *persistent_groups = B->groups;
-    if (replay_safe) *replay_safe = B->replay_safe ? 1 : 0;
+    if (replay_safe) *replay_safe = (B->replay_safe && !B->stale) ? 1 : 0;
     return JACC_OK;
 }
 
@@ -1747,6 +1771,53 @@ int jacc_time_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const
         }
         return JACC_OK;
     } catch (...) {
+        return set_err(c, JACC_ERR_INVALID, "internal error");
+    }
+}
+
+int jacc_time_loop_parts(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc_arg *args,
+                         const double *scalars, int nscalars, const jacc_config *cfg, double *step_ms,
+                         double *kernel_ms, int nkernel) {
+    GUARD(c);
+    if (c->dry) return set_err(c, JACC_ERR_UNSUPPORTED, "timing needs the device");
+    if (c->cur) return set_err(c, JACC_ERR_INVALID, "timing inside an open batch");
+    if (!step_ms || nkernel < 0 || (nkernel && !kernel_ms) || nkernel > kMaxK)
+        return set_err(c, JACC_ERR_INVALID, "bad timing outputs");
+    if (cfg && cfg->persistent) return set_err(c, JACC_ERR_UNSUPPORTED, "per-partition timing of a persistent loop");
+    try {
+        if (c->kev.empty()) {
+            c->kev.assign(2 * kMaxK, nullptr);
+            for (auto &e : c->kev) HIPCHK(c, hipEventCreate(&e), "hipEventCreate");
+        }
+        const int slot = kind == JACC_LOOP_SUM ? kSlots - 2 : -1;
+        int rc = join_into0(c);
+        if (rc) return rc;
+        HIPCHK(c, hipEventRecord(c->t0, c->st[0].s), "hipEventRecord");
+        rc = fork_from0(c);
+        if (rc) return rc;
+        assume_joined(c);
+        c->time_parts = true;
+        c->kev_used = 0;
+        rc = loop_impl(c, kind, b, nargs, args, scalars, nscalars, slot, nullptr, cfg);
+        c->time_parts = false;
+        if (rc) return rc;
+        rc = join_into0(c);
+        if (rc) return rc;
+        HIPCHK(c, hipEventRecord(c->t1, c->st[0].s), "hipEventRecord");
+        HIPCHK(c, hipEventSynchronize(c->t1), "hipEventSynchronize");
+        float f = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&f, c->t0, c->t1), "hipEventElapsedTime");
+        *step_ms = f;
+        for (int p = 0; p < nkernel; ++p) {
+            kernel_ms[p] = 0.0;
+            if (!(c->kev_used >> p & 1)) continue;
+            HIPCHK(c, hipEventElapsedTime(&f, c->kev[2 * p], c->kev[2 * p + 1]), "hipEventElapsedTime");
+            kernel_ms[p] = f;
+        }
+        assume_joined(c);
+        return JACC_OK;
+    } catch (...) {
+        c->time_parts = false;
         return set_err(c, JACC_ERR_INVALID, "internal error");
     }
 }

@@ -111,6 +111,9 @@ def lib():
     L.jacc_time_loop.argtypes = [vp, i32, ctypes.POINTER(Bounds), i32, ctypes.POINTER(Arg),
                                  ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(Config), i32, i32,
                                  ctypes.POINTER(ctypes.c_double)]
+    L.jacc_time_loop_parts.argtypes = [vp, i32, ctypes.POINTER(Bounds), i32, ctypes.POINTER(Arg),
+                                       ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(Config),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), i32]
     fp = ctypes.POINTER(ctypes.c_float)
     L.jacc_model_nparams.argtypes = [i32]
     L.jacc_model_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
@@ -130,6 +133,7 @@ def lib():
     L.jacc_adapt_destroy.argtypes = [vp]
     L.jacc_adapt_observe.argtypes = [vp, d, d, d, ctypes.POINTER(i32)]
     L.jacc_adapt_state.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)]
+    L.jacc_adapt_mean_diff.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)]
     L.jacc_parallel_dim.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
     _lib = L
     return L
@@ -390,6 +394,24 @@ class Context:
         self._check(st)
         return out
 
+    def time_loop_parts(self, kind, bnds, args, scalars=(), cfg=None, nparts=None, raw=False):
+        """One timed run of a loop call: (step ms, per-partition kernel ms)."""
+        n = len(args)
+        A = (Arg * n)()
+        for i, (a, mode, lo, hi, whole) in enumerate(args):
+            A[i] = Arg(self._ptr(a), mode, lo, hi, int(whole))
+        S = (ctypes.c_double * max(1, len(scalars)))(*scalars)
+        nk = self.K if nparts is None else nparts
+        ker = np.zeros(max(1, nk), dtype=np.float64)
+        step = ctypes.c_double(0.0)
+        st = self.L.jacc_time_loop_parts(self.ctx, kind, ctypes.byref(bnds), n, A, S, len(scalars),
+                                         ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(step),
+                                         ker.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nk)
+        if raw:
+            return st
+        self._check(st)
+        return step.value, ker[:nk]
+
     # -- sync / reductions -----------------------------------------------------
     def wait(self):
         return self._check(self.L.jacc_wait(self.ctx))
@@ -547,6 +569,13 @@ class Adaptive:
         self.L.jacc_adapt_state(self.h, ctypes.byref(m), ctypes.byref(e), cnt)
         return {"mode": m.value, "eff_dup": e.value, "n_dup": cnt[0], "eq1": cnt[1], "eq2": cnt[2], "eq3": cnt[3],
                 "violations": cnt[4]}
+
+    def mean_diff(self):
+        """(mean of (t_k + t_c) - min(right sides) over the partitioned runs, their count)."""
+        m = ctypes.c_double(0.0)
+        n = ctypes.c_longlong(0)
+        self.L.jacc_adapt_mean_diff(self.h, ctypes.byref(m), ctypes.byref(n))
+        return m.value, n.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -33,12 +33,12 @@ def run_jacobi(u0, steps, K, cfg=None, ctx_flags=0):
     return src
 
 
-def run_heat(u0, steps, alpha, K, cfg=None):
+def run_heat(u0, steps, alpha, K, cfg=None, ctx_flags=0):
     """T heat steps with the fused residual into slots 0..T-1; returns
     (final field, residuals)."""
     a = np.ascontiguousarray(u0, dtype=np.float64).copy()
     b = a.copy()
-    with context(K) as c:
+    with context(K, ctx_flags) as c:
         c.enter(a, halo=(1, 1))
         c.enter(b, halo=(1, 1))
         src, dst = a, b

@@ -35,16 +35,35 @@ def test_eq1_hits_are_cumulative_not_consecutive():
     assert A.run(obs, 8, PEAK) == [0, 0, 0, 0, 0, 0, 0, 0, 1]
 
 
-def test_switches_off_after_five_eq3_violations():
-    ws = 1 << 20
-    dup = (1e-3, 0.0, ws)       # eff_dup = 1e-3 / 2^20 s/B; Eq. 1 holds for n = 4
-    slow = (4e-4, 7e-4, ws)     # left 1.1e-3 > eff_dup*ws = 1e-3 (Eq. 3), < 4*4e-4 (Eq. 2)
-    fast = (3e-4, 1e-4, ws)     # left 4e-4: neither
-    obs = [dup] * 6 + [slow, fast, slow, slow, fast, slow, slow, fast]
+# Dyadic times (units of 2^-13 s, WriteSize 2^20 B) keep every sum exact.
+_W = float(1 << 20)
+_u = 2.0 ** -13
+_DUP = (8 * _u, 0.0, _W)                       # eff_dup * WriteSize = 8u; Eq. 1 holds for n = 4
+_SLOW = (4 * _u, 5 * _u, _W)                   # left 9u > 8u (Eq. 3), < n*t_k = 16u: difference +1u
+_FAST = (4 * _u, 0.0, _W)                      # left 4u: neither; difference 4u - 8u = -4u
+_FASTISH = (4 * _u, 3 * _u, _W)                # left 7u: neither; difference -1u
+
+
+def test_switches_off_after_five_eq3_violations_with_positive_mean():
+    obs = [_DUP] * 6 + [_SLOW, _FASTISH, _SLOW, _SLOW, _FASTISH, _SLOW, _SLOW, _FAST]
     modes = A.run(obs, 4, 1e12)
     assert modes[:6] == [0, 0, 0, 0, 0, 1]
-    assert modes[6:13] == [1, 1, 1, 1, 1, 1, 2]
+    # five violations at the thirteenth observation; mean (5 - 2)/7 u > 0
+    assert modes[6:12] == [1] * 6 and modes[12] == 2
     assert modes[13] == 2  # stays duplicated
+
+
+def test_five_violations_with_nonpositive_mean_stay_partitioned():
+    """The switch-off needs both parts of the rule: five violations of Eq. 3
+    occur, but the executions that beat both bounds keep the mean difference
+    at or below zero, so the loop stays partitioned until it turns positive."""
+    obs = [_DUP] * 6 + [_SLOW, _FAST, _SLOW, _SLOW, _FAST, _SLOW, _SLOW]
+    # after them: 5 violations, sum of differences 5u - 8u = -3u
+    more = [_SLOW] * 4  # sums -2u, -1u, 0 (not above zero), +1u
+    modes = A.run(obs + more, 4, 1e12)
+    assert modes[5:13] == [1] * 8
+    assert modes[13:16] == [1, 1, 1]
+    assert modes[16] == 2
 
 
 def test_switch_off_through_eq2_alone():
@@ -83,6 +102,17 @@ def _lib_modes(obs, n, peak):
        obs=st.lists(st.tuples(st.floats(0, 1e-2), st.floats(0, 1e-2), st.floats(1.0, 1e9)), max_size=40))
 def test_library_matches_oracle_on_random_streams(n, peak, obs):
     assert _lib_modes(obs, n, peak) == A.run(obs, n, peak)
+
+
+def test_library_mean_difference_over_partitioned_runs():
+    a = jacc.Adaptive(4, 1e12)
+    for o in [_DUP] * 6 + [_SLOW, _FAST, _SLOW]:
+        a.observe(*o)
+    mean, n = a.mean_diff()
+    assert n == 3 and mean == (1 - 4 + 1) * _u / 3
+    s = a.state()
+    assert s["violations"] == 2 and s["eq3"] == 2 and s["eq2"] == 0
+    a.close()
 
 
 def test_library_state_and_errors():

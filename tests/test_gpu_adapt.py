@@ -1,7 +1,7 @@
 """The adaptive duplicate-vs-partition policy driving real Jacobi sweeps on
 the device: the field is bit-exact against the oracle whatever modes were
 taken, and the library's decisions equal the oracle policy replayed on the
-same measured step times."""
+same measured (kernel, exchange) times."""
 import numpy as np
 import pytest
 
@@ -19,5 +19,28 @@ def test_adaptive_jacobi_bit_exact_and_policy_parity(shape, n, steps, peak):
     out, modes, times = adaptive.jacobi_adaptive(u0, steps, n, peak)
     assert np.array_equal(out, oracle.jacobi2d(u0, steps))
     ws = 8.0 * (shape[0] - 2) * (shape[1] - 2)
-    assert modes == A.run([(t, 0.0, ws) for t in times], n, peak)
-    assert all(t > 0 for t in times)
+    assert modes == A.run([(tk, tc, ws) for tk, tc in times], n, peak)
+    assert all(tk > 0 and tc >= 0 for tk, tc in times)
+    # the duplicate-mode steps report no exchange; a partitioned step's
+    # kernel is one partition's, so it is shorter than the whole step
+    assert all(tc == 0.0 for (tk, tc), m in zip(times, [0] + modes[:-1]) if m != 1)
+
+
+def test_time_loop_parts_partition_kernels_and_step():
+    """Per-partition kernel times are positive for partitions with work and
+    bounded by the step time."""
+    from gpu_util import context
+    from paper_2110_14340_amd import jacc
+    u = inputs.jacobi_grid(1030, 2050, seed=4)
+    v = u.copy()
+    with context(4, jacc.INIT_LAZY) as c:
+        c.enter(u, halo=(1, 1))
+        c.enter(v, halo=(1, 1))
+        b = jacc.bounds((1, 1029), (1, 2049))
+        step, ker = c.time_loop_parts(jacc.JACOBI2D, b, [(u, jacc.READ, -1, 1, 0), (v, jacc.WRITE, 0, 0, 0)])
+        assert step > 0 and ker.shape == (4,)
+        assert np.all(ker > 0) and np.all(ker <= step)
+        c.exit(v)
+    one = u.copy()
+    oracle.jacobi2d_sweep(u, one)
+    assert np.array_equal(v, one)

@@ -78,25 +78,28 @@ def test_gemm_small_frobenius_and_integer_exact(M, N, L, K):
         assert np.array_equal(_gemm_dev(Ai, Bi, K, slab, threads), oracle.gemm(Ai, Bi))
 
 
-def test_gemm_4096_sampled_rows():
-    say("gemm 4096^3 K=1 and K=4, sampled rows")
+def test_gemm_4096_full_frobenius_and_integer_exact():
+    """C = A*B at 4096^3 against the oracle over every element of C:
+    Frobenius-norm bound for uniform inputs, exact equality for
+    integer-valued inputs (whose products and sums are all exact)."""
     n = 4096
     A, B = inputs.gemm_inputs(n, n, n, seed=3)
+    say(f"oracle: gemm 4096^3 on {oracle.threads()} host threads")
+    ref = oracle.gemm_mt(A, B)
+    bound = 1e-12 * np.linalg.norm(A) * np.linalg.norm(B)
     C1 = _gemm_dev(A, B, 1)
+    say(f"  K=1 Frobenius error {np.linalg.norm(C1 - ref):.3e} (bound {bound:.3e})")
+    assert np.linalg.norm(C1 - ref) <= bound
     C4 = _gemm_dev(A, B, 4)
     assert np.array_equal(C1, C4)  # no split-k: partitioning never changes an element's sum order
+    assert np.linalg.norm(C4 - ref) <= bound
     assert np.array_equal(C1, _gemm_dev(A, B, 1, 32))  # nor does the k-slab depth
-    assert np.array_equal(C1, _gemm_dev(A, B, 1, 16, 512))  # nor the workgroup size
-    # one row of every residue mod 16 (the matrix-core output interleaves
-    # rows across lane groups), block edges and the last row
-    rows = sorted(set([1024 + r for r in range(16)] + [0, 1, 4, 2047, 2050, 4095]))
-    for r in rows:
-        ref = oracle.gemm_rows(A, B, r, r + 1)
-        assert np.linalg.norm(C4[r] - ref[0]) <= 1e-12 * np.linalg.norm(A[r]) * np.linalg.norm(B)
+    assert np.array_equal(C1, _gemm_dev(A, B, 1, 16, 256))  # nor the workgroup size
+    del C1, C4, ref
     Ai, Bi = inputs.gemm_inputs(n, n, n, seed=5, integer=True)
-    Ci = _gemm_dev(Ai, Bi, 4)
-    for r in rows:
-        assert np.array_equal(Ci[r], oracle.gemm_rows(Ai, Bi, r, r + 1)[0])
+    say("  integer-valued inputs")
+    ref_i = oracle.gemm_mt(Ai, Bi)
+    assert np.array_equal(_gemm_dev(Ai, Bi, 4), ref_i)
 
 
 # ------------------------------------------------------------------ SpMV
@@ -136,17 +139,17 @@ def test_spmv_small(n, K):
         assert np.array_equal(_spmv_dev(rpi, coli, vali, xi, K, cfg), ref_i)
 
 
-def test_spmv_2_22_rows_k1_k4():
-    say("spmv 2^22 rows K=1,4")
+def test_spmv_2_22_rows_k1_k4_every_row():
+    say("spmv 2^22 rows K=1,4, every row against the oracle")
     n = 1 << 22
     rp, col, val, x = inputs.csr_matrix(n, n, 16, seed=4)
+    ref = oracle.spmv_csr_mt(rp, col, val, x)
+    bound = 1e-13 * _row_bound(rp, col, val, x)
     y1 = _spmv_dev(rp, col, val, x, 1)
     y4 = _spmv_dev(rp, col, val, x, 4)
-    assert np.array_equal(y1, y4)
-    bound = _row_bound(rp, col, val, x)
-    for lo in (0, n // 4 - 3, n // 2, n - 100):
-        ref = oracle.spmv_csr(rp, col, val, x, rows=(lo, lo + 100))
-        assert np.all(np.abs(y4[lo:lo + 100] - ref[lo:lo + 100]) <= 1e-13 * bound[lo:lo + 100])
+    assert np.array_equal(y1, y4)  # each row's sum order is fixed by the lanes-per-row layout
+    bad = np.flatnonzero(np.abs(y4 - ref) > bound)
+    assert bad.size == 0, f"{bad.size} rows outside the bound, first {bad[:5]}"
 
 
 # ------------------------------------------------------------------ predicate-filtered scatter

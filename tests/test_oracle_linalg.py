@@ -175,3 +175,18 @@ def test_scatter_filtered_partitions_equal_plain(K):
     idx = np.random.default_rng(14).permutation(n).astype(np.int32)
     out = inputs.uniform(n, seed=15)
     assert np.array_equal(oracle.scatter_sq_partitioned(x, idx, out, K), oracle.scatter_sq(x, idx, out))
+
+
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_gemm_multithreaded_bit_identical_and_integer_exact(threads):
+    A, B = inputs.gemm_inputs(70, 45, 33, seed=7)
+    assert np.array_equal(oracle.gemm_mt(A, B, threads), oracle.gemm(A, B))
+    Ai, Bi = inputs.gemm_inputs(41, 29, 57, seed=8, integer=True)
+    ref = Ai.astype(np.int64) @ Bi.astype(np.int64)
+    assert np.array_equal(oracle.gemm_mt(Ai, Bi, threads), ref.astype(np.float64))
+
+
+@pytest.mark.parametrize("threads", [1, 5])
+def test_spmv_multithreaded_bit_identical(threads):
+    rp, col, val, x = inputs.csr_matrix(9000, 9000, 16, seed=12)
+    assert np.array_equal(oracle.spmv_csr_mt(rp, col, val, x, threads), oracle.spmv_csr(rp, col, val, x))

@@ -178,3 +178,29 @@ def test_heat_window_equals_full_run(win):
     zs, ys, xs = win
     assert np.array_equal(oracle.heat3d_window(g, T, 0.1, zs, ys, xs),
                           full[zs[0]:zs[1], ys[0]:ys[1], xs[0]:xs[1]])
+
+
+# ------------------------------------------------------------------ multi-threaded forms
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_jacobi_multithreaded_bit_identical_to_sequential(threads):
+    u0 = inputs.jacobi_grid(203, 131, seed=14)
+    assert np.array_equal(oracle.jacobi2d_mt(u0, 9, threads), oracle.jacobi2d(u0, 9))
+
+
+@pytest.mark.parametrize("threads", [1, 4, 7])
+def test_heat_multithreaded_field_identical_and_residual_exact_within_bound(threads):
+    g = inputs.heat_field(11, 9, 13, seed=15)
+    ref, _ = oracle.heat3d(g, 3, 0.1)
+    out, res = oracle.heat3d_mt(g, 3, 0.1, threads)
+    assert np.array_equal(out, ref)
+    # the residual of the last step against the exact rational sum of the
+    # squared differences of the stored fields (per-plane compensated sums,
+    # then compensated over planes: terms within 3u, sums within 2u each)
+    prev, _ = oracle.heat3d(g, 2, 0.1)
+    ex = exact.residual_of_stored(prev, out)
+    assert abs(res[-1] - float(ex)) <= 8 * U * float(ex)
+
+
+def test_oracle_threads_reports_the_request():
+    assert oracle.threads(3) == 3
+    assert oracle.threads(0) >= 1

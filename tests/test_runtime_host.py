@@ -383,6 +383,39 @@ def test_batch_not_replay_safe_is_refused():
     assert race_check(c.trace()) == []
 
 
+def test_batch_of_an_exited_array_is_stale_and_refused():
+    """A graph addresses the slabs of the arrays it captured: once one of them
+    leaves the data region, replays are refused (also after a re-enter of
+    the same host range, which gets new slabs)."""
+    c = dry(2)
+    a = np.zeros((30, 8))
+    b = np.zeros((30, 8))
+    x = np.zeros((30, 8))
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    c.enter(x, halo=(1, 1))
+    c.batch_begin()
+    c.jacobi2d(a, b)
+    c.jacobi2d(b, a)
+    g = c.batch_end()
+    c.batch_begin()
+    c.jacobi2d(x, b)                 # a second graph over x and b
+    g2 = c.batch_end()
+    c.enter(a, halo=(1, 1))          # a second reference: exit below does not free a
+    c.exit(a)
+    assert c.batch_launch(g, 1, raw=True) == jacc.OK
+    c.exit(a)                        # reference count 0: slabs freed
+    assert c.batch_launch(g, 1, raw=True) == jacc.ERR_INVALID
+    assert "left the data region" in c.last_error()
+    assert not c.batch_info(g)["replay_safe"]
+    assert c.batch_launch(g2, 1, raw=True) == jacc.OK   # g2 never used a
+    c.enter(a, halo=(1, 1))
+    assert c.batch_launch(g, 1, raw=True) == jacc.ERR_INVALID
+    c.exit(b)
+    assert c.batch_launch(g2, 1, raw=True) == jacc.ERR_INVALID
+    c.close()
+
+
 def test_batch_persistent_group_packs_independent_loops():
     c = dry(2)
     arrs = []
