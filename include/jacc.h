@@ -368,12 +368,137 @@ int jacc_model_gradients(jacc_model *m, const float *X, const float *y, int n, f
 /* One Adam step with learning rate lr on the gradient of the last
  * jacc_model_gradients call. */
 int jacc_model_adam_step(jacc_model *m, float lr);
-/* Minibatch training: `epochs` passes over (X, y) in an order shuffled per
- * epoch from `seed` (splitmix64 + Fisher-Yates), minibatches of `batch`
- * rows, one Adam step each.  epoch_loss[e] (optional) receives the mean
- * minibatch loss of epoch e. */
-int jacc_model_train(jacc_model *m, const float *X, const float *y, int n, int epochs, int batch, float lr,
-                     uint64_t seed, float *epoch_loss);
+/* Minibatch training of one network: `epochs` passes over (X, y) in an
+ * order shuffled per epoch from `seed` (splitmix64 + Fisher-Yates),
+ * minibatches of `batch` rows, one Adam step each.  epoch_loss[e] (optional)
+ * receives the mean minibatch loss of epoch e. */
+int jacc_model_fit(jacc_model *m, const float *X, const float *y, int n, int epochs, int batch, float lr,
+                   uint64_t seed, float *epoch_loss);
+
+/* ---- autotuner and learned choice of launch configurations ----------------
+ * The paper names auto-tuning as future work (Sec. "Conclusion"), and its
+ * adaptive rule (Sec. "Adaptive Utilization") already picks, per kernel,
+ * between duplicated and distributed execution from profiled times.  Here
+ * a stencil loop (JACOBI2D, HEAT3D) gets a launch configuration and a
+ * partition count K.  No choice changes a field bit.
+ *
+ * Candidates.  For each K of a requested set (those not above the array's
+ * interior rows), in this order: workgroup shapes (bx, by) in {(64,1),
+ * (128,1), (256,1), (512,1), (64,4), (128,2), (256,2), (256,4)}, for HEAT3D
+ * rows per wave in {1, 4} (4 only with at most 256 threads), tiles in {1, 4,
+ * 16, 64}, vec in {1, 2} (2 only for an even row length); then persistent
+ * execution with 256 threads, tiles {1, 4, 16}, vec {1, 2}.  order and march
+ * stay 0 (the defaults).  A candidate's index in this order breaks ties.
+ *
+ * Features (the cost model's input, JACC_NFEATURES floats): 1 for 3-D,
+ * log2 of each extent (1 for a missing third), log2 of the interior cells,
+ * log2 bx, log2 by, log2 tile, vec, log2 K, persistent, log2 of the
+ * workgroups one launch over the interior uses, log2 rows.
+ *
+ * Timing database: a text file of median-ready sample lists keyed by the
+ * loop signature (kind, extents) and the candidate, in sections keyed by
+ * "<gpu arch>|hip<runtime version>|<library build id>", so timings of
+ * another device, runtime or build are kept in the file but never used.
+ * A malformed file is an error (JACC_ERR_INVALID), never overwritten. */
+typedef struct {
+    jacc_config cfg;
+    int32_t K;
+    int32_t pad_;
+} jacc_candidate;
+
+enum { JACC_NFEATURES = 13, JACC_MAX_CANDIDATES = 1024 };
+
+/* Candidates of a stencil loop over an array of extents extent[0..ndim)
+ * (ndim 2 for JACOBI2D, 3 for HEAT3D) for the partition counts ks[0..nks)
+ * (1..64 each).  Writes at most cap of them to out (out may be NULL) and
+ * their number to *n. */
+int jacc_candidates(int kind, const int64_t *extent, int ndim, const int *ks, int nks, jacc_candidate *out, int cap,
+                    int *n);
+/* The JACC_NFEATURES features of one candidate. */
+int jacc_features(int kind, const int64_t *extent, int ndim, const jacc_candidate *c, float *out);
+/* Build key of the timing database and of cost-model files on this context
+ * ("dry|hip0|<build>" for a dry-run context); library-owned string. */
+const char *jacc_build_key(jacc_ctx *ctx);
+
+typedef struct {
+    int32_t warmup;      /* untimed replays per candidate (0: 1) */
+    int32_t reps;        /* timed replays per candidate (0: 5) */
+    int32_t nks;         /* partition counts to search (0: the arrays' own K) */
+    int32_t ks[8];
+    const char *db_path; /* timing database read first and written back, or NULL */
+} jacc_tune_opts;
+
+/* Exhaustive autotuner of one stencil loop call (kind, bounds, 2 arguments
+ * and scalars as for jacc_parallel_loop; the arguments must be present and
+ * give the shapes and halos).  Every candidate runs on scratch replicas of
+ * the two arrays entered with the candidate's K (the caller's arrays are
+ * never written), as a one-loop captured graph replayed `warmup` times
+ * untimed and `reps` times timed with HIP events; candidates already in the
+ * database are not run again.  The choice is the smallest median, ties to
+ * the lowest candidate index.  *best receives it; medians (optional, `cap`
+ * doubles) each candidate's median in ms and *ncand their number.
+ * JACC_ERR_UNSUPPORTED for other loop kinds and in dry-run contexts. */
+int jacc_tune(jacc_ctx *ctx, int kind, const jacc_bounds *bounds, int nargs, const jacc_arg *args,
+              const double *scalars, int nscalars, const jacc_tune_opts *opts, jacc_candidate *best,
+              double *medians, int cap, int *ncand);
+/* Median of n samples (the mean of the two middle ones for even n) and the
+ * index of the smallest of n values, ties to the lowest index: the
+ * selection rule jacc_tune applies. */
+double jacc_median(const double *samples, int n);
+int jacc_argmin(const double *values, int n);
+
+typedef struct {
+    int32_t members;   /* networks whose predictions are averaged (0: 3) */
+    int32_t epochs;    /* 0: 600 */
+    int32_t batch;     /* 0: 256 */
+    float lr;          /* 0: 1e-3 */
+    uint64_t seed;     /* initial weights (He-uniform from splitmix64) and sample orders */
+    int32_t holdout;   /* > 0: every holdout-th loop signature of the database is kept out of
+                          training and its mean squared error reported */
+    int32_t pad_;
+} jacc_train_opts;
+
+typedef struct {
+    int32_t rows, signatures;  /* database rows used for training, and their loop signatures */
+    float loss_first, loss_last;  /* mean training loss of the first and last epoch (member 0) */
+    float heldout_mse;         /* on the held-out signatures (0 without) */
+    int32_t pad_;
+} jacc_train_report;
+
+/* Trains the cost model on the GPU from every row of the timing database
+ * under this context's build key (features -> log of the median ms),
+ * standardising the features by their training mean and standard deviation,
+ * and writes it to out_path: magic, build key, feature count, members,
+ * scaler, parameters, checksum.  opts/report may be NULL. */
+int jacc_model_train(jacc_ctx *ctx, const char *db_path, const char *out_path, const jacc_train_opts *opts,
+                     jacc_train_report *report);
+/* Loads a cost-model file and attaches it to the context (replacing any
+ * attached one).  JACC_ERR_INVALID for a missing, truncated or corrupt file
+ * (checksum) or one written under another build key; the context then keeps
+ * no model.  While a model is attached, jacc_parallel_loop with cfg = NULL
+ * on a stencil loop outside a batch uses the model's pick among the
+ * non-persistent candidates at its arrays' K (cached per loop signature;
+ * inside a batch only an already cached pick is used, else the defaults). */
+int jacc_model_load(jacc_ctx *ctx, const char *path);
+int jacc_model_unload(jacc_ctx *ctx);
+/* The attached model's choice among the candidates for ks[0..nks): the
+ * smallest predicted log time (mean over members; ties to the lowest index),
+ * batched inference on the GPU.  pred (optional, cap floats) receives every
+ * candidate's prediction and *ncand their number.  JACC_ERR_INVALID without
+ * an attached model. */
+int jacc_model_pick(jacc_ctx *ctx, int kind, const int64_t *extent, int ndim, const int *ks, int nks,
+                    jacc_candidate *best, float *pred, int cap, int *ncand);
+
+/* The configuration for a stencil loop call by the fallback chain
+ * model -> tuner -> default: the pick of the model in model_path (loaded
+ * and attached when it is not the attached one) if it loads; else, when
+ * opts != NULL, jacc_tune's choice; else the library defaults (all config
+ * fields 0) at the arrays' K.  *source receives 1, 2 or 3 for the three;
+ * the reason a step was skipped is left in jacc_last_error. */
+enum { JACC_CHOICE_MODEL = 1, JACC_CHOICE_TUNER = 2, JACC_CHOICE_DEFAULT = 3 };
+int jacc_choose(jacc_ctx *ctx, int kind, const jacc_bounds *bounds, int nargs, const jacc_arg *args,
+                const double *scalars, int nscalars, const char *model_path, const jacc_tune_opts *opts,
+                jacc_candidate *out, int *source);
 
 /* ---- operation trace (planning and tests) ------------------------------ */
 enum {

@@ -6,6 +6,7 @@ no fast-math, and packed FP32 instructions disabled.  Objects go to
 ``_build/``; the shared library lands beside this file.
 """
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
@@ -29,11 +30,24 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src):
+def build_id():
+    """First 12 hex digits of the SHA-1 of every library source and header:
+    timing databases and cost-model files are keyed by it."""
+    h = hashlib.sha1()
+    files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".h")))
+    for path in files + [os.path.join(INCLUDE, "jacc.h")]:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:12]
+
+
+def _compile(src, bid):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = ["hipcc", *COMMON, "-c", src, "-o", obj]
+    flags = [*COMMON, f'-DJACC_BUILD_ID="{bid}"']
+    cmd = ["hipcc", *flags, "-c", src, "-o", obj]
     if src.endswith(".hip"):
-        cmd = ["hipcc", "-x", "hip", *COMMON, "-c", src, "-o", obj]
+        cmd = ["hipcc", "-x", "hip", *flags, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -43,8 +57,9 @@ def _compile(src):
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
+    bid = build_id()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda src: _compile(src, bid), srcs))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

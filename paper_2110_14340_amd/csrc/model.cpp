@@ -205,8 +205,8 @@ int jacc_model_adam_step(jacc_model *m, float lr) {
     return JACC_OK;
 }
 
-int jacc_model_train(jacc_model *m, const float *X, const float *y, int n, int epochs, int batch, float lr,
-                     uint64_t seed, float *epoch_loss) {
+int jacc_model_fit(jacc_model *m, const float *X, const float *y, int n, int epochs, int batch, float lr,
+                   uint64_t seed, float *epoch_loss) {
     if (bad(m) || !X || !y || n < 1 || epochs < 0 || batch < 1) return JACC_ERR_INVALID;
     const int bsz = batch < n ? batch : n;
     const int nb = (n + bsz - 1) / bsz;

@@ -26,6 +26,7 @@
 #include <string>
 #include <vector>
 
+#include "ctx_internal.h"
 #include "kernels.h"
 
 namespace {
@@ -290,6 +291,9 @@ struct jacc_ctx {
     bool time_parts = false;
     std::vector<hipEvent_t> kev;
     uint64_t kev_used = 0;  // bit p: partition p launched in the timed call
+    // cost model attached by jacc_model_load (owned; released at finalize)
+    void *model = nullptr;
+    void (*model_release)(void *) = nullptr;
     // fault injection (tests): fail the n-th op of a kind
     int fault_kind = 0;  // 1 copy, 2 launch
     int64_t fault_n = -1, fault_count = 0;
@@ -914,6 +918,15 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
 int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc_arg *args, const double *scalars,
               int nscalars, int slot, double *red_host, const jacc_config *cfg) {
     const bool want_red = slot >= 0 || red_host;
+    jacc_config picked;
+    if (!cfg && c->model && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) && nargs == 2 && args) {
+        // no configuration given: the attached cost model's pick for this
+        // loop on its arrays' partitions (cached per loop signature)
+        Array *W = lookup(c, args[1].host);
+        if (W && W->host == (uintptr_t)args[1].host &&
+            jr::model_config(c, kind, W->d.extent, W->d.ndim, W->K, &picked))
+            cfg = &picked;
+    }
     if (slot >= kSlots) return set_err(c, JACC_ERR_INVALID, "reduction slot %d out of range", slot);
     if (red_host && c->cur) return set_err(c, JACC_ERR_INVALID, "a synchronous reduction inside a batch");
     Array *arr[8];
@@ -1352,6 +1365,8 @@ int jacc_finalize(jacc_ctx *c) {
     if (!c) return JACC_ERR_INVALID;
     int status = c->status;
     try {
+        if (c->model && c->model_release) c->model_release(c->model);  // its buffers come from this context
+        c->model = nullptr;
         if (c->cur) {  // abandon an open capture
             if (live(c)) {
                 hipGraph_t g = nullptr;
@@ -1852,14 +1867,28 @@ int jacc_trace_clear(jacc_ctx *c) {
 }  // extern "C"
 
 // ---- internal access for other library modules -------------------------------
-#include "ctx_internal.h"
 
 namespace jr {
 bool dry(const jacc_ctx *c) { return c->dry; }
 bool failed(const jacc_ctx *c) { return c->status != JACC_OK; }
+bool in_batch(const jacc_ctx *c) { return c->cur != nullptr || c->plan_only; }
 hipStream_t stream0(const jacc_ctx *c) { return c->st[0].s; }
 int alloc(jacc_ctx *c, size_t bytes, void **out) { return dev_alloc(c, bytes, out); }
 void release(jacc_ctx *c, void *p) { dev_free(c, p); }
 int device_error(jacc_ctx *c, hipError_t e, const char *what) { return dev_fail(c, e, what); }
 int error(jacc_ctx *c, int code, const char *msg) { return set_err(c, code, "%s", msg); }
+int array_info(jacc_ctx *c, const void *host, jacc_array_desc *d, size_t *bytes, int *K) {
+    Array *A = lookup(c, host);
+    if (!A) return set_err(c, JACC_ERR_NOT_PRESENT, "%p is not present", host);
+    if (d) *d = A->d;
+    if (bytes) *bytes = A->bytes;
+    if (K) *K = A->K;
+    return JACC_OK;
+}
+void *attached_model(const jacc_ctx *c) { return c->model; }
+void attach_model(jacc_ctx *c, void *model, void (*release_model)(void *)) {
+    if (c->model && c->model_release) c->model_release(c->model);
+    c->model = model;
+    c->model_release = release_model;
+}
 }  // namespace jr

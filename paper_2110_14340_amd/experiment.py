@@ -9,7 +9,8 @@ seed 6); the model is trained only on timings of other shapes (seed 7+).
 These stand in for applications with tens to hundreds of kernels of uneven
 sizes (the paper's benchmark table).
 """
-import math
+import os
+import tempfile
 import time
 
 import numpy as np
@@ -60,55 +61,52 @@ def graph_time(shapes, datas, configs, reps=10, keep_outputs=False):
         ctx.close()
 
 
-def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=600, members=3, tune_reps=5, graph_reps=30, log=print,
-        test_shapes=None, train_shapes=None):
+def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=300, members=3, tune_reps=5, graph_reps=30, log=print,
+        test_shapes=None, train_shapes=None, workdir=None):
+    """The batched/learned experiment.  Timing databases and the model file
+    go to `workdir` (a fresh temporary directory by default)."""
     t_start = time.perf_counter()
     test_shapes = test_shapes or inputs.batch_shapes(5, n2d, n3d)
     train_shapes = train_shapes or inputs.batch_shapes(7, train2d, train3d)
-    ctx = jacc.Context(2)
-    db = tuner.TimingDB()
-    # 1. exhaustive timings of the training shapes -> dataset
-    X, y, group = [], [], []
-    t0 = time.perf_counter()
-    for li, sh in enumerate(train_shapes):
-        cands, meds, _ = tuner.tune(ctx, sh, _data(sh, 1000 + li), db=db, reps=tune_reps)
-        if li % 16 == 15:
-            log(f"  tuned {li + 1}/{len(train_shapes)} training shapes")
-        for c, m in zip(cands, meds):
-            X.append(tuner.features(sh, c))
-            y.append(math.log(m))
-            group.append(li)
-    X, y, group = np.array(X), np.array(y), np.array(group)
-    t_train_tune = time.perf_counter() - t0
-    log(f"training set: {len(y)} timings from {len(train_shapes)} shapes ({t_train_tune:.1f} s)")
-    # 2. train the GPU network (80/20 split by loop for a held-out loss)
-    val = group % 5 == 4
-    model = tuner.CostModel(ctx, init_params=[inputs.mlp_init(tuner.NFEAT, seed=8 + m) for m in range(members)])
-    t0 = time.perf_counter()
-    losses = model.fit(X[~val], y[~val], epochs=epochs, batch=256, lr=1e-3, seed=9)
-    t_fit = time.perf_counter() - t0
-    val_mse = float(np.mean((model.predict(X[val]) - y[val]) ** 2)) if val.any() else None
-    log(f"model: loss {losses[0]:.4f} -> {losses[-1]:.4f} in {epochs} epochs ({t_fit:.1f} s), held-out mse {val_mse}")
-    # 3. the test batch: exhaustive choice, model choice, default
-    exh, mlp, dflt, datas = [], [], [], []
-    regret_loop = []
-    t0 = time.perf_counter()
-    for li, sh in enumerate(test_shapes):
-        d = _data(sh, 6000 + li)
-        datas.append(d)
-        cands, meds, _ = tuner.tune(ctx, sh, d, db=db, reps=tune_reps)
-        best = tuner.select(meds)
-        exh.append(cands[best])
-        pick, _ = model.pick(sh, cands)
-        mlp.append(pick)
-        dflt.append(dict(tuner.DEFAULT_CONFIG))
-        regret_loop.append(meds[cands.index(pick)] / meds[best] - 1.0)
-        if li % 32 == 31:
-            log(f"  tuned {li + 1}/{len(test_shapes)} test shapes")
-    t_test_tune = time.perf_counter() - t0
-    db.save()
-    model.close()
-    ctx.close()
+    workdir = workdir or tempfile.mkdtemp(prefix="jacc_learned_")
+    train_db = os.path.join(workdir, "train_timings.db")
+    test_db = os.path.join(workdir, "test_timings.db")
+    model_path = os.path.join(workdir, "cost_model.bin")
+    ctx = jacc.Context(max(tuner.KS))
+    try:
+        # 1. exhaustive timings of the training shapes -> the training database
+        t0 = time.perf_counter()
+        for li, sh in enumerate(train_shapes):
+            tuner.tune(ctx, sh, _data(sh, 1000 + li), db_path=train_db, reps=tune_reps)
+            if li % 16 == 15:
+                log(f"  tuned {li + 1}/{len(train_shapes)} training shapes")
+        t_train_tune = time.perf_counter() - t0
+        # 2. the GPU-trained ensemble, from the database, into a model file
+        t0 = time.perf_counter()
+        rep = tuner.train(ctx, train_db, model_path, members=members, epochs=epochs, seed=9, holdout=5)
+        t_fit = time.perf_counter() - t0
+        log(f"model: {rep['rows']} timings of {rep['signatures']} shapes ({t_train_tune:.1f} s to tune), "
+            f"loss {rep['loss_first']:.4f} -> {rep['loss_last']:.4f} in {epochs} epochs ({t_fit:.1f} s), "
+            f"held-out mse {rep['heldout_mse']:.4f}")
+        ctx.model_load(model_path)
+        # 3. the test batch: exhaustive choice, model choice, default
+        exh, mlp, dflt, datas, regret_loop = [], [], [], [], []
+        t0 = time.perf_counter()
+        for li, sh in enumerate(test_shapes):
+            d = _data(sh, 6000 + li)
+            datas.append(d)
+            cands, meds, best = tuner.tune(ctx, sh, d, db_path=test_db, reps=tune_reps)
+            exh.append(cands[best])
+            pick, pcands, _ = tuner.pick(ctx, sh)
+            assert pcands == cands
+            mlp.append(pick)
+            dflt.append(dict(tuner.DEFAULT_CONFIG))
+            regret_loop.append(meds[cands.index(pick)] / meds[best] - 1.0)
+            if li % 32 == 31:
+                log(f"  tuned {li + 1}/{len(test_shapes)} test shapes")
+        t_test_tune = time.perf_counter() - t0
+    finally:
+        ctx.close()
     log(f"test batch: {len(test_shapes)} loops tuned exhaustively ({t_test_tune:.1f} s)")
     t_exh, info_e, out_e = graph_time(test_shapes, datas, exh, graph_reps, keep_outputs=True)
     t_mlp, info_m, out_m = graph_time(test_shapes, datas, mlp, graph_reps, keep_outputs=True)
@@ -116,6 +114,7 @@ def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=600, members=3, tune_re
     identical = all(np.array_equal(a, b) and np.array_equal(a, c) for a, b, c in zip(out_e, out_m, out_d))
     cells = sum(float(np.prod([d - 2 for d in sh])) for sh in test_shapes)
     alg_bytes = 16.0 * cells
+    ks_used = {"exhaustive": sorted({c["K"] for c in exh}), "learned": sorted({c["K"] for c in mlp})}
     result = {
         "loops": len(test_shapes),
         "algorithmic_gb": round(alg_bytes / 1e9, 3),
@@ -125,12 +124,15 @@ def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=600, members=3, tune_re
         "regret_learned_vs_exhaustive": round(t_mlp / t_exh - 1.0, 4),
         "gain_learned_vs_default": round(t_def / t_mlp, 3),
         "mean_per_loop_regret": round(float(np.mean(regret_loop)), 4),
+        "median_per_loop_regret": round(float(np.median(regret_loop)), 4),
+        "partition_counts_searched": list(tuner.KS),
+        "partition_counts_chosen": ks_used,
         "persistent_groups": {"exhaustive": info_e["persistent_groups"], "learned": info_m["persistent_groups"]},
         "outputs_bit_identical_across_configs": bool(identical),
-        "train_timings": int(len(y)),
+        "train_timings": int(rep["rows"]),
         "train_shapes": len(train_shapes),
-        "model_loss_first_last": [round(float(losses[0]), 5), round(float(losses[-1]), 5)],
-        "heldout_mse": None if val_mse is None else round(val_mse, 5),
+        "model_loss_first_last": [round(float(rep["loss_first"]), 5), round(float(rep["loss_last"]), 5)],
+        "heldout_mse": round(float(rep["heldout_mse"]), 5),
         "seconds": round(time.perf_counter() - t_start, 1),
     }
     return result, (test_shapes, datas, out_m)

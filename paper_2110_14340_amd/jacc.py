@@ -55,6 +55,26 @@ class Config(ctypes.Structure):
                 ("march", ctypes.c_int32), ("rows", ctypes.c_int32)]
 
 
+class Candidate(ctypes.Structure):
+    _fields_ = [("cfg", Config), ("K", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class TuneOpts(ctypes.Structure):
+    _fields_ = [("warmup", ctypes.c_int32), ("reps", ctypes.c_int32), ("nks", ctypes.c_int32),
+                ("ks", ctypes.c_int32 * 8), ("db_path", ctypes.c_char_p)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("members", ctypes.c_int32), ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("seed", ctypes.c_uint64), ("holdout", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("signatures", ctypes.c_int32), ("loss_first", ctypes.c_float),
+                ("loss_last", ctypes.c_float), ("heldout_mse", ctypes.c_float), ("pad_", ctypes.c_int32)]
+
+
 class Allocator(ctypes.Structure):
     ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
     FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -124,7 +144,26 @@ def lib():
     L.jacc_model_predict.argtypes = [vp, fp, i32, fp]
     L.jacc_model_gradients.argtypes = [vp, fp, fp, i32, fp, fp]
     L.jacc_model_adam_step.argtypes = [vp, ctypes.c_float]
-    L.jacc_model_train.argtypes = [vp, fp, fp, i32, i32, i32, ctypes.c_float, ctypes.c_uint64, fp]
+    L.jacc_model_fit.argtypes = [vp, fp, fp, i32, i32, i32, ctypes.c_float, ctypes.c_uint64, fp]
+    CP = ctypes.POINTER(Candidate)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    i32p = ctypes.POINTER(ctypes.c_int)
+    L.jacc_candidates.argtypes = [i32, i64p, i32, i32p, i32, CP, i32, i32p]
+    L.jacc_features.argtypes = [i32, i64p, i32, CP, fp]
+    L.jacc_build_key.argtypes = [vp]
+    L.jacc_build_key.restype = ctypes.c_char_p
+    L.jacc_median.argtypes = [ctypes.POINTER(ctypes.c_double), i32]
+    L.jacc_median.restype = ctypes.c_double
+    L.jacc_argmin.argtypes = [ctypes.POINTER(ctypes.c_double), i32]
+    L.jacc_tune.argtypes = [vp, i32, ctypes.POINTER(Bounds), i32, ctypes.POINTER(Arg), ctypes.POINTER(ctypes.c_double),
+                            i32, ctypes.POINTER(TuneOpts), CP, ctypes.POINTER(ctypes.c_double), i32, i32p]
+    L.jacc_model_train.argtypes = [vp, ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(TrainOpts),
+                                   ctypes.POINTER(TrainReport)]
+    L.jacc_model_load.argtypes = [vp, ctypes.c_char_p]
+    L.jacc_model_unload.argtypes = [vp]
+    L.jacc_model_pick.argtypes = [vp, i32, i64p, i32, i32p, i32, CP, fp, i32, i32p]
+    L.jacc_choose.argtypes = [vp, i32, ctypes.POINTER(Bounds), i32, ctypes.POINTER(Arg),
+                              ctypes.POINTER(ctypes.c_double), i32, ctypes.c_char_p, ctypes.POINTER(TuneOpts), CP, i32p]
     L.jacc_trace_len.argtypes = [vp]
     L.jacc_trace_get.argtypes = [vp, i32, ctypes.POINTER(TraceOp)]
     L.jacc_trace_clear.argtypes = [vp]
@@ -156,6 +195,84 @@ def bounds(*pairs):
         b.lo[d] = lo
         b.hi[d] = hi
     return b
+
+
+CHOICE_MODEL, CHOICE_TUNER, CHOICE_DEFAULT = 1, 2, 3
+NFEATURES = 13
+MAX_CANDIDATES = 1024
+_CAND_FIELDS = ("bx", "by", "tile", "vec", "persistent", "rows")
+
+
+def cand_dict(c):
+    """A jacc_candidate as a dict of its configuration fields and K."""
+    d = {k: int(getattr(c.cfg, k)) for k in _CAND_FIELDS}
+    d["K"] = int(c.K)
+    return d
+
+
+def cand_struct(d):
+    c = Candidate()
+    c.cfg = config(bx=d["bx"], by=d["by"], tile=d["tile"], vec=d["vec"], persistent=d.get("persistent", 0),
+                   rows=d.get("rows", 1))
+    c.K = d["K"]
+    return c
+
+
+def _i64s(v):
+    return (ctypes.c_int64 * len(v))(*[int(x) for x in v])
+
+
+def _i32s(v):
+    return (ctypes.c_int * max(1, len(v)))(*[int(x) for x in v])
+
+
+def stencil_kind(shape):
+    return JACOBI2D if len(shape) == 2 else HEAT3D
+
+
+def candidates(shape, ks):
+    """jacc_candidates: the tuner's candidates (dicts) in their tie-break order."""
+    L = lib()
+    n = ctypes.c_int(0)
+    out = (Candidate * MAX_CANDIDATES)()
+    rc = L.jacc_candidates(stencil_kind(shape), _i64s(shape), len(shape), _i32s(ks), len(ks), out, MAX_CANDIDATES,
+                           ctypes.byref(n))
+    if rc != OK:
+        raise JaccError(rc, "jacc_candidates")
+    return [cand_dict(out[i]) for i in range(min(n.value, MAX_CANDIDATES))]
+
+
+def features(shape, cand):
+    """jacc_features: the cost model's input for one candidate."""
+    out = np.zeros(NFEATURES, dtype=np.float32)
+    c = cand_struct(cand)
+    rc = lib().jacc_features(stencil_kind(shape), _i64s(shape), len(shape), ctypes.byref(c),
+                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    if rc != OK:
+        raise JaccError(rc, "jacc_features")
+    return out
+
+
+def median(samples):
+    v = np.ascontiguousarray(samples, dtype=np.float64)
+    return float(lib().jacc_median(v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), v.size))
+
+
+def argmin(values):
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    rc = lib().jacc_argmin(v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), v.size)
+    if rc < 0:
+        raise JaccError(rc, "jacc_argmin")
+    return rc
+
+
+def tune_opts(ks=(), db_path=None, warmup=0, reps=0):
+    o = TuneOpts()
+    o.warmup, o.reps, o.nks = warmup, reps, len(ks)
+    for i, k in enumerate(ks):
+        o.ks[i] = k
+    o.db_path = db_path.encode() if db_path else None
+    return o
 
 
 class TorchAllocator:
@@ -412,6 +529,81 @@ class Context:
         self._check(st)
         return step.value, ker[:nk]
 
+    # -- tuner and cost model ----------------------------------------------------
+    def _stencil_args(self, u_in, u_out):
+        A = (Arg * 2)()
+        A[0] = Arg(self._ptr(u_in), READ, -1, 1, 0)
+        A[1] = Arg(self._ptr(u_out), WRITE, 0, 0, 0)
+        shape = u_in.shape
+        b = bounds(*[(1, e - 1) for e in shape])
+        scal = (ctypes.c_double * 1)(0.1)
+        return A, b, scal, (1 if len(shape) == 3 else 0)
+
+    def tune(self, u_in, u_out, ks=(), db_path=None, warmup=0, reps=0):
+        """jacc_tune for the stencil sweep u_in -> u_out (JACOBI2D for 2-D,
+        HEAT3D with alpha 0.1 for 3-D): (best candidate, candidates, medians)."""
+        A, b, scal, ns = self._stencil_args(u_in, u_out)
+        o = tune_opts(ks, db_path, warmup, reps)
+        best = Candidate()
+        med = np.zeros(MAX_CANDIDATES, dtype=np.float64)
+        n = ctypes.c_int(0)
+        self._check(self.L.jacc_tune(self.ctx, stencil_kind(u_in.shape), ctypes.byref(b), 2, A, scal, ns,
+                                     ctypes.byref(o), ctypes.byref(best),
+                                     med.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), MAX_CANDIDATES,
+                                     ctypes.byref(n)))
+        cands = candidates(u_in.shape, list(ks) if ks else [self.arrays_K(u_out)])
+        assert len(cands) == n.value
+        return cand_dict(best), cands, med[:n.value].copy()
+
+    def arrays_K(self, a):
+        """Partition count of a present array (from its slab table)."""
+        K = 0
+        while K < 64 and self.L.jacc_slab_info(self.ctx, self._ptr(a), K, None, None, None) == OK:
+            K += 1
+        return K
+
+    def build_key(self):
+        return self.L.jacc_build_key(self.ctx).decode()
+
+    def model_train(self, db_path, out_path, members=3, epochs=600, batch=256, lr=1e-3, seed=0, holdout=0):
+        o = TrainOpts(members, epochs, batch, lr, seed, holdout, 0)
+        r = TrainReport()
+        self._check(self.L.jacc_model_train(self.ctx, db_path.encode(), out_path.encode(), ctypes.byref(o),
+                                            ctypes.byref(r)))
+        return {"rows": r.rows, "signatures": r.signatures, "loss_first": r.loss_first, "loss_last": r.loss_last,
+                "heldout_mse": r.heldout_mse}
+
+    def model_load(self, path, raw=False):
+        st = self.L.jacc_model_load(self.ctx, path.encode())
+        return st if raw else self._check(st)
+
+    def model_unload(self):
+        return self._check(self.L.jacc_model_unload(self.ctx))
+
+    def model_pick(self, shape, ks, raw=False):
+        """(chosen candidate, candidates, predicted log times)."""
+        best = Candidate()
+        pred = np.zeros(MAX_CANDIDATES, dtype=np.float32)
+        n = ctypes.c_int(0)
+        st = self.L.jacc_model_pick(self.ctx, stencil_kind(shape), _i64s(shape), len(shape), _i32s(ks), len(ks),
+                                    ctypes.byref(best), pred.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                    MAX_CANDIDATES, ctypes.byref(n))
+        if raw:
+            return st
+        self._check(st)
+        return cand_dict(best), candidates(shape, ks), pred[:n.value].copy()
+
+    def choose(self, u_in, u_out, model_path=None, ks=(), db_path=None, tune=True, warmup=0, reps=0):
+        """jacc_choose: (candidate, source) by the chain model -> tuner -> default."""
+        A, b, scal, ns = self._stencil_args(u_in, u_out)
+        o = tune_opts(ks, db_path, warmup, reps)
+        out = Candidate()
+        src = ctypes.c_int(0)
+        self._check(self.L.jacc_choose(self.ctx, stencil_kind(u_in.shape), ctypes.byref(b), 2, A, scal, ns,
+                                       model_path.encode() if model_path else None,
+                                       ctypes.byref(o) if tune else None, ctypes.byref(out), ctypes.byref(src)))
+        return cand_dict(out), src.value
+
     # -- sync / reductions -----------------------------------------------------
     def wait(self):
         return self._check(self.L.jacc_wait(self.ctx))
@@ -533,8 +725,8 @@ class Model:
     def train(self, X, y, epochs, batch=256, lr=1e-3, seed=0):
         X, y = _f32(X), _f32(y)
         losses = np.zeros(max(1, epochs), dtype=np.float32)
-        self.c._check(self.L.jacc_model_train(self.m, _fptr(X), _fptr(y), X.shape[0], epochs, batch,
-                                              ctypes.c_float(lr), ctypes.c_uint64(seed), _fptr(losses)))
+        self.c._check(self.L.jacc_model_fit(self.m, _fptr(X), _fptr(y), X.shape[0], epochs, batch,
+                                            ctypes.c_float(lr), ctypes.c_uint64(seed), _fptr(losses)))
         return losses[:epochs]
 
 
