@@ -266,7 +266,7 @@ int jacc_reduction_read(jacc_ctx *ctx, int first, int count, double *out);
 
 /* Text of the last error on this context (library-owned; valid until the
  * next call on ctx).  jacc_last_error(NULL) gives the reason of the last
- * failed jacc_init on the calling thread. */
+ * failed jacc_init or jacc_heat3d_noalloc on the calling thread. */
 const char *jacc_last_error(const jacc_ctx *ctx);
 
 /* ---- batches: many loop nests in one captured HIP graph ---------------------
@@ -586,6 +586,40 @@ int jacc_adapt_mean_diff(const jacc_adapt *a, double *mean_diff, long long *n_pa
  * planning helper: the runtime partitions dimension 0.  Returns
  * JACC_ERR_INVALID on bad arguments. */
 int jacc_parallel_dim(int ndim, const int *parallel_iters, const int *sequential_iters, int column_major, int *dim);
+
+/* ---- allocation-free heat step ----------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  One heat
+ * step with its residual on caller-owned device buffers, computing exactly
+ * what a one-partition JACC_LOOP_HEAT3D loop with a reduction computes (same
+ * loop body, launch shape and addition order, so the field and the residual
+ * are bit-identical to that loop's), without a context and without any
+ * allocation: the residual's workgroup partials go to a fixed array of
+ * JACC_NOALLOC_MAX_PARTIALS doubles (512 KiB) that the library holds on every
+ * device it runs on until the process ends.
+ *   u_in, u_out  device pointers to nz x ny x nx FP64 fields, row-major with z
+ *                outermost; must not overlap.  u_out's interior
+ *                [1,nz-1) x [1,ny-1) x [1,nx-1) receives
+ *                u + alpha*((((x-1 + x+1) + (y-1 + y+1)) + (z-1 + z+1)) - 6u);
+ *                its boundary faces are not written.
+ *   residual     device pointer to one double receiving the sum over the
+ *                interior of (u_out - u_in)^2 of the stored values, or NULL
+ *                (then no reduction and no size limit).
+ *   stream       hipStream_t to enqueue on (NULL: the null stream); the call
+ *                returns after enqueueing.
+ * The current device is the one that runs the step; on the first call on a
+ * device the library looks up that device's copy of the partials array.
+ * Every call on one device shares that copy (each call overwrites the
+ * partials it reads, so nothing carries over between calls), so calls with a
+ * residual that may overlap in time on one device race: order them on one
+ * stream or by events.  Errors (nothing is launched): JACC_ERR_INVALID for NULL or
+ * overlapping fields or non-positive extents; JACC_ERR_RANGE when the
+ * default launch for these extents needs more than JACC_NOALLOC_MAX_PARTIALS
+ * workgroups (cubes above 1026^3) and residual != NULL; JACC_ERR_DEVICE for a
+ * failed HIP call.  jacc_last_error(NULL) gives the reason. */
+#define JACC_NOALLOC_MAX_PARTIALS 65536
+int jacc_heat3d_noalloc(const double *u_in, double *u_out, int64_t nz, int64_t ny, int64_t nx, double alpha,
+                        double *residual, void *stream);
 
 #ifdef __cplusplus
 }

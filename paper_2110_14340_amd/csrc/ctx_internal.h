@@ -14,6 +14,9 @@ int alloc(jacc_ctx *c, size_t bytes, void **out);
 void release(jacc_ctx *c, void *p);
 int device_error(jacc_ctx *c, hipError_t e, const char *what);  // makes the context sticky
 int error(jacc_ctx *c, int code, const char *msg);
+// reason of a failed context-free call, read back by jacc_last_error(NULL)
+// on the calling thread
+void set_thread_error(const char *msg);
 // descriptor, byte size and partition count of the array whose host copy
 // starts at `host` (JACC_ERR_NOT_PRESENT when there is none)
 int array_info(jacc_ctx *c, const void *host, jacc_array_desc *d, size_t *bytes, int *K);

@@ -37,7 +37,7 @@ constexpr int kEventRing = 16;
 constexpr int64_t kWgCapacity = 1 << 16;  // workgroup partials per stream
 constexpr int kTaskCapacity = 4096;       // persistent tasks per batch
 
-thread_local std::string g_init_err;  // message of the last failed jacc_init
+thread_local std::string g_init_err;  // message of the last failed context-free call (jacc_init, no-alloc step)
 
 struct Range {
     int64_t lo = 0, hi = 0;
@@ -1885,6 +1885,7 @@ int array_info(jacc_ctx *c, const void *host, jacc_array_desc *d, size_t *bytes,
     if (K) *K = A->K;
     return JACC_OK;
 }
+void set_thread_error(const char *msg) { g_init_err = msg ? msg : ""; }
 void *attached_model(const jacc_ctx *c) { return c->model; }
 void attach_model(jacc_ctx *c, void *model, void (*release_model)(void *)) {
     if (c->model && c->model_release) c->model_release(c->model);

@@ -174,6 +174,7 @@ def lib():
     L.jacc_adapt_state.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)]
     L.jacc_adapt_mean_diff.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)]
     L.jacc_parallel_dim.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
+    L.jacc_heat3d_noalloc.argtypes = [vp, vp, i64, i64, i64, d, vp, vp]
     _lib = L
     return L
 
@@ -793,3 +794,32 @@ def parallel_dim(parallel_iters, sequential_iters, column_major=False):
     if rc != OK:
         raise JaccError(rc, "jacc_parallel_dim")
     return out.value
+
+
+NOALLOC_MAX_PARTIALS = 65536
+
+
+def heat3d_noalloc(u_in, u_out, alpha, residual=None, stream=None):
+    """jacc_heat3d_noalloc on device tensors: one heat step of the contiguous
+    FP64 (nz, ny, nx) tensor `u_in` into `u_out`, the residual (a one-element
+    FP64 device tensor, or None) written on the device.  `stream` is a
+    torch.cuda.Stream (default: the current stream).  Raises JaccError with
+    the library's reason on a nonzero status."""
+    import torch
+    for t in (u_in, u_out):
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.dim() == 3 and t.is_contiguous()):
+            raise ValueError("fields must be contiguous 3-D float64 tensors")
+    if tuple(u_in.shape) != tuple(u_out.shape):
+        raise ValueError("u_in and u_out differ in shape")
+    res_ptr = None
+    if residual is not None:
+        if not (residual.dtype == torch.float64 and residual.numel() >= 1):
+            raise ValueError("residual must be a float64 tensor of at least one element")
+        res_ptr = residual.data_ptr()
+    if stream is None:
+        stream = torch.cuda.current_stream(u_in.device) if u_in.is_cuda else None
+    s_ptr = stream.cuda_stream if stream is not None else None
+    nz, ny, nx = u_in.shape
+    rc = lib().jacc_heat3d_noalloc(u_in.data_ptr(), u_out.data_ptr(), nz, ny, nx, float(alpha), res_ptr, s_ptr)
+    if rc != OK:
+        raise JaccError(rc, lib().jacc_last_error(None).decode())

@@ -553,3 +553,27 @@ def test_filtered_jacobi_plan_every_partition_sweeps_the_box_writes_its_block():
                   [(a, jacc.READ, -1, 1, 0), (b, jacc.WRITE | jacc.FILTERED, 0, 0, 0)],
                   cfg=jacc.config(persistent=1), raw=True) == jacc.ERR_UNSUPPORTED
     c.close()
+
+
+def test_noalloc_heat_step_refuses_bad_arguments_before_any_device_call():
+    """jacc_heat3d_noalloc checks its arguments on the host first: these calls
+    are refused before the library touches a device (none exists here), with
+    the reason readable through jacc_last_error(NULL).  The pointers are never
+    dereferenced."""
+    L = jacc.lib()
+    base = 1 << 40
+    n = 64
+    field = n * n * n * 8
+    cases = [
+        ((0, base, n, n, n, 0.1, None), jacc.ERR_INVALID, b"NULL"),
+        ((base, base + 8, n, n, n, 0.1, None), jacc.ERR_INVALID, b"overlap"),
+        ((base, base + field, 0, n, n, 0.1, None), jacc.ERR_INVALID, b"positive"),
+        ((base, base + field, n, n, n, 0.1, base + field // 2), jacc.ERR_INVALID, b"overlaps"),
+        ((base, base + field, 1 << 40, 1 << 40, 4, 0.1, None), jacc.ERR_INVALID, b"overflow"),
+        # 1100^3 with a residual: more workgroup partials than the fixed array holds
+        ((base, base + (1100 ** 3) * 8, 1100, 1100, 1100, 0.1, base - 64), jacc.ERR_RANGE, b"partials"),
+    ]
+    for args, want, text in cases:
+        rc = L.jacc_heat3d_noalloc(*args, None)
+        assert rc == want, (args, rc)
+        assert text in L.jacc_last_error(None), L.jacc_last_error(None)
