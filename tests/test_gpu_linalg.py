@@ -139,6 +139,19 @@ def test_spmv_small(n, K):
         assert np.array_equal(_spmv_dev(rpi, coli, vali, xi, K, cfg), ref_i)
 
 
+@pytest.mark.parametrize("n,K,draws", [(3000, 1, 40), (20000, 3, 70)])
+def test_spmv_rows_longer_than_the_lane_group(n, K, draws):
+    """Rows of up to `draws` entries: every lane of a row group adds several
+    terms in increasing k."""
+    say(f"spmv n={n} K={K} up to {draws} entries per row")
+    rp, col, val, x = inputs.csr_matrix(n, n, draws, seed=11)
+    ref = oracle.spmv_csr(rp, col, val, x)
+    bound = 1e-13 * _row_bound(rp, col, val, x)
+    for lanes, order in ((4, 2), (8, 1), (16, 2)):
+        y = _spmv_dev(rp, col, val, x, K, jacc.config(tile=lanes, order=order))
+        assert np.all(np.abs(y - ref) <= bound)
+
+
 def test_spmv_2_22_rows_k1_k4_every_row():
     say("spmv 2^22 rows K=1,4, every row against the oracle")
     n = 1 << 22
