@@ -61,10 +61,49 @@ def graph_time(shapes, datas, configs, reps=10, keep_outputs=False):
         ctx.close()
 
 
+def copy_bandwidth(nbytes=1 << 28, reps=5):
+    """Device-to-device copy bandwidth (bytes/s, read + write counted once:
+    bytes moved per copy), the peak of Eq. 1 on one GPU."""
+    import torch
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    y.copy_(x)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    t1.record()
+    t1.synchronize()
+    return nbytes * reps / (t0.elapsed_time(t1) * 1e-3)
+
+
+def eq1_partitions(t_dup_s, write_bytes, n, peak):
+    """The partition count Eq. 1 (Sec. "Adaptive Utilization") chooses for a
+    loop whose duplicated (one-partition) execution takes t_dup_s: n when
+    t_dup > t_dup/n + WriteSize/peak, else 1."""
+    return n if t_dup_s > t_dup_s / n + write_bytes / peak else 1
+
+
+def interleaved_times(shapes, datas, configs_by_name, rounds=3, reps=30):
+    """Graph time of each configuration set, measured in `rounds` interleaved
+    rounds (A, B, ..., A, B, ...); the minimum of the per-round medians."""
+    best = {k: float("inf") for k in configs_by_name}
+    for _ in range(rounds):
+        for k, cfgs in configs_by_name.items():
+            ms, _, _ = graph_time(shapes, datas, cfgs, reps)
+            best[k] = min(best[k], ms)
+    return best
+
+
 def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=300, members=3, tune_reps=5, graph_reps=30, log=print,
         test_shapes=None, train_shapes=None, workdir=None):
     """The batched/learned experiment.  Timing databases and the model file
-    go to `workdir` (a fresh temporary directory by default)."""
+    go to `workdir` (a fresh temporary directory by default).  Besides the
+    exhaustive, learned and default configurations, a fourth set takes the
+    partition count from Eq. 1 (duplicate or split over the largest K) and
+    the rest of the configuration from the tuner's best candidate at that
+    partition count."""
     t_start = time.perf_counter()
     test_shapes = test_shapes or inputs.batch_shapes(5, n2d, n3d)
     train_shapes = train_shapes or inputs.batch_shapes(7, train2d, train3d)
@@ -89,8 +128,10 @@ def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=300, members=3, tune_re
             f"loss {rep['loss_first']:.4f} -> {rep['loss_last']:.4f} in {epochs} epochs ({t_fit:.1f} s), "
             f"held-out mse {rep['heldout_mse']:.4f}")
         ctx.model_load(model_path)
-        # 3. the test batch: exhaustive choice, model choice, default
-        exh, mlp, dflt, datas, regret_loop = [], [], [], [], []
+        # 3. the test batch: exhaustive choice, model choice, default, Eq. 1
+        peak = copy_bandwidth()
+        nmax = max(tuner.KS)
+        exh, mlp, dflt, rule, datas, regret_loop = [], [], [], [], [], []
         t0 = time.perf_counter()
         for li, sh in enumerate(test_shapes):
             d = _data(sh, 6000 + li)
@@ -102,6 +143,11 @@ def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=300, members=3, tune_re
             mlp.append(pick)
             dflt.append(dict(tuner.DEFAULT_CONFIG))
             regret_loop.append(meds[cands.index(pick)] / meds[best] - 1.0)
+            one = [i for i, c in enumerate(cands) if c["K"] == 1]
+            t_dup = min(meds[i] for i in one) * 1e-3
+            k_rule = eq1_partitions(t_dup, 8.0 * float(np.prod([d - 2 for d in sh])), nmax, peak)
+            at_k = [i for i, c in enumerate(cands) if c["K"] == k_rule]
+            rule.append(cands[min(at_k, key=lambda i: (meds[i], i))])
             if li % 32 == 31:
                 log(f"  tuned {li + 1}/{len(test_shapes)} test shapes")
         t_test_tune = time.perf_counter() - t0
@@ -111,17 +157,23 @@ def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=300, members=3, tune_re
     t_exh, info_e, out_e = graph_time(test_shapes, datas, exh, graph_reps, keep_outputs=True)
     t_mlp, info_m, out_m = graph_time(test_shapes, datas, mlp, graph_reps, keep_outputs=True)
     t_def, info_d, out_d = graph_time(test_shapes, datas, dflt, graph_reps, keep_outputs=True)
-    identical = all(np.array_equal(a, b) and np.array_equal(a, c) for a, b, c in zip(out_e, out_m, out_d))
+    t_rule, info_r, out_r = graph_time(test_shapes, datas, rule, graph_reps, keep_outputs=True)
+    identical = all(np.array_equal(a, b) and np.array_equal(a, c) and np.array_equal(a, d)
+                    for a, b, c, d in zip(out_e, out_m, out_d, out_r))
     cells = sum(float(np.prod([d - 2 for d in sh])) for sh in test_shapes)
     alg_bytes = 16.0 * cells
-    ks_used = {"exhaustive": sorted({c["K"] for c in exh}), "learned": sorted({c["K"] for c in mlp})}
+    ks_used = {"exhaustive": sorted({c["K"] for c in exh}), "learned": sorted({c["K"] for c in mlp}),
+               "eq1_rule": sorted({c["K"] for c in rule})}
     result = {
         "loops": len(test_shapes),
         "algorithmic_gb": round(alg_bytes / 1e9, 3),
-        "graph_ms": {"exhaustive": round(t_exh, 4), "learned": round(t_mlp, 4), "default": round(t_def, 4)},
+        "graph_ms": {"exhaustive": round(t_exh, 4), "learned": round(t_mlp, 4), "default": round(t_def, 4),
+                     "eq1_rule": round(t_rule, 4)},
         "graph_gbps": {"exhaustive": round(alg_bytes / t_exh / 1e6, 1), "learned": round(alg_bytes / t_mlp / 1e6, 1),
-                       "default": round(alg_bytes / t_def / 1e6, 1)},
+                       "default": round(alg_bytes / t_def / 1e6, 1), "eq1_rule": round(alg_bytes / t_rule / 1e6, 1)},
         "regret_learned_vs_exhaustive": round(t_mlp / t_exh - 1.0, 4),
+        "regret_eq1_rule_vs_exhaustive": round(t_rule / t_exh - 1.0, 4),
+        "eq1_peak_gbps": round(peak / 1e9, 1),
         "gain_learned_vs_default": round(t_def / t_mlp, 3),
         "mean_per_loop_regret": round(float(np.mean(regret_loop)), 4),
         "median_per_loop_regret": round(float(np.median(regret_loop)), 4),
@@ -135,7 +187,7 @@ def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=300, members=3, tune_re
         "heldout_mse": round(float(rep["heldout_mse"]), 5),
         "seconds": round(time.perf_counter() - t_start, 1),
     }
-    return result, (test_shapes, datas, out_m)
+    return result, (test_shapes, datas, out_m, {"exhaustive": exh, "learned": mlp, "default": dflt, "eq1_rule": rule})
 
 
 def independent_loops(n_loops=96, streams=(1, 4, 16), steps=2, seed=11, reps=5, keep_outputs=False):

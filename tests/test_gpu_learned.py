@@ -17,8 +17,8 @@ def test_small_batched_learned_experiment():
     say("learned experiment, small")
     test_shapes = inputs.batch_shapes(5, 10, 6, side2d=(64, 400), side3d=(32, 64))
     train_shapes = inputs.batch_shapes(7, 6, 4, side2d=(64, 400), side3d=(32, 64))
-    res, (shapes, datas, outs) = experiment.run(epochs=80, tune_reps=3, graph_reps=5, log=say,
-                                                test_shapes=test_shapes, train_shapes=train_shapes)
+    res, (shapes, datas, outs, _) = experiment.run(epochs=80, tune_reps=3, graph_reps=5, log=say,
+                                                   test_shapes=test_shapes, train_shapes=train_shapes)
     say(str(res))
     assert res["outputs_bit_identical_across_configs"]
     for sh, d, o in zip(shapes, datas, outs):
@@ -30,6 +30,31 @@ def test_small_batched_learned_experiment():
         assert np.array_equal(o, ref), sh
     assert res["model_loss_first_last"][1] < res["model_loss_first_last"][0]
     assert np.isfinite(res["regret_learned_vs_exhaustive"])
+
+
+def test_learned_batch_within_five_percent_of_the_tuner_and_faster_than_default():
+    """What the trained network gains.  A fixed seeded batch of 48 uneven
+    sweeps (24 2-D with sides log-uniform in [64, 2048], 24 3-D in [32, 256])
+    runs as one graph configured three ways; the network was trained on the
+    tuner's timings of 96 other shapes of the same laws.  The learned graph
+    is within 5 % of the exhaustive tuner's and faster than the fixed default
+    configuration (graph times: the minimum over three interleaved rounds of
+    the median of 30 replays).  Every output is bit-identical across the
+    configurations, including the Eq. 1 rule's."""
+    say("learned vs exhaustive vs default, 48-loop batch")
+    test_shapes = inputs.batch_shapes(5, 24, 24, side2d=(64, 2048), side3d=(32, 256))
+    train_shapes = inputs.batch_shapes(7, 48, 48, side2d=(64, 2048), side3d=(32, 256))
+    res, (shapes, datas, _, cfgs) = experiment.run(epochs=300, tune_reps=5, graph_reps=30, log=say,
+                                                   test_shapes=test_shapes, train_shapes=train_shapes)
+    say(str(res))
+    assert res["outputs_bit_identical_across_configs"]
+    t = experiment.interleaved_times(shapes, datas, {k: cfgs[k] for k in ("exhaustive", "learned", "default")},
+                                     rounds=3, reps=30)
+    regret = t["learned"] / t["exhaustive"] - 1.0
+    gain = t["default"] / t["learned"]
+    say(f"  graph ms {t}; regret {regret:+.4f}, gain over default {gain:.3f}")
+    assert regret <= 0.05, f"learned graph {regret:+.2%} slower than the exhaustive tuner's"
+    assert gain > 1.0, f"learned graph not faster than the default ({gain:.3f}x)"
 
 
 def test_full_batch_of_256_sweeps_in_one_graph_equals_oracle():
