@@ -184,14 +184,42 @@ typedef struct {
  *   SCATTER_SQ in (f64) R WHOLE; idx (int32) R WHOLE; out (f64) W|FILTERED.
  *             1-D bounds over i.  out[idx[i]] = in[i]*in[i] (the map of the
  *             paper's OpenACC example with an indirect write); indices must be
- *             distinct; an index outside [0, rows of out) is skipped. */
+ *             distinct; an index outside [0, rows of out) is skipped.
+ *   PRED_CHAIN a (f64) W|FILTERED; b (f64) W|FILTERED; c (f64) R WHOLE; idx
+ *             (int32, T x 3) R WHOLE; xs (f64, T) R WHOLE.  a and b are entered
+ *             whole (replicated).  1-D bounds over t in [0, T).  The statement
+ *             chain of the paper's filtering example (Sec. "Predicate-Based
+ *             Filtering", Fig. conv-code): with (i, j, k) = idx[t], x = xs[t]:
+ *               a[i] = x;  b[i] = a[i];  x = c[j];  a[k] = x;  b[k] = a[k];
+ *             Every partition runs every iteration on its own replicas of a
+ *             and b under the example's guards: a's writes and the read of c
+ *             are kept where the index lies in a's or b's owner block of the
+ *             partition, b's writes where it lies in b's.  Iterations must not
+ *             write an element another iteration touches; an iteration with i
+ *             or k outside [0, min(rows of a, rows of b)) or j outside
+ *             [0, rows of c) is skipped.
+ *
+ * FILTERED writes into an array entered whole: partition p's owner block of
+ * that array is B_p (the equal division of dim 0); after the loop B_p of
+ * partition p's replica holds the array's rows and the other replicas' copies
+ * of B_p are stale (they are pulled when read, or broadcast at once under
+ * JACC_INIT_EAGER).  Writes a partition makes outside its owner block stay
+ * private to its replica.
+ *
+ * Aliasing (Sec. "Predicate-Based Filtering"): when one array is passed in
+ * two argument positions and one of them writes, the partition ranges cannot
+ * be trusted; if every argument's array is entered whole the loop runs
+ * duplicated — every partition computes the whole iteration space on its own
+ * replicas without filtering, and no rows move afterwards (every replica then
+ * holds the result) — otherwise the call returns JACC_ERR_RANGE. */
 enum {
     JACC_LOOP_JACOBI2D = 1,
     JACC_LOOP_HEAT3D = 2,
     JACC_LOOP_SUM = 3,
     JACC_LOOP_GEMM = 4,
     JACC_LOOP_SPMV_CSR = 5,
-    JACC_LOOP_SCATTER_SQ = 6
+    JACC_LOOP_SCATTER_SQ = 6,
+    JACC_LOOP_PRED_CHAIN = 7
 };
 
 /* jacc_init flags */
@@ -206,7 +234,10 @@ enum {
                                       (which wait for the neighbours), so no partition's bulk
                                       waits on another stream; default for 2 to 4 partitions,
                                       this flag asks for it at any partition count */
-    JACC_INIT_NO_SPLIT = 1u << 5   /* never split (one launch per partition) */
+    JACC_INIT_NO_SPLIT = 1u << 5,  /* never split (one launch per partition) */
+    JACC_INIT_EAGER = 1u << 6      /* the paper's coherence: after every loop each partition
+                                      sends the rows it wrote to every other slab holding them
+                                      (device copies on its stream); no mirror stores, no pulls */
 };
 
 /* Create a context with K partitions (1 <= K <= 64).  streams: K hipStream_t
@@ -513,7 +544,11 @@ enum {
     JACC_OP_SYNC = 9,    /* host waits for stream */
     JACC_OP_COMBINE = 10, /* reduction combine on stream into slot `kind` */
     JACC_OP_ACCESS = 11,  /* the op `seq` on stream touches slab dst of array rows
-                             [lo,hi): kind 1 = read, 2 = write */
+                             [lo,hi): kind 1 = read, 2 = write, 3 = write of values
+                             private to that slab (a filtered loop's writes outside
+                             the partition's owner block), 4 = write of the values
+                             the same loop writes in the first partition's slab (a
+                             duplicated loop) */
     JACC_OP_JOIN = 12     /* all streams joined: every later op is ordered after every
                              earlier op (around graph launches and timed runs) */
 };

@@ -82,6 +82,11 @@ def lib():
         L.oracle_scatter_sq.restype = None
         L.oracle_scatter_sq_partitioned.argtypes = [_f64p, _i32p, _f64p, _i64, _i64, _i64, ctypes.c_int]
         L.oracle_scatter_sq_partitioned.restype = ctypes.c_int
+        L.oracle_pred_chain.argtypes = [_f64p, _i64, _f64p, _i64, _f64p, _i64, _i32p, _f64p, _i64, _i64]
+        L.oracle_pred_chain.restype = None
+        L.oracle_pred_chain_partitioned.argtypes = [_f64p, _i64, _f64p, _i64, _f64p, _i64, _i32p, _f64p, _i64, _i64,
+                                                    ctypes.c_int]
+        L.oracle_pred_chain_partitioned.restype = ctypes.c_int
         L.oracle_threads.argtypes = [ctypes.c_int]
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_jacobi2d_mt.argtypes = [_f64p, _f64p, _i64, _i64, _i64, ctypes.c_int]
@@ -246,6 +251,33 @@ def scatter_sq_partitioned(inp, idx, out, K, rows=None):
     lo, hi = rows if rows is not None else (0, inp.size)
     assert lib().oracle_scatter_sq_partitioned(inp, idx, o, o.size, lo, hi, K) == 0
     return o
+
+
+# --------------------------------------------------------------------------
+# Statement chain of the paper's predicate-filtering example (Sec.
+# "Predicate-Based Filtering", Fig. conv-code)
+# --------------------------------------------------------------------------
+def pred_chain(a, b, c, idx, xs, rows=None):
+    """Plain sequential chain; returns new (a, b).  `b is a` runs the aliased
+    form (one array written through both names) and returns it twice."""
+    idx = _c(idx, np.int32).reshape(-1, 3)
+    c, xs = _c(c), _c(xs)
+    lo, hi = rows if rows is not None else (0, xs.size)
+    ra = _c(a).copy()
+    rb = ra if b is a else _c(b).copy()
+    lib().oracle_pred_chain(ra, ra.size, rb, rb.size, c, c.size, idx, xs, lo, hi)
+    return ra, rb
+
+
+def pred_chain_partitioned(a, b, c, idx, xs, K, rows=None):
+    """The chain on K replicas with the example's guards, owner rows
+    gathered; returns new (a, b)."""
+    idx = _c(idx, np.int32).reshape(-1, 3)
+    c, xs = _c(c), _c(xs)
+    lo, hi = rows if rows is not None else (0, xs.size)
+    ra, rb = _c(a).copy(), _c(b).copy()
+    assert lib().oracle_pred_chain_partitioned(ra, ra.size, rb, rb.size, c, c.size, idx, xs, lo, hi, K) == 0
+    return ra, rb
 
 
 # --------------------------------------------------------------------------

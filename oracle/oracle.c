@@ -444,6 +444,79 @@ void oracle_spmv_csr(const int32_t *rp, const int32_t *col, const double *val, c
 }
 
 /* ------------------------------------------------------------------------ */
+/* Statement chain of the paper's predicate-filtering example (Sec.          */
+/* "Predicate-Based Filtering", Fig. conv-code).  Iteration t, in order,      */
+/* with (i, j, k) = idx[3t..3t+2] and x = xs[t]:                              */
+/*   a[i] = x;  b[i] = a[i];  x = c[j];  a[k] = x;  b[k] = a[k];             */
+/* An iteration whose i or k lies outside [0, min(na, nb)) or whose j lies   */
+/* outside [0, nc) is skipped.  a and b may be the same array.               */
+/* ------------------------------------------------------------------------ */
+void oracle_pred_chain(double *a, int64_t na, double *b, int64_t nb, const double *c, int64_t nc,
+                       const int32_t *idx, const double *xs, int64_t lo, int64_t hi)
+{
+    int64_t nab = na < nb ? na : nb;
+    for (int64_t t = lo; t < hi; ++t) {
+        int64_t i = idx[3 * t], j = idx[3 * t + 1], k = idx[3 * t + 2];
+        if (i < 0 || i >= nab || k < 0 || k >= nab || j < 0 || j >= nc) continue;
+        double x = xs[t];
+        a[i] = x;
+        b[i] = a[i];
+        x = c[j];
+        a[k] = x;
+        b[k] = a[k];
+    }
+}
+
+/* The same chain run the paper's way on K devices: every device holds its
+ * own copies of a and b and runs every iteration, each statement guarded as
+ * in the example by the owner ranges (equal division) of the arrays whose
+ * local values it feeds; afterwards each device's owner rows are what the
+ * others receive, so the result is the owner rows gathered.  Returns 0, or
+ * -1 on a bad K or a failed allocation. */
+int oracle_pred_chain_partitioned(double *a, int64_t na, double *b, int64_t nb, const double *c, int64_t nc,
+                                  const int32_t *idx, const double *xs, int64_t lo, int64_t hi, int K)
+{
+    if (K < 1 || K > na || K > nb) return -1;
+    int64_t nab = na < nb ? na : nb;
+    double *ra = malloc((size_t)na * sizeof(double)), *rb = malloc((size_t)nb * sizeof(double));
+    double *out_a = malloc((size_t)na * sizeof(double)), *out_b = malloc((size_t)nb * sizeof(double));
+    if (!ra || !rb || !out_a || !out_b) {
+        free(ra);
+        free(rb);
+        free(out_a);
+        free(out_b);
+        return -1;
+    }
+    for (int p = 0; p < K; ++p) {
+        int64_t alo = block_lo(na, K, p), ahi = block_lo(na, K, p + 1);
+        int64_t blo = block_lo(nb, K, p), bhi = block_lo(nb, K, p + 1);
+        memcpy(ra, a, (size_t)na * sizeof(double)); /* device p's replicas */
+        memcpy(rb, b, (size_t)nb * sizeof(double));
+        for (int64_t t = lo; t < hi; ++t) {
+            int64_t i = idx[3 * t], j = idx[3 * t + 1], k = idx[3 * t + 2];
+            if (i < 0 || i >= nab || k < 0 || k >= nab || j < 0 || j >= nc) continue;
+            int i_a = alo <= i && i < ahi, i_b = blo <= i && i < bhi;
+            int k_a = alo <= k && k < ahi, k_b = blo <= k && k < bhi;
+            double x = xs[t];
+            if (i_a || i_b) ra[i] = x;
+            if (i_b) rb[i] = ra[i];
+            x = (k_a || k_b) ? c[j] : 0.0;
+            if (k_a || k_b) ra[k] = x;
+            if (k_b) rb[k] = ra[k];
+        }
+        memcpy(out_a + alo, ra + alo, (size_t)(ahi - alo) * sizeof(double));
+        memcpy(out_b + blo, rb + blo, (size_t)(bhi - blo) * sizeof(double));
+    }
+    memcpy(a, out_a, (size_t)na * sizeof(double));
+    memcpy(b, out_b, (size_t)nb * sizeof(double));
+    free(ra);
+    free(rb);
+    free(out_a);
+    free(out_b);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Indirect write: out[idx[i]] = in[i]*in[i] for i in [lo, hi) (distinct     */
 /* indices; an index outside [0, n_out) is skipped).                         */
 /* ------------------------------------------------------------------------ */

@@ -78,6 +78,7 @@ int check_config(const Launch &L) {
             return ((c.tile == 4 || c.tile == 8 || c.tile == 16) && (c.order == 1 || c.order == 2)) ? 0 : 1;
         case JACC_LOOP_SUM:
         case JACC_LOOP_SCATTER_SQ:
+        case JACC_LOOP_PRED_CHAIN:
             return 0;  // fixed internal configurations; fields are ignored
         default:
             return 1;
@@ -104,6 +105,7 @@ hipError_t launch_loop(const Launch &L, hipStream_t s) {
         case JACC_LOOP_GEMM: return launch_gemm(L, s);
         case JACC_LOOP_SPMV_CSR: return launch_spmv(L, s);
         case JACC_LOOP_SCATTER_SQ: return launch_scatter(L, s);
+        case JACC_LOOP_PRED_CHAIN: return launch_chain(L, s);
         default: return hipErrorInvalidValue;
     }
 }

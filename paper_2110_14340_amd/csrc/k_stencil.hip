@@ -191,7 +191,8 @@ __device__ __forceinline__ double heat_tile(const double *__restrict__ in, doubl
                                             int64_t nx, int64_t z_lo, int64_t z_hi, int64_t y_lo, int64_t y_hi,
                                             int64_t x_lo, int64_t x_hi, int64_t col0, int tile, int march, double alpha,
                                             const Mirrors &mir, int64_t bxi, int64_t byi, int64_t bzi, int tx,
-                                            int ty, int bdx, int bdy) {
+                                            int ty, int bdx, int bdy, int64_t own_lo = INT64_MIN,
+                                            int64_t own_hi = INT64_MAX) {
     const int lane = tx & (kWave - 1);
     const int64_t x = col0 + (bxi * bdx + tx) * VEC;
     const int64_t y = y_lo + byi * bdy + ty;
@@ -231,6 +232,7 @@ __device__ __forceinline__ double heat_tile(const double *__restrict__ in, doubl
         for (int k = 0; k < kU; ++k) {
             if (m + k < n) {
                 const int64_t z = a + (m + k) * d;
+                const bool keep = z >= own_lo && z < own_hi;  // write guard of a filtered loop
                 const Row<VEC> &zprev = r[k], &c = r[k + 1], &znext = r[k + 2];
                 // y neighbours: rows of the same plane (cache hits)
                 double ym[VEC], yp[VEC];
@@ -252,12 +254,12 @@ __device__ __forceinline__ double heat_tile(const double *__restrict__ in, doubl
                     const double pz = zprev.v[v] + znext.v[v];
                     const double lap = ((px + py) + pz) - 6.0 * c.v[v];
                     o[v] = c.v[v] + alpha * lap;
-                    if (RES && comp[v]) {
+                    if (RES && comp[v] && keep) {
                         const double dd = o[v] - c.v[v];
                         acc += dd * dd;
                     }
                 }
-                store_out<VEC>(out, z * plane + y * nx + x, z, mir, o, all, comp);
+                if (keep) store_out<VEC>(out, z * plane + y * nx + x, z, mir, o, all, comp);
             }
         }
 #pragma unroll
@@ -313,7 +315,8 @@ __device__ __forceinline__ double heat_rows_tile(const double *__restrict__ in, 
                                                  int64_t nx, int64_t z_lo, int64_t z_hi, int64_t y_lo, int64_t y_hi,
                                                  int64_t x_lo, int64_t x_hi, int64_t col0, int tile, int march,
                                                  double alpha, const Mirrors &mir, int64_t bxi, int64_t byi,
-                                                 int64_t bzi, int tx, int ty, int bdx, int bdy) {
+                                                 int64_t bzi, int tx, int ty, int bdx, int bdy, int64_t own_lo,
+                                                 int64_t own_hi) {
     const int lane = tx & (kWave - 1);
     const int64_t x = col0 + (bxi * bdx + tx) * VEC;
     const int64_t yb = y_lo + (byi * bdy + ty) * R;
@@ -352,6 +355,7 @@ __device__ __forceinline__ double heat_rows_tile(const double *__restrict__ in, 
             for (int v = 0; v < VEC; ++v) pz[i][v] = A.v[i + 1][v] + C.v[i + 1][v];
         if (m + 3 <= n + 1) load(m + 3, A);
         const int64_t z = a + m * d;
+        const bool keep = z >= own_lo && z < own_hi;  // write guard of a filtered loop
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             if (i < rr) {
@@ -368,12 +372,12 @@ __device__ __forceinline__ double heat_rows_tile(const double *__restrict__ in, 
                     const double py = B.v[i][v] + B.v[i + 2][v];
                     const double lap = ((px + py) + pz[i][v]) - 6.0 * c.v[v];
                     o[v] = c.v[v] + alpha * lap;
-                    if (RES && comp[v]) {
+                    if (RES && comp[v] && keep) {
                         const double dd = o[v] - c.v[v];
                         acc += dd * dd;
                     }
                 }
-                store_out<VEC>(out, z * plane + (yb + i) * nx + x, z, mir, o, all, comp);
+                if (keep) store_out<VEC>(out, z * plane + (yb + i) * nx + x, z, mir, o, all, comp);
             }
         }
     };
@@ -421,7 +425,7 @@ __global__ void __launch_bounds__(R == 1 ? 1024 : 256)
 heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t ny, int64_t nx, int64_t z_lo,
               int64_t z_hi, int64_t y_lo, int64_t y_hi, int64_t x_lo, int64_t x_hi, int64_t col0, int tile,
               int march, double alpha, double *__restrict__ wg_partials, Mirrors mir, int64_t gx, int64_t gy,
-              int order) {
+              int order, int64_t own_lo, int64_t own_hi) {
     __shared__ double sh[16];
     const int64_t t = tile_of(order == 3 ? 2 : order);
     const int64_t gz = (int64_t)gridDim.x / (gx * gy);
@@ -430,11 +434,11 @@ heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t n
     double acc;
     if constexpr (R == 1)
         acc = heat_tile<VEC, RES>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, march, alpha, mir,
-                                  bxi, byi, bzi, threadIdx.x, threadIdx.y, blockDim.x, blockDim.y);
+                                  bxi, byi, bzi, threadIdx.x, threadIdx.y, blockDim.x, blockDim.y, own_lo, own_hi);
     else
         acc = heat_rows_tile<VEC, R, RES>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, march,
                                           alpha, mir, bxi, byi, bzi, threadIdx.x, threadIdx.y, blockDim.x,
-                                          blockDim.y);
+                                          blockDim.y, own_lo, own_hi);
     if (RES) {
         const double s = block_sum(acc, sh);
         if (threadIdx.x == 0 && threadIdx.y == 0) wg_partials[t] = s;  // partials in tile order
@@ -546,9 +550,11 @@ hipError_t launch_heat3d(const Launch &L, hipStream_t s) {
     double *out = (double *)L.a[1].ptr;
     const double alpha = L.scalars[0];
     const bool res = L.wg_partials != nullptr;
+    const bool filtered = L.own_hi > L.own_lo;  // FILTERED output: keep the owner planes only
+    const int64_t own_lo = filtered ? L.own_lo : INT64_MIN, own_hi = filtered ? L.own_hi : INT64_MAX;
 #define HEAT_ARGS                                                                                                    \
     in, out, ny, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1], L.lo[2], L.hi[2], col0, c.tile, c.march, alpha,             \
-        L.wg_partials, L.mir, gx, gy, c.order
+        L.wg_partials, L.mir, gx, gy, c.order, own_lo, own_hi
 #define HEAT_LAUNCH(V, R)                                                                 \
     do {                                                                                  \
         if (res)                                                                          \

@@ -43,7 +43,8 @@ struct Launch {
     double scalars[4];
     Cfg cfg;
     Mirrors mir;  // stencil kinds only
-    int64_t own_lo, own_hi;  // owner rows of a FILTERED output (writes elsewhere are dropped)
+    int64_t own_lo, own_hi;    // owner rows of a FILTERED output (writes elsewhere are dropped)
+    int64_t own2_lo, own2_hi;  // owner rows of a second FILTERED output (PRED_CHAIN's b)
     // reductions: workgroup partials go to `wg_partials` (capacity
     // `wg_capacity` doubles); the finaliser writes their ordered sum to
     // `part_out`.  Both null when the loop reduces nothing.
@@ -113,6 +114,7 @@ hipError_t launch_finalise(const double *partials, int64_t n, double *out, hipSt
 hipError_t launch_gemm(const Launch &L, hipStream_t s);
 hipError_t launch_spmv(const Launch &L, hipStream_t s);
 hipError_t launch_scatter(const Launch &L, hipStream_t s);
+hipError_t launch_chain(const Launch &L, hipStream_t s);
 
 // ---- learned cost model (k_mlp.hip) ----------------------------------------
 constexpr int kMlpHidden = 64;

@@ -259,6 +259,7 @@ struct jacc_ctx {
     bool lazy = false;       // pull halo rows before reads instead of mirroring them at writes
     bool split = false;      // stencil partitions: own-block rows first, edge rows after (any K)
     bool no_split = false;   // never split (default: split at K <= 4)
+    bool eager = false;      // broadcast written rows to every holder after each loop
     bool plan_only = false;  // planning pass without device work (batch replay check)
     jacc_allocator alloc{};
     bool use_hipmalloc = true;
@@ -455,7 +456,11 @@ int fork_from0(jacc_ctx *c) {
 
 // Hazard bookkeeping for an access by stream s (its next op, seq+1) to rows r
 // of slab p of array A.  write: RAW+WAW+WAR waits, then becomes last writer.
-int hazard(jacc_ctx *c, Array *A, int p, Range r, bool write, int s) {
+// wkind: how a write is traced — 2 a write, 3 values private to the slab (a
+// filtered loop's writes outside the partition's owner block), 4 the value
+// the same loop computes in every replica (a duplicated loop's partitions
+// after the first).
+int hazard(jacc_ctx *c, Array *A, int p, Range r, bool write, int s, int wkind = 2) {
     if (r.empty()) return JACC_OK;
     Slab &sl = A->slabs[p];
     std::vector<std::pair<int, int64_t>> need;
@@ -488,7 +493,7 @@ int hazard(jacc_ctx *c, Array *A, int p, Range r, bool write, int s) {
         }
     });
     sl.acc.coalesce();
-    trace(c, JACC_OP_ACCESS, s, A->id, -1, p, write ? 2 : 1, r.lo, r.hi, next);
+    trace(c, JACC_OP_ACCESS, s, A->id, -1, p, write ? wkind : 1, r.lo, r.hi, next);
     return JACC_OK;
 }
 
@@ -561,6 +566,14 @@ void note_write(Array *A, int p, Range w) {
         else
             A->valid[q].sub(w);
     }
+}
+
+// Rows every replica computed alike (a duplicated loop): valid in every
+// holder, with no single latest writer.
+void note_everywhere(Array *A, Range w) {
+    if (w.empty()) return;
+    A->writer.assign(w, -1);
+    for (int q = 0; q < A->K; ++q) A->valid[q].add(w);
 }
 
 // Source of each row for gathers: the last writer, else the block owner.
@@ -725,6 +738,7 @@ bool kind_info(int kind, KindInfo *k) {
         case JACC_LOOP_GEMM: *k = {3, 2, 0}; return true;
         case JACC_LOOP_SPMV_CSR: *k = {5, 1, 0}; return true;
         case JACC_LOOP_SCATTER_SQ: *k = {3, 1, 0}; return true;
+        case JACC_LOOP_PRED_CHAIN: *k = {5, 1, 0}; return true;
         default: return false;
     }
 }
@@ -747,7 +761,7 @@ struct PartPlan {
 // the iterations (the written array; the read array for SUM).
 int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc_arg *args, const double *scalars,
                  int nscalars, bool want_red, const jacc_config *cfg, Array **arr, jk::Launch &L,
-                 std::vector<PartPlan> &plan, int *primary_out) {
+                 std::vector<PartPlan> &plan, int *primary_out, bool *dup_out) {
     KindInfo ki;
     if (!kind_info(kind, &ki)) return set_err(c, JACC_ERR_INVALID, "unknown loop kind %d", kind);
     if (!b || nargs != ki.nargs || !args)
@@ -837,28 +851,61 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
             if (b->hi[0] > arr[0]->E) return set_err(c, JACC_ERR_RANGE, "SCATTER_SQ bounds exceed in");
             primary = 2;
             break;
+        case JACC_LOOP_PRED_CHAIN:
+            if (!is(0, JACC_F64, 1) || !is(1, JACC_F64, 1) || !is(2, JACC_F64, 1) || !is(3, JACC_I32, 2) ||
+                !is(4, JACC_F64, 1) || arr[3]->d.extent[1] != 3)
+                return set_err(c, JACC_ERR_INVALID, "PRED_CHAIN takes f64 a, b, c, int32 idx (T x 3) and f64 xs (T)");
+            if (arr[3]->E != arr[4]->E) return set_err(c, JACC_ERR_INVALID, "PRED_CHAIN: idx and xs differ in length");
+            for (int i = 0; i < 2; ++i)
+                if (!(args[i].mode & JACC_FILTERED) || !arr[i]->whole)
+                    return set_err(c, JACC_ERR_INVALID,
+                                   "PRED_CHAIN writes a and b FILTERED into arrays entered whole (replicated)");
+            for (int i = 2; i < 5; ++i)
+                if (!args[i].whole) return set_err(c, JACC_ERR_INVALID, "PRED_CHAIN reads c, idx and xs whole");
+            if (b->hi[0] > arr[3]->E) return set_err(c, JACC_ERR_RANGE, "PRED_CHAIN bounds exceed idx");
+            primary = 0;
+            break;
     }
     if (!(args[primary].mode & JACC_WRITE) && kind != JACC_LOOP_SUM)
         return set_err(c, JACC_ERR_INVALID, "the output argument must be declared writable");
 
     Array *P = arr[primary];
+    // Aliasing: one array in two argument positions, one of them written (the
+    // paper's aliased pointers).  The partition ranges cannot be trusted; with
+    // every array replicated the loop runs duplicated (each partition computes
+    // everything on its own replicas, unfiltered, and nothing moves after it),
+    // otherwise it is refused.
+    bool aliased = false, all_whole = true;
+    for (int i = 0; i < nargs; ++i) {
+        all_whole = all_whole && arr[i]->whole;
+        for (int j = 0; j < i; ++j)
+            if (arr[i] == arr[j] && ((args[i].mode | args[j].mode) & JACC_WRITE)) aliased = true;
+    }
+    if (aliased && !all_whole)
+        return set_err(c, JACC_ERR_RANGE,
+                       "an argument array is aliased (read and written through two arguments) and not entered "
+                       "whole: duplicated execution needs replicas");
+    const bool dup = aliased;
+    *dup_out = dup;
     // A filtered output is written through data-dependent indices: every
     // partition runs the whole iteration space (the write-index arithmetic is
-    // duplicated) and keeps the writes that land in its owner block.
+    // duplicated) and keeps the writes that land in its owner block.  A
+    // filtered output entered whole is divided into owner blocks like a
+    // partitioned one; its replicas hold every row.
     const bool filtered = (args[primary].mode & JACC_FILTERED) != 0;
     plan.assign(K, PartPlan{});
     for (int p = 0; p < K; ++p) {
-        Range own = P->whole ? (p == 0 ? Range{0, P->E} : Range{0, 0}) : P->block(p);
-        plan[p].iters = filtered ? Range{b->lo[0], b->hi[0]} : isect({b->lo[0], b->hi[0]}, own);
-        if (filtered && own.empty()) plan[p].iters = Range{};
+        Range own = (P->whole && !filtered) ? (p == 0 ? Range{0, P->E} : Range{0, 0}) : P->block(p);
+        plan[p].iters = (filtered || dup) ? Range{b->lo[0], b->hi[0]} : isect({b->lo[0], b->hi[0]}, own);
+        if (filtered && !dup && own.empty()) plan[p].iters = Range{};
         plan[p].rng.resize(nargs);
         for (int i = 0; i < nargs; ++i) {
             Range r{};
             if (!plan[p].iters.empty()) {
-                if (args[i].whole)
+                if (args[i].whole || dup)
                     r = {0, arr[i]->E};
                 else if (args[i].mode & JACC_FILTERED)
-                    r = own;
+                    r = arr[i]->block(p);
                 else
                     r = isect({plan[p].iters.lo + args[i].off_lo, plan[p].iters.hi - 1 + args[i].off_hi + 1},
                               {0, arr[i]->E});
@@ -881,7 +928,7 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
     }
     // one array written by two partitions, or read by one partition where
     // another writes it in the same loop (the paper duplicates such loops)
-    for (int i = 0; i < nargs; ++i) {
+    for (int i = 0; i < nargs && !dup; ++i) {
         if (!(args[i].mode & JACC_WRITE)) continue;
         for (int j = 0; j < nargs; ++j) {
             if (arr[j] != arr[i]) continue;
@@ -933,7 +980,8 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     jk::Launch L;
     std::vector<PartPlan> plan;
     int primary = -1;
-    int rc = prepare_loop(c, kind, b, nargs, args, scalars, nscalars, want_red, cfg, arr, L, plan, &primary);
+    bool dup = false;
+    int rc = prepare_loop(c, kind, b, nargs, args, scalars, nscalars, want_red, cfg, arr, L, plan, &primary, &dup);
     if (rc) return rc;
     const bool persistent = L.cfg.persistent != 0;
     // a pending persistent group is launched before anything that touches
@@ -983,6 +1031,14 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     // persistent launch when the configuration asks for it
     const bool one_stream = c->serialize || c->cur != nullptr;
     auto stream_for = [&](int p) { return (one_stream || persistent) ? 0 : (base + p) % ns; };
+    // rows of its slab a partition may write: a filtered output entered
+    // whole takes private writes anywhere in the partition's replica
+    int first_run = 0;  // first partition with iterations (a duplicated loop's reference replica)
+    while (first_run < K - 1 && plan[first_run].iters.empty()) ++first_run;
+    auto write_span = [&](int i, const PartPlan &pp) {
+        return ((args[i].mode & JACC_FILTERED) && arr[i]->whole && !pp.iters.empty()) ? Range{0, arr[i]->E}
+                                                                                        : pp.rng[i];
+    };
     ++c->tick;
     for (int p = 0; p < K; ++p) c->st[stream_for(p)].last_use = c->tick;
     for (int i = 0; i < nargs; ++i)
@@ -990,7 +1046,7 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     // mirrors: a stencil partition also writes the rows of its output that
     // other slabs hold as halo (at most one neighbour block on each side)
     const bool can_mirror =
-        !c->lazy && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) && !P->whole && K > 1;
+        !c->lazy && !c->eager && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) && !P->whole && K > 1;
     const int red_slot = slot >= 0 ? slot : kSlots - 1;  // a synchronous-only reduction uses the last slot
     std::vector<int> order;       // partitions that reduce, in partition order
     std::vector<int> red_streams;  // their streams
@@ -1080,6 +1136,10 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             LP.own_lo = pp.rng[primary].lo;
             LP.own_hi = pp.rng[primary].hi;
         }
+        if (kind == JACC_LOOP_PRED_CHAIN) {
+            LP.own2_lo = pp.rng[1].lo;
+            LP.own2_hi = pp.rng[1].hi;
+        }
         LP.mir.n = (int)mirrors.size();
         for (size_t k = 0; k < mirrors.size(); ++k) {
             const Slab &sq = P->slabs[mirrors[k].first];
@@ -1097,12 +1157,17 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             if (t.ntiles > 0) c->ptasks.push_back(t);
             for (int i = 0; i < nargs; ++i) {
                 if (args[i].mode & JACC_READ) c->paccs.push_back({arr[i], p, pp.rng[i], false});
-                if (args[i].mode & JACC_WRITE) c->paccs.push_back({arr[i], p, pp.rng[i], true});
+                if (args[i].mode & JACC_WRITE) c->paccs.push_back({arr[i], p, write_span(i, pp), true});
                 c->parrays.push_back(arr[i]);
             }
             for (auto &m : mirrors) c->paccs.push_back({P, m.first, m.second, true});
             for (int i = 0; i < nargs; ++i)
-                if (args[i].mode & JACC_WRITE) note_write(arr[i], p, pp.rng[i]);
+                if (args[i].mode & JACC_WRITE) {
+                    if (dup)
+                        note_everywhere(arr[i], pp.rng[i]);
+                    else
+                        note_write(arr[i], p, pp.rng[i]);
+                }
             note_mirrors();
             continue;
         }
@@ -1112,8 +1177,16 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
                 if (rc) return rc;
             }
             if (args[i].mode & JACC_WRITE) {
-                rc = hazard(c, arr[i], p, pp.rng[i], true, s);
+                const Range span = write_span(i, pp);
+                rc = hazard(c, arr[i], p, pp.rng[i], true, s, (dup && p != first_run) ? 4 : 2);
                 if (rc) return rc;
+                // private writes of a filtered output outside the owner block
+                for (const Range &x : {Range{span.lo, std::min(span.hi, pp.rng[i].lo)},
+                                       Range{std::max(span.lo, pp.rng[i].hi), span.hi}}) {
+                    if (x.empty() || pp.rng[i].empty()) continue;
+                    rc = hazard(c, arr[i], p, x, true, s, 3);
+                    if (rc) return rc;
+                }
             }
         }
         for (auto &m : mirrors) {  // writes into another partition's slab
@@ -1159,8 +1232,32 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             if (rc) return rc;
         }
         for (int i = 0; i < nargs; ++i)
-            if (args[i].mode & JACC_WRITE) note_write(arr[i], p, pp.rng[i]);
+            if (args[i].mode & JACC_WRITE) {
+                if (dup)
+                    note_everywhere(arr[i], pp.rng[i]);
+                else
+                    note_write(arr[i], p, pp.rng[i]);
+            }
         note_mirrors();
+    }
+    // the paper's coherence: every partition sends the rows it wrote to every
+    // other slab that holds them, on its own stream after its kernel
+    if (c->eager && !dup && !persistent) {
+        for (int p = 0; p < K; ++p) {
+            if (plan[p].iters.empty()) continue;
+            for (int i = 0; i < nargs; ++i) {
+                if (!(args[i].mode & JACC_WRITE)) continue;
+                Array *A = arr[i];
+                for (int q = 0; q < K; ++q) {
+                    if (q == p) continue;
+                    const Range x = isect(plan[p].rng[i], A->slabs[q].rows);
+                    if (x.empty()) continue;
+                    rc = issue_copy(c, A, p, q, x, stream_for(p));
+                    if (rc) return rc;
+                    A->valid[q].add(x);
+                }
+            }
+        }
     }
     if (want_red) {
         const int s0 = one_stream ? 0 : base % ns;
@@ -1284,6 +1381,10 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
         g_init_err = "allocator without alloc/free";
         return JACC_ERR_INVALID;
     }
+    if ((flags & JACC_INIT_EAGER) && (flags & JACC_INIT_LAZY)) {
+        g_init_err = "JACC_INIT_EAGER and JACC_INIT_LAZY exclude each other";
+        return JACC_ERR_INVALID;
+    }
     jacc_ctx *c = nullptr;
     try {
         c = new jacc_ctx();
@@ -1295,6 +1396,7 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
         c->lazy = (flags & JACC_INIT_LAZY) != 0;
         c->split = (flags & JACC_INIT_SPLIT) != 0;
         c->no_split = (flags & JACC_INIT_NO_SPLIT) != 0;
+        c->eager = (flags & JACC_INIT_EAGER) != 0;
         if (alloc) {
             c->alloc = *alloc;
             c->use_hipmalloc = false;

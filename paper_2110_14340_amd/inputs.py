@@ -98,3 +98,23 @@ def mlp_init(F, seed, H=64):
 
     return {"W1": he(H, F), "b1": np.zeros(H), "W2": he(H, H), "b2": np.zeros(H),
             "W3": he(H, H), "b3": np.zeros(H), "w4": he(1, H)[0] * 0.5, "b4": np.zeros(1)}
+
+
+def pred_chain_inputs(na, nb, nc, T, seed, skipped=0):
+    """Inputs of the filtering example's statement chain: a (na), b (nb), c
+    (nc) and xs (T) uniform[0,1); idx (T x 3 int32) with i and k 2T distinct
+    indices drawn without replacement from [0, min(na, nb)) (so no element is
+    touched by two iterations) and j uniform over [0, nc).  The first
+    `skipped` iterations get an out-of-range index (i, j or k in turn)."""
+    r = rng(seed)
+    nab = min(na, nb)
+    assert 2 * T <= nab
+    ik = r.permutation(nab)[:2 * T]
+    idx = np.empty((T, 3), dtype=np.int32)
+    idx[:, 0] = ik[:T]
+    idx[:, 1] = r.integers(0, nc, size=T)
+    idx[:, 2] = ik[T:]
+    for t in range(min(skipped, T)):
+        col = t % 3
+        idx[t, col] = (nab if col != 1 else nc) + t if t % 2 == 0 else -1 - t
+    return r.random(na), r.random(nb), r.random(nc), idx, r.random(T)

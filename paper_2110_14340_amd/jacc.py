@@ -22,8 +22,8 @@ COPYIN, CREATE, COPY = 1, 2, 3
 COPYOUT, DELETE = 1, 2
 UPDATE_HOST, UPDATE_DEVICE = 1, 2
 READ, WRITE, READWRITE, FILTERED = 1, 2, 3, 4
-JACOBI2D, HEAT3D, SUM, GEMM, SPMV_CSR, SCATTER_SQ = 1, 2, 3, 4, 5, 6
-INIT_DRYRUN, INIT_TRACE, INIT_SERIALIZE, INIT_LAZY, INIT_SPLIT, INIT_NO_SPLIT = 1, 2, 4, 8, 16, 32
+JACOBI2D, HEAT3D, SUM, GEMM, SPMV_CSR, SCATTER_SQ, PRED_CHAIN = 1, 2, 3, 4, 5, 6, 7
+INIT_DRYRUN, INIT_TRACE, INIT_SERIALIZE, INIT_LAZY, INIT_SPLIT, INIT_NO_SPLIT, INIT_EAGER = 1, 2, 4, 8, 16, 32, 64
 OP_NAMES = {1: "ALLOC", 2: "FREE", 3: "H2D", 4: "D2H", 5: "COPY", 6: "KERNEL", 7: "RECORD", 8: "WAIT",
             9: "SYNC", 10: "COMBINE", 11: "ACCESS", 12: "JOIN"}
 STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOT_PRESENT", -3: "ALREADY_PRESENT", -4: "RANGE", -5: "ALLOC",
@@ -462,6 +462,15 @@ class Context:
         b = bounds((0, y.shape[0]))
         return self.loop(SPMV_CSR, b, [(rp, READ, 0, 1, 0), (col, READ, 0, 0, 1), (val, READ, 0, 0, 1),
                                        (x, READ, 0, 0, 1), (y, WRITE, 0, 0, 0)], cfg=cfg, raw=raw)
+
+    def pred_chain(self, a, b, c, idx, xs, rows=None, raw=False):
+        """The statement chain of the paper's filtering example over
+        iterations `rows` (default all): a and b (entered whole) written
+        FILTERED, c, idx (T x 3 int32) and xs read whole.  Passing the same
+        array as a and b runs the loop duplicated."""
+        bnd = bounds(rows or (0, xs.shape[0]))
+        return self.loop(PRED_CHAIN, bnd, [(a, WRITE | FILTERED, 0, 0, 0), (b, WRITE | FILTERED, 0, 0, 0),
+                                           (c, READ, 0, 0, 1), (idx, READ, 0, 0, 1), (xs, READ, 0, 0, 1)], raw=raw)
 
     def scatter_sq(self, x, idx, out, rows=None, raw=False):
         """out[idx[i]] = x[i]^2 with writes filtered to each partition's rows."""

@@ -74,7 +74,8 @@ def test_jacobi_8192_1000_steps_full_oracle(jacobi_8192, K, flags):
     assert_same(run_jacobi(u0, 1000, K, ctx_flags=flags), ref)
 
 
-@pytest.mark.parametrize("K,flags", [(4, jacc.INIT_LAZY), (4, jacc.INIT_SPLIT), (3, jacc.INIT_LAZY | jacc.INIT_SPLIT)])
+@pytest.mark.parametrize("K,flags", [(4, jacc.INIT_LAZY), (4, jacc.INIT_SPLIT), (3, jacc.INIT_LAZY | jacc.INIT_SPLIT),
+                                     (4, jacc.INIT_EAGER), (3, jacc.INIT_EAGER | jacc.INIT_SPLIT)])
 def test_jacobi_512_100_steps_coherence_modes(K, flags):
     say(f"jacobi 512^2 T=100 K={K} flags={flags}")
     u0 = inputs.jacobi_grid(512, 512, seed=0)

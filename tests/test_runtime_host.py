@@ -14,7 +14,7 @@ import pytest
 from hypothesis import given, settings, strategies as st
 
 from oracle import plan as P
-from paper_2110_14340_amd import jacc
+from paper_2110_14340_amd import inputs, jacc
 from trace_check import freshness_check, race_check
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -313,7 +313,7 @@ def test_injected_device_fault_is_sticky():
     code = r"""
 import numpy as np, sys
 sys.path.insert(0, sys.argv[1])
-from paper_2110_14340_amd import jacc
+from paper_2110_14340_amd import inputs, jacc
 c = jacc.Context(4, flags=jacc.INIT_DRYRUN | jacc.INIT_TRACE | jacc.INIT_LAZY)
 a = np.zeros((32, 8)); b = np.zeros((32, 8))
 c.enter(a, halo=(1, 1)); c.enter(b, halo=(1, 1))
@@ -577,3 +577,95 @@ def test_noalloc_heat_step_refuses_bad_arguments_before_any_device_call():
         rc = L.jacc_heat3d_noalloc(*args, None)
         assert rc == want, (args, rc)
         assert text in L.jacc_last_error(None), L.jacc_last_error(None)
+
+
+# ------------------------------------------------------------------ predicate-filtered chain (Fig. conv-code)
+def _chain_ctx(K, flags=0, alias=False, n=(100, 70, 20, 30)):
+    c = jacc.Context(K, flags=DRY | flags)
+    a, b, cc, idx, xs = inputs.pred_chain_inputs(*n, seed=1)
+    c.enter(a, whole=True)
+    if not alias:
+        c.enter(b, whole=True)
+    for arr in (cc, idx, xs):
+        c.enter(arr, whole=True)
+    return c, a, (a if alias else b), cc, idx, xs
+
+
+def _blocks(E, K):
+    return [(p * E // K, (p + 1) * E // K) for p in range(K)]
+
+
+@pytest.mark.parametrize("K", [1, 3, 4])
+def test_pred_chain_plans_lazy_eager_and_duplicated(K):
+    """Filtered chain on whole replicas: every partition runs every iteration.
+    Lazy coherence moves nothing and gathers each owner block from its owner;
+    the paper's eager coherence sends each owner block of a and b to every
+    other replica (K(K-1) copies per array); an aliased call (a passed as b)
+    runs duplicated and moves nothing, every replica holding the result.  The
+    traces (with a whole-array sum of a afterwards, which pulls the blocks it
+    lacks) are race-free and every read is fresh."""
+    for flags, alias in ((0, False), (jacc.INIT_EAGER, False), (0, True), (jacc.INIT_EAGER, True)):
+        c, a, b, cc, idx, xs = _chain_ctx(K, flags, alias)
+        c.trace_clear()
+        c.pred_chain(a, b, cc, idx, xs)
+        ops = c.trace()
+        kernels = [(t["dst"], t["lo"], t["hi"]) for t in ops if t["op"] == "KERNEL"]
+        assert kernels == [(p, 0, 30) for p in range(K)]
+        copies = sorted((t["array"], t["src"], t["dst"], t["lo"], t["hi"]) for t in ops if t["op"] == "COPY")
+        if flags and not alias:
+            ida, idb = {t["array"] for t in ops if t["op"] == "ACCESS" and t["kind"] in (2, 3)}
+            want = sorted((arr, p, q, lo, hi) for arr, E in ((min(ida, idb), 100), (max(ida, idb), 70))
+                          for p, (lo, hi) in enumerate(_blocks(E, K)) for q in range(K) if q != p)
+            assert copies == want
+        else:
+            assert copies == []
+        c.update(a, jacc.UPDATE_HOST)
+        d2h = [(t["src"], t["lo"], t["hi"]) for t in c.trace() if t["op"] == "D2H"][-K if not alias else -1:]
+        assert d2h == ([(0, 0, 100)] if alias else [(p, lo, hi) for p, (lo, hi) in enumerate(_blocks(100, K))])
+        c.sum(a, sync=True)
+        full = c.trace()
+        assert race_check(full) == [], (flags, alias)
+        assert freshness_check(full) == [], (flags, alias)
+        c.close()
+
+
+def test_pred_chain_and_aliasing_refusals():
+    c = jacc.Context(3, flags=DRY)
+    a, b, cc, idx, xs = inputs.pred_chain_inputs(100, 70, 20, 30, seed=1)
+    c.enter(a)  # partitioned, not replicated
+    c.enter(b, whole=True)
+    for arr in (cc, idx, xs):
+        c.enter(arr, whole=True)
+    st = c.pred_chain(a, b, cc, idx, xs, raw=True)
+    assert st == jacc.ERR_INVALID and "entered whole" in c.last_error()
+    # an in-place sweep of a partitioned grid: aliased, no replicas
+    u = np.zeros((40, 16))
+    c.enter(u, halo=(1, 1))
+    st = c.loop(jacc.JACOBI2D, jacc.bounds((1, 39), (1, 15)), [(u, jacc.READ, -1, 1, 0), (u, jacc.WRITE, 0, 0, 0)],
+                raw=True)
+    assert st == jacc.ERR_RANGE and "aliased" in c.last_error()
+    c.close()
+    assert jacc.lib().jacc_init(ctypes.byref(ctypes.c_void_p()), 2, None, None,
+                                jacc.INIT_DRYRUN | jacc.INIT_EAGER | jacc.INIT_LAZY) == jacc.ERR_INVALID
+
+
+@pytest.mark.parametrize("K", [2, 4])
+def test_eager_coherence_of_stencils_sends_halo_rows(K):
+    """Under the paper's eager coherence a Jacobi sweep sends each partition's
+    boundary rows to the neighbours holding them as halo (two rows per inner
+    boundary, as copies on the writer's stream) instead of mirror stores, and
+    a second sweep reads fresh halos without pulls."""
+    c = jacc.Context(K, flags=DRY | jacc.INIT_EAGER)
+    a = np.zeros((66, 20))
+    b = np.zeros((66, 20))
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    c.trace_clear()
+    c.jacobi2d(a, b)
+    c.jacobi2d(b, a)
+    ops = c.trace()
+    copies = [t for t in ops if t["op"] == "COPY"]
+    assert len(copies) == 2 * 2 * (K - 1)
+    assert all(t["hi"] - t["lo"] == 1 for t in copies)
+    assert race_check(ops) == [] and freshness_check(ops) == []
+    c.close()

@@ -8,7 +8,10 @@
   be ordered, otherwise the trace has a race.
 * freshness_check: replays the trace in issue order with symbolic versions
   and checks that every row a kernel reads holds the latest value written
-  to that row of the array (by any partition or the host).
+  to that row of the array (by any partition or the host).  A private write
+  (a filtered loop's write outside the partition's owner block) leaves a
+  value that is never the latest; a duplicated loop's later partitions write
+  the value its first partition wrote.
 """
 from collections import defaultdict
 
@@ -53,7 +56,7 @@ def race_check(trace, skip_wait=None):
             vc[d] = dict(v)
             op_vc[(d, n)] = dict(v)
             for a in pending.pop((d, n), []):
-                mode = "w" if a["kind"] == 2 else "r"
+                mode = "w" if a["kind"] in (2, 3, 4) else "r"
                 for row in range(a["lo"], a["hi"]):
                     key = (a["array"], a["dst"], row)
                     for (ps, pn, pm) in hist[key]:
@@ -108,6 +111,13 @@ def freshness_check(trace):
                             stale.append(f"kernel s{t['stream']}#{t['seq']} reads array {a['array']} row {row} "
                                          f"in slab {a['dst']}: version {have}, latest {want}")
             written = {}   # one new value per (array, row), whichever slabs receive it
+            for a in acc:
+                if a["kind"] == 3:  # private values: never the array's latest
+                    for row in range(a["lo"], a["hi"]):
+                        stored[(a["array"], a["dst"], row)] = ("private", new_version())
+                elif a["kind"] == 4:  # a duplicated loop: the value its first partition wrote
+                    for row in range(a["lo"], a["hi"]):
+                        stored[(a["array"], a["dst"], row)] = logical.get((a["array"], row))
             for a in acc:
                 if a["kind"] == 2:
                     for row in range(a["lo"], a["hi"]):
