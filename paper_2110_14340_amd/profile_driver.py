@@ -7,6 +7,9 @@ written) that calibrates the HBM byte counters:
   rocprofv3 --pmc FETCH_SIZE -d <dir> -- python3 -m paper_2110_14340_amd.profile_driver jacobi
   rocprofv3 --pmc WRITE_SIZE -d <dir> -- python3 -m paper_2110_14340_amd.profile_driver jacobi
   rocprofv3 --kernel-trace --stats -d <dir> -- python3 -m paper_2110_14340_amd.profile_driver jacobi
+
+Workloads: jacobi (8192^2), heat (512^3 with the residual), sum (512^3),
+gemm (4096^3), spmv (2^22 rows).
 """
 import sys
 
@@ -51,6 +54,13 @@ def main(which="jacobi", launches=20, cfg=None):
             c.enter(C, clause=jacc.CREATE)
             for _ in range(max(1, launches // 4)):
                 c.gemm(A, B, C)
+            c.wait()
+    elif which == "sum":
+        xs = inputs.uniform((512, 512, 512), seed=7)
+        with jacc.Context(1) as c:
+            c.enter(xs)
+            for t in range(launches):
+                c.sum(xs, slot=t, sync=False)
             c.wait()
     elif which == "spmv":
         nr = 1 << 22
