@@ -142,7 +142,18 @@ typedef struct {
  *   tile       rows (2-D) or planes (3-D) each thread marches through;
  *              GEMM: k-slab depth staged through LDS, 16 or 32 (with bx =
  *              256 or 512 threads per 128x128 tile); SPMV_CSR: lanes per
- *              row, 4, 8 or 16 (order 2 = non-temporal col/val loads)
+ *              row, 4, 8 or 16 (order 2 = non-temporal col/val loads), or
+ *              with order 4 (column bands) lanes per row and band, 1 to 16,
+ *              by = bands per XCD (1, 2, 4, 8), rows = rows per lane (2 or 4
+ *              with one lane).  The banded form copies each partition's
+ *              entries once into band-major order on the device (kept until
+ *              row_ptr, col or val change), runs the bands of XCD j on XCD j
+ *              so that its slice of x stays in that XCD's L2, and adds each
+ *              row's band sums in band order: within the SpMV bound of the
+ *              plain order, and the same bits for every partition count.  It
+ *              is the default when x has at least 2^20 elements, except
+ *              inside batches, which capture the plain form (an explicit
+ *              order 4 there returns JACC_ERR_UNSUPPORTED).
  *   vec        1 or 2 consecutive FP64 elements per lane (2 needs an even row
  *              length)
  *   persistent 1 = run the loop inside the batched persistent kernel

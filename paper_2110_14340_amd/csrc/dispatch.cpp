@@ -75,7 +75,16 @@ int check_config(const Launch &L) {
             // k-slab depth and workgroup size; other fields are ignored
             return ((c.tile == 16 || c.tile == 32) && (c.bx == 256 || c.bx == 512)) ? 0 : 1;
         case JACC_LOOP_SPMV_CSR:
-            return ((c.tile == 4 || c.tile == 8 || c.tile == 16) && (c.order == 1 || c.order == 2)) ? 0 : 1;
+            // order 4: column-banded, by = bands per XCD, tile = lanes per
+            // row and band (1 to 16)
+            if (c.order == 4)
+                return ((c.tile == 1 || c.tile == 2 || c.tile == 4 || c.tile == 8 || c.tile == 16) &&
+                        (c.by == 1 || c.by == 2 || c.by == 4 || c.by == 8) &&
+                        (c.rows == 1 || (c.tile == 1 && (c.rows == 2 || c.rows == 4))))
+                           ? 0
+                           : 1;
+            if (c.tile != 4 && c.tile != 8 && c.tile != 16) return 1;
+            return (c.order == 1 || c.order == 2) ? 0 : 1;
         case JACC_LOOP_SUM:
         case JACC_LOOP_SCATTER_SQ:
         case JACC_LOOP_PRED_CHAIN:

@@ -113,6 +113,22 @@ int64_t sum_workgroups(const Launch &L);
 hipError_t launch_finalise(const double *partials, int64_t n, double *out, hipStream_t s);
 hipError_t launch_gemm(const Launch &L, hipStream_t s);
 hipError_t launch_spmv(const Launch &L, hipStream_t s);
+
+// Column-banded SpMV of one partition (rows L.lo[0]..L.hi[0]): device
+// buffers of its band-major copy.  bands = 8*S; bptr holds bands*n + 1
+// offsets, sums band_scan_blocks(bands*n) + 1 scan totals, bcol/bval the
+// partition's entries, part bands*n doubles (also the counts' scratch during
+// the build).
+struct BandBufs {
+    int bands;
+    int64_t ncols;
+    int32_t *bptr, *sums, *bcol;
+    double *bval, *part;
+};
+int64_t band_width(int64_t ncols, int bands);
+int64_t band_scan_blocks(int64_t len);
+hipError_t build_bands(const Launch &L, const BandBufs &bb, hipStream_t s);
+hipError_t launch_spmv_banded(const Launch &L, const BandBufs &bb, hipStream_t s);
 hipError_t launch_scatter(const Launch &L, hipStream_t s);
 hipError_t launch_chain(const Launch &L, hipStream_t s);
 

@@ -36,6 +36,7 @@ constexpr int kSlots = 4096;
 constexpr int kEventRing = 16;
 constexpr int64_t kWgCapacity = 1 << 16;  // workgroup partials per stream
 constexpr int kTaskCapacity = 4096;       // persistent tasks per batch
+constexpr int64_t kBandedMinCols = 1 << 20;  // SpMV x length from which the banded form is the default
 
 thread_local std::string g_init_err;  // message of the last failed context-free call (jacc_init, no-alloc step)
 
@@ -173,6 +174,7 @@ struct Array {
     std::vector<Slab> slabs;
     IntervalMap<int32_t> writer;  // -1: host data, valid in every holder
     std::vector<IntervalSet> valid;
+    uint64_t version = 0;  // bumped by every device write (kernels, copies from the host)
     Range block(int p) const {
         return {(int64_t)((__int128)p * E / K), (int64_t)((__int128)(p + 1) * E / K)};
     }
@@ -240,6 +242,18 @@ struct Batch {
     int groups = 0;
 };
 
+// The column-banded copy of one partition's rows of a CSR matrix, built on
+// the device at its first banded product and kept while row_ptr, col and val
+// are unchanged (their versions).
+struct BandCache {
+    int rp_id = -1, col_id = -1, val_id = -1, p = 0, bands = 0;
+    int64_t lo = 0, hi = 0;
+    uint64_t v_rp = 0, v_col = 0, v_val = 0;
+    bool built = false;
+    jk::BandBufs bb{};
+    void *mem[5] = {};
+};
+
 size_t dtype_size(int dt) {
     switch (dt) {
         case JACC_F64: return 8;
@@ -292,6 +306,8 @@ struct jacc_ctx {
     bool time_parts = false;
     std::vector<hipEvent_t> kev;
     uint64_t kev_used = 0;  // bit p: partition p launched in the timed call
+    // banded SpMV copies, per partition and matrix
+    std::vector<BandCache> bands;
     // cost model attached by jacc_model_load (owned; released at finalize)
     void *model = nullptr;
     void (*model_release)(void *) = nullptr;
@@ -559,6 +575,7 @@ int make_fresh(jacc_ctx *c, Array *A, int p, Range need, int s) {
 
 void note_write(Array *A, int p, Range w) {
     if (w.empty()) return;
+    ++A->version;
     A->writer.assign(w, p);
     for (int q = 0; q < A->K; ++q) {
         if (q == p)
@@ -572,6 +589,7 @@ void note_write(Array *A, int p, Range w) {
 // holder, with no single latest writer.
 void note_everywhere(Array *A, Range w) {
     if (w.empty()) return;
+    ++A->version;
     A->writer.assign(w, -1);
     for (int q = 0; q < A->K; ++q) A->valid[q].add(w);
 }
@@ -617,6 +635,7 @@ int h2d_rows(jacc_ctx *c, Array *A, int p, Range r) {
     int rc = hazard(c, A, p, r, true, s);
     if (rc) return rc;
     const Slab &sl = A->slabs[p];
+    ++A->version;
     if (live(c)) {
         char *dp = (char *)sl.dev + (size_t)(r.lo - sl.rows.lo) * A->row_bytes;
         const char *hp = (const char *)A->host + (size_t)r.lo * A->row_bytes;
@@ -661,7 +680,20 @@ int gather(jacc_ctx *c, Array *A, Range r) {
     return JACC_OK;
 }
 
+void drop_bands(jacc_ctx *c, int array_id) {
+    for (size_t i = 0; i < c->bands.size();) {
+        BandCache &bc = c->bands[i];
+        if (array_id < 0 || bc.rp_id == array_id || bc.col_id == array_id || bc.val_id == array_id) {
+            for (void *m : bc.mem) dev_free(c, m);
+            c->bands.erase(c->bands.begin() + (long)i);
+        } else {
+            ++i;
+        }
+    }
+}
+
 void free_array(jacc_ctx *c, Array *A) {
+    drop_bands(c, A->id);
     for (int p = 0; p < A->K; ++p) {
         trace(c, JACC_OP_FREE, -1, A->id, -1, p, 0, A->slabs[p].rows.lo, A->slabs[p].rows.hi, 0);
         dev_free(c, A->slabs[p].dev);
@@ -947,11 +979,20 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
     for (const PartPlan &pp : plan) L.part_rows = std::max(L.part_rows, pp.iters.hi - pp.iters.lo);
     if (cfg) cf = {cfg->bx, cfg->by, cfg->tile, cfg->vec, cfg->persistent, cfg->order, cfg->march, cfg->rows};
     L.cfg = jk::default_config(kind, L, cf);
+    if (kind == JACC_LOOP_SPMV_CSR && !cf.order && !c->cur && arr[3]->E >= kBandedMinCols) {
+        // x far larger than an XCD's L2: the column-banded form, one band
+        // per XCD, two lanes per row and band (measured at 2^22 columns)
+        L.cfg.order = 4;
+        if (!cf.tile) L.cfg.tile = 2;
+        if (!cf.by) L.cfg.by = 1;
+    }
     if (jk::check_config(L) != 0)
         return set_err(c, JACC_ERR_INVALID,
                        "configuration bx=%d by=%d tile=%d vec=%d persistent=%d order=%d march=%d rows=%d not valid for kind %d",
                        L.cfg.bx, L.cfg.by, L.cfg.tile, L.cfg.vec, L.cfg.persistent, L.cfg.order, L.cfg.march,
                        L.cfg.rows, kind);
+    if (kind == JACC_LOOP_SPMV_CSR && L.cfg.order == 4 && c->cur)
+        return set_err(c, JACC_ERR_UNSUPPORTED, "the column-banded SpMV form is not captured in batches");
     if (L.cfg.persistent) {
         if (!c->cur) return set_err(c, JACC_ERR_INVALID, "persistent execution needs an open batch");
         if (want_red) return set_err(c, JACC_ERR_UNSUPPORTED, "persistent execution of a reduction");
@@ -959,6 +1000,58 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
             return set_err(c, JACC_ERR_UNSUPPORTED, "persistent execution of a filtered loop");
     }
     *primary_out = primary;
+    return JACC_OK;
+}
+
+// The banded copy of partition p's rows of the CSR matrix in arr[0..2]
+// (row_ptr, col, val) for x = arr[3]: found, marked for a rebuild when the
+// matrix changed since it was built, or allocated.
+int band_cache(jacc_ctx *c, Array **arr, int p, Range rows, int bands, BandCache **out) {
+    Array *rp = arr[0], *col = arr[1], *val = arr[2];
+    for (BandCache &bc : c->bands)
+        if (bc.rp_id == rp->id && bc.col_id == col->id && bc.val_id == val->id && bc.p == p && bc.lo == rows.lo &&
+            bc.hi == rows.hi && bc.bands == bands) {
+            if (bc.v_rp != rp->version || bc.v_col != col->version || bc.v_val != val->version) {
+                bc.built = false;
+                bc.v_rp = rp->version;
+                bc.v_col = col->version;
+                bc.v_val = val->version;
+            }
+            *out = &bc;
+            return JACC_OK;
+        }
+    const int64_t n = rows.hi - rows.lo, len = (int64_t)bands * n;
+    const int64_t nb = jk::band_scan_blocks(len);
+    if (nb > 8192) return set_err(c, JACC_ERR_UNSUPPORTED, "banded SpMV: %lld band rows exceed the scan", (long long)len);
+    BandCache bc;
+    bc.rp_id = rp->id;
+    bc.col_id = col->id;
+    bc.val_id = val->id;
+    bc.p = p;
+    bc.bands = bands;
+    bc.lo = rows.lo;
+    bc.hi = rows.hi;
+    bc.v_rp = rp->version;
+    bc.v_col = col->version;
+    bc.v_val = val->version;
+    const size_t sizes[5] = {(size_t)(len + 1) * 4, (size_t)(nb + 1) * 4, (size_t)col->E * 4, (size_t)col->E * 8,
+                             (size_t)len * 8};
+    for (int i = 0; i < 5; ++i) {
+        int rc = dev_alloc(c, sizes[i], &bc.mem[i]);
+        if (rc) {
+            for (int j = 0; j < i; ++j) dev_free(c, bc.mem[j]);
+            return rc;
+        }
+    }
+    bc.bb.bands = bands;
+    bc.bb.ncols = arr[3]->E;
+    bc.bb.bptr = (int32_t *)bc.mem[0];
+    bc.bb.sums = (int32_t *)bc.mem[1];
+    bc.bb.bcol = (int32_t *)bc.mem[2];
+    bc.bb.bval = (double *)bc.mem[3];
+    bc.bb.part = (double *)bc.mem[4];
+    c->bands.push_back(bc);
+    *out = &c->bands.back();
     return JACC_OK;
 }
 
@@ -1217,7 +1310,18 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
         }
         const bool timed = c->time_parts && live(c) && p < kMaxK;
         if (timed) HIPCHK(c, hipEventRecord(c->kev[2 * p], c->st[s].s), "hipEventRecord");
-        if (live(c)) HIPCHK(c, jk::launch_loop(LP, c->st[s].s), "kernel launch");
+        if (kind == JACC_LOOP_SPMV_CSR && LP.cfg.order == 4) {  // column-banded product
+            BandCache *bc = nullptr;
+            rc = band_cache(c, arr, p, pp.iters, 8 * LP.cfg.by, &bc);
+            if (rc) return rc;
+            if (live(c)) {
+                if (!bc->built) HIPCHK(c, jk::build_bands(LP, bc->bb, c->st[s].s), "banded SpMV build");
+                HIPCHK(c, jk::launch_spmv_banded(LP, bc->bb, c->st[s].s), "kernel launch");
+            }
+            bc->built = true;
+        } else if (live(c)) {
+            HIPCHK(c, jk::launch_loop(LP, c->st[s].s), "kernel launch");
+        }
         if (timed) {
             HIPCHK(c, hipEventRecord(c->kev[2 * p + 1], c->st[s].s), "hipEventRecord");
             c->kev_used |= (uint64_t)1 << p;

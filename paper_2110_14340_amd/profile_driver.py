@@ -73,7 +73,7 @@ def main(which="jacobi", launches=20, cfg=None):
             c.enter(xv, whole=True)
             c.enter(yv, clause=jacc.CREATE)
             for _ in range(launches):
-                c.spmv(rp, col, val, xv, yv)
+                c.spmv(rp, col, val, xv, yv, cfg=cfg)
             c.wait()
     for _ in range(3):  # the calibration copies, last
         y.copy_(x)

@@ -133,8 +133,10 @@ def test_spmv_small(n, K):
     xi = inputs.int_valued(n, seed=10, lo=-10, hi=10)
     ref_i = oracle.spmv_csr(rpi, coli, vali, xi)
     assert np.array_equal(_spmv_dev(rpi, coli, vali, xi, K), ref_i)
-    for lanes, order in ((4, 1), (16, 1), (8, 2), (4, 2)):  # lanes per row; non-temporal col/val loads
-        cfg = jacc.config(tile=lanes, order=order)
+    # lanes per row; order 2: non-temporal col/val loads; order 4: column bands (by per XCD)
+    for lanes, order, by, rows in ((4, 1, 0, 0), (16, 1, 0, 0), (8, 2, 0, 0), (4, 2, 0, 0), (16, 4, 1, 0), (8, 4, 2, 0),
+                                   (4, 4, 8, 0), (1, 4, 1, 0), (2, 4, 2, 0), (1, 4, 1, 2), (1, 4, 2, 4)):
+        cfg = jacc.config(tile=lanes, order=order, by=by, rows=rows)
         assert np.all(np.abs(_spmv_dev(rp, col, val, x, K, cfg) - ref) <= 1e-13 * _row_bound(rp, col, val, x))
         assert np.array_equal(_spmv_dev(rpi, coli, vali, xi, K, cfg), ref_i)
 
@@ -147,9 +149,35 @@ def test_spmv_rows_longer_than_the_lane_group(n, K, draws):
     rp, col, val, x = inputs.csr_matrix(n, n, draws, seed=11)
     ref = oracle.spmv_csr(rp, col, val, x)
     bound = 1e-13 * _row_bound(rp, col, val, x)
-    for lanes, order in ((4, 2), (8, 1), (16, 2)):
-        y = _spmv_dev(rp, col, val, x, K, jacc.config(tile=lanes, order=order))
+    for lanes, order, by, rows in ((4, 2, 0, 0), (8, 1, 0, 0), (16, 2, 0, 0), (16, 4, 1, 0), (8, 4, 4, 0), (1, 4, 1, 0),
+                                   (2, 4, 2, 0), (1, 4, 1, 4), (1, 4, 2, 2)):
+        y = _spmv_dev(rp, col, val, x, K, jacc.config(tile=lanes, order=order, by=by, rows=rows))
         assert np.all(np.abs(y - ref) <= bound)
+
+
+def test_banded_spmv_rebuilds_after_the_matrix_changes():
+    """The banded copy is built at the first product and reused; new values
+    (update to the device) and a new row_ptr/col (re-entered arrays) give
+    products of the new matrix."""
+    say("banded spmv reuse and rebuild")
+    n = 30000
+    rp, col, val, x = inputs.csr_matrix(n, n, 16, seed=12)
+    cfg = jacc.config(tile=16, order=4, by=2)
+    y = np.zeros(n)
+    with context(3) as c:
+        for arr in (col, val, x):
+            c.enter(arr, whole=True)
+        c.enter(rp, halo=(1, 1))
+        c.enter(y, clause=jacc.CREATE)
+        for step in range(3):
+            if step == 2:
+                val[:] = -2.0 * val
+                c.update(val, jacc.UPDATE_DEVICE)
+            c.spmv(rp, col, val, x, y, cfg=cfg)
+            c.update(y, jacc.UPDATE_HOST)
+            ref = oracle.spmv_csr(rp, col, val, x)
+            assert np.all(np.abs(y - ref) <= 1e-13 * _row_bound(rp, col, val, x)), step
+        c.exit(y)
 
 
 def test_spmv_2_22_rows_k1_k4_every_row():
@@ -163,6 +191,13 @@ def test_spmv_2_22_rows_k1_k4_every_row():
     assert np.array_equal(y1, y4)  # each row's sum order is fixed by the lanes-per-row layout
     bad = np.flatnonzero(np.abs(y4 - ref) > bound)
     assert bad.size == 0, f"{bad.size} rows outside the bound, first {bad[:5]}"
+    for by in (1, 2):
+        say(f"  column-banded form, {8 * by} bands, K=1 and 4")
+        cfg = jacc.config(tile=16, order=4, by=by)
+        b1 = _spmv_dev(rp, col, val, x, 1, cfg)
+        assert np.array_equal(_spmv_dev(rp, col, val, x, 4, cfg), b1)  # band boundaries do not depend on K
+        bad = np.flatnonzero(np.abs(b1 - ref) > bound)
+        assert bad.size == 0, f"{bad.size} banded rows outside the bound, first {bad[:5]}"
 
 
 # ------------------------------------------------------------------ predicate-filtered scatter
