@@ -87,17 +87,17 @@ def run_jacobi(ctx_mod, torch, u0, K, steps, warmup, cfg=None, flags=0):
     return t1 - t0, ev_s
 
 
-def run_jacobi_graph(jacc, torch, u0, K, steps, warmup, tile=8, per_graph=2):
+def run_jacobi_graph(jacc, torch, u0, K, steps, warmup, per_graph=2, persistent=True):
     """The same partitioned sweeps captured once as a graph of `per_graph`
-    steps (the K partitions of a step are tasks of one persistent launch,
-    halo rows written through by the producing tiles) and replayed
-    steps/per_graph times."""
+    steps and replayed steps/per_graph times: the K partitions of a step as
+    tasks of one persistent launch (halo rows written through by the
+    producing tiles), or (persistent=False) as K launches in sequence."""
     a = u0.copy()
     b = u0.copy()
     c = jacc.Context(K)
     c.enter(a, halo=(1, 1))
     c.enter(b, halo=(1, 1))
-    cfg = jacc.config(tile=tile, vec=2, persistent=1)
+    cfg = jacc.config(vec=2, persistent=1) if persistent else None
     c.batch_begin()
     for t in range(per_graph):
         (c.jacobi2d(a, b, cfg=cfg) if t % 2 == 0 else c.jacobi2d(b, a, cfg=cfg))
@@ -308,14 +308,15 @@ def main():
             wall, _ = run_jacobi(jacc, torch, u0, K, args.steps, args.warmup, flags=fl)
             modes.setdefault(name, {})[str(K)] = {"ms_per_step": round(wall / args.steps * 1e3, 5),
                                                   "gbps": round(step_bytes * args.steps / wall / 1e9, 1)}
-    graph = {}
+    graph, graph_plain = {}, {}
     for K in ks:
-        if K == 1:
-            continue
         log(f"jacobi K={K} as a replayed graph")
         wall = run_jacobi_graph(jacc, torch, u0, K, args.steps, args.warmup)
         graph[K] = {"ms_per_step": round(wall / args.steps * 1e3, 5),
                     "gbps": round(step_bytes * args.steps / wall / 1e9, 1)}
+        wall = run_jacobi_graph(jacc, torch, u0, K, args.steps, args.warmup, persistent=False)
+        graph_plain[K] = {"ms_per_step": round(wall / args.steps * 1e3, 5),
+                          "gbps": round(step_bytes * args.steps / wall / 1e9, 1)}
     main_k = max(ks)
     wall_main = per_k[main_k]["ms_per_step"] / 1e3 * args.steps
     value = step_bytes * args.steps / wall_main / 1e9
@@ -338,6 +339,7 @@ def main():
         "frac_hbm_peak": round(value / HBM_PEAK_GBS, 4),
         "per_k": {str(k): v for k, v in per_k.items()},
         "per_k_graph": {str(k): v for k, v in graph.items()},
+        "per_k_graph_plain_launches": {str(k): v for k, v in graph_plain.items()},
         "per_k_modes": modes,
     }
     if 1 in per_k and main_k != 1:

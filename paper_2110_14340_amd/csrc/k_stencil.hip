@@ -451,6 +451,34 @@ heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t n
 // Jacobi tasks only; without the heat bodies the kernel needs fewer
 // registers, so more workgroups are resident at once.
 // ---------------------------------------------------------------------------
+// One tile (local index `local`) of task T.
+template <bool JONLY>
+__device__ __forceinline__ void persistent_tile(const PTask &T, int64_t local) {
+    const int64_t bxi = local % T.gx;
+    const int64_t rest = local / T.gx;
+    if (JONLY || T.kind == JACC_LOOP_JACOBI2D) {
+        if (T.vec == 2)
+            jacobi_tile<2>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, T.mir, bxi,
+                           rest, threadIdx.x, 0, kPersistentThreads, 1);
+        else
+            jacobi_tile<1>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, T.mir, bxi,
+                           rest, threadIdx.x, 0, kPersistentThreads, 1);
+    } else if constexpr (!JONLY) {
+        const int64_t byi = rest % T.gy, bzi = rest / T.gy;
+        if (T.vec == 2)
+            (void)heat_tile<2, false>(T.in, T.out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2], T.hi[2],
+                                      T.col0, T.tile, T.march, T.alpha, T.mir, bxi, byi, bzi, threadIdx.x, 0,
+                                      kPersistentThreads, 1);
+        else
+            (void)heat_tile<1, false>(T.in, T.out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2], T.hi[2],
+                                      T.col0, T.tile, T.march, T.alpha, T.mir, bxi, byi, bzi, threadIdx.x, 0,
+                                      kPersistentThreads, 1);
+    }
+}
+
+// Workgroup b runs tile b of the concatenated tile list of all tasks (the
+// task found by a binary search over the tasks' first tiles); with fewer
+// workgroups than tiles it would take tiles b, b + grid, ... .
 template <bool JONLY>
 __global__ void __launch_bounds__(kPersistentThreads)
 persistent_kernel(const PTask *__restrict__ tasks, int ntasks, int64_t total) {
@@ -463,28 +491,7 @@ persistent_kernel(const PTask *__restrict__ tasks, int ntasks, int64_t total) {
             else
                 hi = mid - 1;
         }
-        const PTask &T = tasks[lo];
-        const int64_t local = t - T.tile_begin;
-        const int64_t bxi = local % T.gx;
-        const int64_t rest = local / T.gx;
-        if (JONLY || T.kind == JACC_LOOP_JACOBI2D) {
-            if (T.vec == 2)
-                jacobi_tile<2>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, T.mir, bxi,
-                               rest, threadIdx.x, 0, kPersistentThreads, 1);
-            else
-                jacobi_tile<1>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, T.mir, bxi,
-                               rest, threadIdx.x, 0, kPersistentThreads, 1);
-        } else if constexpr (!JONLY) {
-            const int64_t byi = rest % T.gy, bzi = rest / T.gy;
-            if (T.vec == 2)
-                (void)heat_tile<2, false>(T.in, T.out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2],
-                                          T.hi[2], T.col0, T.tile, T.march, T.alpha, T.mir, bxi, byi, bzi, threadIdx.x, 0,
-                                          kPersistentThreads, 1);
-            else
-                (void)heat_tile<1, false>(T.in, T.out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2],
-                                          T.hi[2], T.col0, T.tile, T.march, T.alpha, T.mir, bxi, byi, bzi, threadIdx.x, 0,
-                                          kPersistentThreads, 1);
-        }
+        persistent_tile<JONLY>(tasks[lo], t - tasks[lo].tile_begin);
     }
 }
 
@@ -623,29 +630,17 @@ bool make_task(const Launch &L, PTask *t) {
 // current device (occupancy x compute units): a larger grid would leave a
 // second, partial generation of workgroups running after the first, with
 // part of the chip idle.  Queried once per device and kernel variant.
-template <bool JONLY>
-static int64_t persistent_grid_cap() {
-    static int64_t cap[64] = {};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
-    if (!cap[dev]) {
-        int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<JONLY>, kPersistentThreads, 0) !=
-                hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu <= 0 ||
-            cus <= 0) {
-            (void)hipGetLastError();
-            return 1024;
-        }
-        cap[dev] = (int64_t)per_cu * cus;
-    }
-    return cap[dev];
+// One workgroup per tile (measured: 2.5-5 % faster on 8192^2 steps than a
+// resident-sized grid walking static rounds of tiles), up to the largest
+// one-dimensional grid.
+int64_t persistent_grid(int64_t tiles, bool /*jacobi_only*/) {
+    const int64_t max_grid = (int64_t)INT32_MAX;
+    return tiles < max_grid ? tiles : max_grid;
 }
 
-hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, bool jacobi_only, hipStream_t s) {
-    if (ntasks <= 0 || tiles <= 0) return hipSuccess;
-    const int64_t cap = jacobi_only ? persistent_grid_cap<true>() : persistent_grid_cap<false>();
-    const int64_t grid = tiles < cap ? tiles : cap;
+hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, int64_t grid, bool jacobi_only,
+                             hipStream_t s) {
+    if (ntasks <= 0 || tiles <= 0 || grid <= 0) return hipSuccess;
     if (jacobi_only)
         hipLaunchKernelGGL(persistent_kernel<true>, dim3((unsigned)grid), dim3(kPersistentThreads), 0, s, tasks, ntasks,
                            tiles);

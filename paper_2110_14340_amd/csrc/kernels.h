@@ -95,10 +95,14 @@ constexpr int kPersistentThreads = 256;
 // the persistent kernel).
 bool make_task(const Launch &L, PTask *t);
 
-// Launches the persistent kernel over `ntasks` device task records whose
-// tiles total `tiles` (jacobi_only: every task is a Jacobi sweep, which
-// selects the variant without the heat bodies).
-hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, bool jacobi_only, hipStream_t s);
+// Workgroups of a persistent launch over `tiles` tiles (one per tile).
+int64_t persistent_grid(int64_t tiles, bool jacobi_only);
+
+// Launches the persistent kernel with `grid` workgroups over `ntasks` device
+// task records whose tiles total `tiles` (jacobi_only: every task is a
+// Jacobi sweep, which selects the variant without the heat bodies).
+hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, int64_t grid, bool jacobi_only,
+                             hipStream_t s);
 
 // Number of workgroups the loop's reduction writes partials for (for
 // sizing; <= wg_capacity is required).

@@ -733,10 +733,11 @@ int flush_group(jacc_ctx *c) {
         jacobi_only = jacobi_only && t.kind == JACC_LOOP_JACOBI2D;
     }
     if (live(c)) {
+        const int64_t grid = jk::persistent_grid(tiles, jacobi_only);
         // the table is written to pinned memory now and uploaded once when
         // the batch closes, before the graph first runs
         std::memcpy(B->host_tasks + B->tasks_used, c->ptasks.data(), (size_t)n * sizeof(jk::PTask));
-        HIPCHK(c, jk::launch_persistent(B->dev_tasks + B->tasks_used, n, tiles, jacobi_only, c->st[s].s),
+        HIPCHK(c, jk::launch_persistent(B->dev_tasks + B->tasks_used, n, tiles, grid, jacobi_only, c->st[s].s),
                "persistent kernel launch");
     }
     B->tasks_used += n;
