@@ -246,9 +246,13 @@ enum {
                                       waits on another stream; default for 2 to 4 partitions,
                                       this flag asks for it at any partition count */
     JACC_INIT_NO_SPLIT = 1u << 5,  /* never split (one launch per partition) */
-    JACC_INIT_EAGER = 1u << 6      /* the paper's coherence: after every loop each partition
+    JACC_INIT_EAGER = 1u << 6,     /* the paper's coherence: after every loop each partition
                                       sends the rows it wrote to every other slab holding them
                                       (device copies on its stream); no mirror stores, no pulls */
+    JACC_INIT_FORK_CAPTURE = 1u << 7 /* with JACC_INIT_DRYRUN only: plan batches with every
+                                      partition on its own stream, forked from and joined
+                                      into stream 0 around the capture (otherwise
+                                      JACC_ERR_UNSUPPORTED: graphs are captured on one stream) */
 };
 
 /* Create a context with K partitions (1 <= K <= 64).  streams: K hipStream_t

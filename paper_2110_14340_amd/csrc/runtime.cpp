@@ -274,6 +274,7 @@ struct jacc_ctx {
     bool split = false;      // stencil partitions: own-block rows first, edge rows after (any K)
     bool no_split = false;   // never split (default: split at K <= 4)
     bool eager = false;      // broadcast written rows to every holder after each loop
+    bool fork_capture = false;  // plan batches with every partition on its own stream (dry run only)
     bool plan_only = false;  // planning pass without device work (batch replay check)
     jacc_allocator alloc{};
     bool use_hipmalloc = true;
@@ -1123,7 +1124,7 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     // inside a batch everything is captured on stream 0 (a single-stream
     // graph); the partitions of a stencil step become tiles of one
     // persistent launch when the configuration asks for it
-    const bool one_stream = c->serialize || c->cur != nullptr;
+    const bool one_stream = c->serialize || (c->cur != nullptr && !c->fork_capture);
     auto stream_for = [&](int p) { return (one_stream || persistent) ? 0 : (base + p) % ns; };
     // rows of its slab a partition may write: a filtered output entered
     // whole takes private writes anywhere in the partition's replica
@@ -1486,6 +1487,10 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
         g_init_err = "allocator without alloc/free";
         return JACC_ERR_INVALID;
     }
+    if ((flags & JACC_INIT_FORK_CAPTURE) && !(flags & JACC_INIT_DRYRUN)) {
+        g_init_err = "JACC_INIT_FORK_CAPTURE plans batches only (dry run): captured graphs run on one stream";
+        return JACC_ERR_UNSUPPORTED;
+    }
     if ((flags & JACC_INIT_EAGER) && (flags & JACC_INIT_LAZY)) {
         g_init_err = "JACC_INIT_EAGER and JACC_INIT_LAZY exclude each other";
         return JACC_ERR_INVALID;
@@ -1502,6 +1507,7 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
         c->split = (flags & JACC_INIT_SPLIT) != 0;
         c->no_split = (flags & JACC_INIT_NO_SPLIT) != 0;
         c->eager = (flags & JACC_INIT_EAGER) != 0;
+        c->fork_capture = (flags & JACC_INIT_FORK_CAPTURE) != 0;
         if (alloc) {
             c->alloc = *alloc;
             c->use_hipmalloc = false;

@@ -669,3 +669,71 @@ def test_eager_coherence_of_stencils_sends_halo_rows(K):
     assert all(t["hi"] - t["lo"] == 1 for t in copies)
     assert race_check(ops) == [] and freshness_check(ops) == []
     c.close()
+
+
+# ------------------------------------------------------------------ multi-stream capture planning (dry run)
+def _fork_ctx(K):
+    return jacc.Context(K, flags=DRY | jacc.INIT_FORK_CAPTURE)
+
+
+def test_fork_capture_is_refused_on_a_live_context():
+    st = jacc.lib().jacc_init(ctypes.byref(ctypes.c_void_p()), 2, None, None, jacc.INIT_FORK_CAPTURE)
+    assert st == jacc.ERR_UNSUPPORTED
+    assert b"one stream" in jacc.lib().jacc_last_error(None)
+
+
+@pytest.mark.parametrize("K", [2, 4, 8])
+def test_batch_with_partitions_on_their_own_streams_plans_soundly(K):
+    """The batch sequence under which a multi-stream captured graph once
+    crashed the host in jacc_batch_end (two eager sweeps, two captured
+    sweeps, replays with eager sweeps between them), planned with every
+    partition on its own stream inside the capture: every wait finds an
+    event covering the op it waits for (no internal error), the captured
+    kernels use every stream, the graph is replay-safe, and the whole trace
+    is race-free with every read fresh."""
+    c = _fork_ctx(K)
+    a = np.zeros((130, 98))
+    b = np.zeros((130, 98))
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    c.jacobi2d(a, b)
+    c.jacobi2d(b, a)
+    c.trace_clear()
+    c.batch_begin()
+    c.jacobi2d(a, b)
+    c.jacobi2d(b, a)
+    g = c.batch_end()
+    captured = c.trace()
+    assert c.batch_info(g)["replay_safe"]
+    assert {t["stream"] for t in captured if t["op"] == "KERNEL"} == set(range(K))
+    for r in range(4):
+        c.batch_launch(g, 1 + r)
+        c.update(a, jacc.UPDATE_HOST)
+        if r % 2 == 0:
+            c.jacobi2d(a, b)
+            c.jacobi2d(b, a)
+    full = c.trace()
+    assert race_check(full) == []
+    assert freshness_check(full) == []
+    c.close()
+
+
+def test_heat_batch_with_residual_slots_on_their_own_streams():
+    c = _fork_ctx(3)
+    u = np.zeros((30, 20, 36))
+    v = np.zeros((30, 20, 36))
+    c.enter(u, halo=(1, 1))
+    c.enter(v, halo=(1, 1))
+    c.heat3d(u, v, 0.1, slot=10)
+    c.heat3d(v, u, 0.1, slot=11)
+    c.trace_clear()
+    c.batch_begin()
+    for t in range(4):
+        (c.heat3d(u, v, 0.1, slot=t) if t % 2 == 0 else c.heat3d(v, u, 0.1, slot=t))
+    g = c.batch_end()
+    assert c.batch_info(g)["replay_safe"]
+    c.batch_launch(g, 3)
+    c.reductions(0, 4)
+    full = c.trace()
+    assert race_check(full) == [] and freshness_check(full) == []
+    c.close()
