@@ -46,12 +46,19 @@ struct Range {
 };
 inline Range isect(Range a, Range b) { return {std::max(a.lo, b.lo), std::min(a.hi, b.hi)}; }
 
-// Sorted set of disjoint half-open intervals.
+// Sorted set of disjoint half-open intervals.  Updates build the new list in
+// a buffer kept per thread and swap it in, so steady-state planning does not
+// allocate.
 struct IntervalSet {
     std::vector<Range> v;
+    static std::vector<Range> &scratch() {
+        static thread_local std::vector<Range> buf;
+        buf.clear();
+        return buf;
+    }
     void add(Range r) {
         if (r.empty()) return;
-        std::vector<Range> out;
+        std::vector<Range> &out = scratch();
         bool placed = false;
         for (const Range &x : v) {
             if (x.hi < r.lo) {
@@ -71,7 +78,7 @@ struct IntervalSet {
     }
     void sub(Range r) {
         if (r.empty()) return;
-        std::vector<Range> out;
+        std::vector<Range> &out = scratch();
         for (const Range &x : v) {
             if (x.hi <= r.lo || r.hi <= x.lo) {
                 out.push_back(x);
@@ -132,15 +139,45 @@ struct IntervalMap {
         for_range(r, [&](Piece &p) { p.val = val; });
         coalesce();
     }
-    void coalesce() {
-        std::vector<Piece> out;
-        for (const Piece &p : v) {
-            if (!out.empty() && out.back().hi == p.lo && out.back().val == p.val)
-                out.back().hi = p.hi;
-            else
-                out.push_back(p);
+    void coalesce() {  // merges equal neighbours in place
+        size_t w = 0;
+        for (size_t i = 0; i < v.size(); ++i) {
+            if (w > 0 && v[w - 1].hi == v[i].lo && v[w - 1].val == v[i].val) {
+                v[w - 1].hi = v[i].hi;
+            } else {
+                if (w != i) v[w] = std::move(v[i]);
+                ++w;
+            }
         }
-        v.swap(out);
+        v.resize(w);
+    }
+};
+
+// A short list kept inline (no heap allocation up to N elements).
+template <class T, int N>
+struct SmallVec {
+    T inl[N];
+    int n = 0;
+    std::vector<T> spill;  // elements N, N+1, ...
+    int size() const { return n; }
+    T &operator[](int i) { return i < N ? inl[i] : spill[(size_t)(i - N)]; }
+    const T &operator[](int i) const { return i < N ? inl[i] : spill[(size_t)(i - N)]; }
+    void push_back(const T &x) {
+        if (n < N)
+            inl[n] = x;
+        else
+            spill.push_back(x);
+        ++n;
+    }
+    void clear() {
+        n = 0;
+        spill.clear();
+    }
+    bool operator==(const SmallVec &o) const {
+        if (n != o.n) return false;
+        for (int i = 0; i < n; ++i)
+            if ((*this)[i] != o[i]) return false;
+        return true;
     }
 };
 
@@ -149,7 +186,7 @@ struct IntervalMap {
 struct Access {
     int32_t ws = -1;
     int64_t wseq = 0;
-    std::vector<std::pair<int32_t, int64_t>> reads;
+    SmallVec<std::pair<int32_t, int64_t>, 4> reads;
     bool operator==(const Access &o) const { return ws == o.ws && wseq == o.wseq && reads == o.reads; }
 };
 
@@ -480,12 +517,15 @@ int fork_from0(jacc_ctx *c) {
 int hazard(jacc_ctx *c, Array *A, int p, Range r, bool write, int s, int wkind = 2) {
     if (r.empty()) return JACC_OK;
     Slab &sl = A->slabs[p];
-    std::vector<std::pair<int, int64_t>> need;
+    static thread_local std::vector<std::pair<int, int64_t>> need;  // (stream, op) to wait for
+    need.clear();
     sl.acc.for_range(r, [&](IntervalMap<Access>::Piece &pc) {
         if (pc.val.ws >= 0 && pc.val.ws != s) need.push_back({pc.val.ws, pc.val.wseq});
         if (write)
-            for (auto &rd : pc.val.reads)
+            for (int k = 0; k < pc.val.reads.size(); ++k) {
+                const auto &rd = pc.val.reads[k];
                 if (rd.first != s) need.push_back({rd.first, rd.second});
+            }
     });
     for (auto &w : need) {
         int rc = ensure_wait(c, s, w.first, w.second);
@@ -501,11 +541,13 @@ int hazard(jacc_ctx *c, Array *A, int p, Range r, bool write, int s, int wkind =
             // recorded even when s is the last writer: a later write from
             // another stream (a mirror store) must still wait for this read
             bool found = false;
-            for (auto &rd : pc.val.reads)
+            for (int k = 0; k < pc.val.reads.size(); ++k) {
+                auto &rd = pc.val.reads[k];
                 if (rd.first == s) {
                     rd.second = next;
                     found = true;
                 }
+            }
             if (!found) pc.val.reads.push_back({s, next});
         }
     });

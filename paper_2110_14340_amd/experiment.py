@@ -197,7 +197,9 @@ def independent_loops(n_loops=96, streams=(1, 4, 16), steps=2, seed=11, reps=5, 
     independent loops, the least recently used stream, and orders dependent
     loops by events (automated asynchronous execution of independent loop
     nests).  The same loop sequence captured as one graph is timed beside
-    them.  Returns ({variant: ms per pass}, outputs or None); a pass is
+    them, with each loop its own launch and with every loop a task of the
+    persistent kernel (the loops of one sweep, independent of each other,
+    then share one launch: kernel-level parallelism).  Returns ({variant: ms per pass}, outputs or None); a pass is
     `steps` ping-pong sweeps of every grid (sides log-uniform in [64, 1024])."""
     import torch
     r = inputs.rng(seed)
@@ -215,10 +217,10 @@ def independent_loops(n_loops=96, streams=(1, 4, 16), steps=2, seed=11, reps=5, 
             grids.append((a, b))
         return grids
 
-    def one_pass(ctx, grids):
+    def one_pass(ctx, grids, cfg=None):
         for t in range(steps):
             for a, b in grids:
-                (ctx.jacobi2d(a, b) if t % 2 == 0 else ctx.jacobi2d(b, a))
+                (ctx.jacobi2d(a, b, cfg=cfg) if t % 2 == 0 else ctx.jacobi2d(b, a, cfg=cfg))
 
     for ns in streams:
         ctx = jacc.Context(ns)
@@ -244,6 +246,13 @@ def independent_loops(n_loops=96, streams=(1, 4, 16), steps=2, seed=11, reps=5, 
                 one_pass(ctx, grids)
                 g = ctx.batch_end()
                 out["graph"] = round(float(np.median(ctx.batch_time(g, warmup=2, reps=reps))), 4)
+                # the same pass with every loop a task of the persistent
+                # kernel: the independent loops of a sweep share one launch
+                ctx.batch_begin()
+                one_pass(ctx, grids, jacc.config(persistent=1))
+                g = ctx.batch_end()
+                out["graph_tasks"] = round(float(np.median(ctx.batch_time(g, warmup=2, reps=reps))), 4)
+                out["graph_tasks_launches_per_pass"] = ctx.batch_info(g)["persistent_groups"]
         finally:
             ctx.close()
     return out, (shapes, outputs)

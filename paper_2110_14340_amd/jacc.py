@@ -342,7 +342,10 @@ class Context:
         if st != OK:
             raise JaccError(st, "jacc_init failed: " + self.L.jacc_last_error(None).decode())
         self.arrays = {}
+        self._ids = {}  # id(array) -> (array, host address) of entered arrays
         self._calls = {}
+        self._no_scalars = (ctypes.c_double * 1)(0.0)
+        self._loop_fn = self.L.jacc_parallel_loop
 
     # -- helpers ---------------------------------------------------------
     def _check(self, st):
@@ -354,8 +357,13 @@ class Context:
         """Status name of a raw return code (for tests of error paths)."""
         return STATUS_NAMES.get(st, st)
 
-    @staticmethod
-    def _ptr(a):
+    def _ptr(self, a):
+        """Host address of an array; entered arrays are looked up by identity
+        (the context holds them, so neither their id nor their buffer can
+        change while it is open)."""
+        ent = self._ids.get(id(a))
+        if ent is not None and ent[0] is a:
+            return ent[1]
         return a.__array_interface__["data"][0]
 
     def close(self):
@@ -363,6 +371,7 @@ class Context:
             st = self.L.jacc_finalize(self.ctx)
             self.ctx = ctypes.c_void_p()
             self.arrays.clear()
+            self._ids.clear()
             return st
         return OK
 
@@ -387,7 +396,9 @@ class Context:
         if raw:
             return st
         self._check(st)
-        self.arrays[self._ptr(a)] = a
+        p = self._ptr(a)
+        self.arrays[p] = a
+        self._ids[id(a)] = (a, p)
         return st
 
     def exit(self, a, clause=COPYOUT, raw=False):
@@ -429,11 +440,10 @@ class Context:
             b = bounds(*pairs)
             ent = self._calls[key] = (A, b, ctypes.byref(b))
         A, _, bref = ent
-        S = (ctypes.c_double * max(1, len(scalars)))(*scalars)
+        S = (ctypes.c_double * len(scalars))(*scalars) if scalars else self._no_scalars
         out = ctypes.c_double(0.0) if sync else None
-        st = self.L.jacc_parallel_loop(self.ctx, kind, bref, 2, A, S, len(scalars), slot,
-                                       ctypes.byref(out) if sync else None,
-                                       ctypes.byref(cfg) if cfg is not None else None)
+        st = self._loop_fn(self.ctx, kind, bref, 2, A, S, len(scalars), slot, ctypes.byref(out) if sync else None,
+                           ctypes.byref(cfg) if cfg is not None else None)
         if raw:
             return st
         self._check(st)

@@ -15,7 +15,10 @@ def test_independent_loops_on_many_streams_bit_exact():
     seed, steps, reps = 11, 2, 1
     times, (shapes, outs) = experiment.independent_loops(n_loops=24, streams=(1, 4, 16), steps=steps, seed=seed,
                                                          reps=reps, keep_outputs=True)
-    assert set(times) == {"eager_1_streams", "eager_4_streams", "eager_16_streams", "graph"}
+    assert set(times) == {"eager_1_streams", "eager_4_streams", "eager_16_streams", "graph", "graph_tasks",
+                          "graph_tasks_launches_per_pass"}
+    # the independent loops of each sweep share one task-kernel launch
+    assert times["graph_tasks_launches_per_pass"] == steps
     for i, sh in enumerate(shapes):
         u0 = inputs.jacobi_grid(*sh, seed=seed + i)
         assert np.array_equal(outs[i], oracle.jacobi2d(u0, steps * (1 + reps))), (i, sh)
