@@ -53,15 +53,16 @@ def counted_traffic():
     return int(rec["traffic_bytes_per_launch"]) if rec.get("source_sha1") == h else None
 
 
-def run_jacobi(ctx_mod, torch, u0, K, steps, warmup, cfg=None, flags=0):
-    """Times `steps` partitioned Jacobi sweeps after `warmup` untimed ones.
-    Returns (seconds, stream-0 event seconds)."""
+def run_jacobi(ctx_mod, torch, u0, K, steps, warmup, cfg=None, flags=0, part_dim=0):
+    """Times `steps` partitioned Jacobi sweeps after `warmup` untimed ones
+    (row blocks, or column blocks with part_dim=1).  Returns (seconds,
+    stream-0 event seconds)."""
     jacc = ctx_mod
     a = u0.copy()
     b = u0.copy()
     c = jacc.Context(K, flags=flags)
-    c.enter(a, halo=(1, 1))
-    c.enter(b, halo=(1, 1))
+    c.enter(a, halo=(1, 1), part_dim=part_dim)
+    c.enter(b, halo=(1, 1), part_dim=part_dim)
     src, dst = a, b
     for _ in range(warmup):
         c.jacobi2d(src, dst, cfg=cfg)
@@ -308,6 +309,13 @@ def main():
             wall, _ = run_jacobi(jacc, torch, u0, K, args.steps, args.warmup, flags=fl)
             modes.setdefault(name, {})[str(K)] = {"ms_per_step": round(wall / args.steps * 1e3, 5),
                                                   "gbps": round(step_bytes * args.steps / wall / 1e9, 1)}
+    # the arrays split into column blocks instead (halo columns pulled as
+    # strided 2-D copies before each sweep)
+    for K in ks:
+        log(f"jacobi K={K} column blocks")
+        wall, _ = run_jacobi(jacc, torch, u0, K, args.steps, args.warmup, part_dim=1)
+        modes.setdefault("column_split", {})[str(K)] = {"ms_per_step": round(wall / args.steps * 1e3, 5),
+                                                        "gbps": round(step_bytes * args.steps / wall / 1e9, 1)}
     graph, graph_plain = {}, {}
     for K in ks:
         log(f"jacobi K={K} as a replayed graph")

@@ -85,14 +85,26 @@ typedef struct {
 
 typedef enum { JACC_F64 = 0, JACC_F32 = 1, JACC_I32 = 2, JACC_I64 = 3 } jacc_dtype;
 
-/* Array descriptor.  Row-major; dim 0 is the partitioned (outermost)
- * dimension with extent E = extent[0]; a "row" is one index of dim 0 and
- * holds extent[1]*...*extent[ndim-1] elements.  halo_lo/halo_hi are the
- * largest distances (in rows) below and above the owner block that loops
- * will read.  whole != 0 keeps a full replica in every partition.
- * num_partitions: K of this array (0 = the context's K; at most 64; with more
- * partitions than the context has streams, partition p runs on stream p mod
- * the stream count). */
+/* Array descriptor.  Row-major.  part_dim is the partitioned dimension (0,
+ * or 1 for a 2-D array; Sec. "Division of Multidimensional Arrays": the
+ * dimension jacc_parallel_dim chooses) with extent E = extent[part_dim]; a
+ * "row" is one index of that dimension: with part_dim 0 it holds
+ * extent[1]*...*extent[ndim-1] contiguous elements, with part_dim 1 it is a
+ * column of extent[0] elements, extent[1] apart in the host array.  Row
+ * ranges everywhere in this interface (owner blocks, halos, access offsets,
+ * updates) count such rows.  halo_lo/halo_hi are the largest distances (in
+ * rows) below and above the owner block that loops will read.  whole != 0
+ * keeps a full replica in every partition.  num_partitions: K of this array
+ * (0 = the context's K; at most 64; with more partitions than the context has
+ * streams, partition p runs on stream p mod the stream count).
+ * A partition's slab of a part_dim 1 array is its columns, stored as a
+ * dense (extent[0] x slab columns) block; its transfers are strided 2-D
+ * copies.  Such arrays are never whole (JACC_ERR_INVALID) and take JACOBI2D
+ * loops only, with both arguments split along dimension 1 (otherwise
+ * JACC_ERR_UNSUPPORTED): one double per lane (vec 2: JACC_ERR_INVALID), no
+ * mirror stores (halo columns are pulled, or sent under JACC_INIT_EAGER), no
+ * FILTERED output, no persistent execution, no tuning or cost-model picks
+ * (JACC_ERR_UNSUPPORTED). */
 typedef struct {
     int32_t dtype;
     int32_t ndim;            /* 1..4 */
@@ -100,6 +112,8 @@ typedef struct {
     int32_t halo_lo, halo_hi;
     int32_t whole;
     int32_t num_partitions;
+    int32_t part_dim;        /* 0, or 1 for ndim == 2 */
+    int32_t reserved;        /* must be 0 */
 } jacc_array_desc;
 
 /* data_enter clauses */
@@ -376,8 +390,9 @@ int jacc_time_loop_parts(jacc_ctx *ctx, int kind, const jacc_bounds *bounds, int
                          double *kernel_ms, int nkernel);
 
 /* Device pointer of partition p's slab of the array containing `host`, and
- * the slab's first and one-past-last rows.  For callers that run their own
- * kernels on the data (and for tests). */
+ * the slab's first and one-past-last rows (columns for a part_dim 1 array,
+ * whose slab is a dense extent[0] x (row_hi - row_lo) block).  For callers
+ * that run their own kernels on the data (and for tests). */
 int jacc_slab_info(jacc_ctx *ctx, void *host, int p, void **dev, int64_t *row_lo,
                    int64_t *row_hi);
 

@@ -101,10 +101,10 @@ __device__ __forceinline__ int64_t march_dir(int march, int64_t q) { return (mar
 // ---------------------------------------------------------------------------
 template <int VEC>
 __device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, double *__restrict__ out, int64_t nx,
-                                            int64_t r_lo, int64_t r_hi, int64_t c_lo, int64_t c_hi, int64_t col0,
-                                            int tile, int march, const Mirrors &mir, int64_t bxi, int64_t byi, int tx,
-                                            int ty, int bdx, int bdy, int64_t own_lo = INT64_MIN,
-                                            int64_t own_hi = INT64_MAX) {
+                                            int64_t pitch, int64_t r_lo, int64_t r_hi, int64_t c_lo, int64_t c_hi,
+                                            int64_t col0, int tile, int march, const Mirrors &mir, int64_t bxi,
+                                            int64_t byi, int tx, int ty, int bdx, int bdy,
+                                            int64_t own_lo = INT64_MIN, int64_t own_hi = INT64_MAX) {
     const int lane = tx & (kWave - 1);
     const int64_t j = col0 + (bxi * bdx + tx) * VEC;
     const int64_t q = byi * bdy + ty;
@@ -129,13 +129,13 @@ __device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, doubl
     Row<VEC> r[kU + 2];
 #pragma unroll
     for (int k = 0; k < kU + 2; ++k)
-        if (k <= n + 1) load_row<VEC>(in + (a + (k - 1) * d) * nx + j, inb, lane, need_l, need_r, r[k]);
+        if (k <= n + 1) load_row<VEC>(in + (a + (k - 1) * d) * pitch + j, inb, lane, need_l, need_r, r[k]);
     for (int64_t m = 0; m < n; m += kU) {
         Row<VEC> nxt[kU];
 #pragma unroll
         for (int k = 0; k < kU; ++k) {
             const int64_t idx = m + kU + 2 + k;
-            if (idx <= n + 1) load_row<VEC>(in + (a + (idx - 1) * d) * nx + j, inb, lane, need_l, need_r, nxt[k]);
+            if (idx <= n + 1) load_row<VEC>(in + (a + (idx - 1) * d) * pitch + j, inb, lane, need_l, need_r, nxt[k]);
         }
 #pragma unroll
         for (int k = 0; k < kU; ++k) {
@@ -153,7 +153,7 @@ __device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, doubl
                 }
                 // write guard of a filtered loop (every partition computes the
                 // whole box and keeps its owner rows); uniform per row
-                if (row >= own_lo && row < own_hi) store_out<VEC>(out, row * nx + j, row, mir, o, all, comp);
+                if (row >= own_lo && row < own_hi) store_out<VEC>(out, row * pitch + j, row, mir, o, all, comp);
             }
         }
 #pragma unroll
@@ -174,11 +174,11 @@ __device__ __forceinline__ int64_t tile_of(int order) {
 
 template <int VEC>
 __global__ void __launch_bounds__(1024)
-jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t nx, int64_t r_lo, int64_t r_hi,
-                int64_t c_lo, int64_t c_hi, int64_t col0, int tile, int march, Mirrors mir, int64_t gx, int order,
-                int64_t own_lo, int64_t own_hi) {
+jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t nx, int64_t pitch, int64_t r_lo,
+                int64_t r_hi, int64_t c_lo, int64_t c_hi, int64_t col0, int tile, int march, Mirrors mir, int64_t gx,
+                int order, int64_t own_lo, int64_t own_hi) {
     const int64_t t = tile_of(order);
-    jacobi_tile<VEC>(in, out, nx, r_lo, r_hi, c_lo, c_hi, col0, tile, march, mir, t % gx, t / gx, threadIdx.x,
+    jacobi_tile<VEC>(in, out, nx, pitch, r_lo, r_hi, c_lo, c_hi, col0, tile, march, mir, t % gx, t / gx, threadIdx.x,
                      threadIdx.y, blockDim.x, blockDim.y, own_lo, own_hi);
 }
 
@@ -458,10 +458,10 @@ __device__ __forceinline__ void persistent_tile(const PTask &T, int64_t local) {
     const int64_t rest = local / T.gx;
     if (JONLY || T.kind == JACC_LOOP_JACOBI2D) {
         if (T.vec == 2)
-            jacobi_tile<2>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, T.mir, bxi,
+            jacobi_tile<2>(T.in, T.out, T.e1, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, T.mir, bxi,
                            rest, threadIdx.x, 0, kPersistentThreads, 1);
         else
-            jacobi_tile<1>(T.in, T.out, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, T.mir, bxi,
+            jacobi_tile<1>(T.in, T.out, T.e1, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, T.mir, bxi,
                            rest, threadIdx.x, 0, kPersistentThreads, 1);
     } else if constexpr (!JONLY) {
         const int64_t byi = rest % T.gy, bzi = rest / T.gy;
@@ -516,14 +516,18 @@ hipError_t launch_jacobi2d(const Launch &L, hipStream_t s) {
     dim3 grid((unsigned)(gx * gy));
     const double *in = (const double *)L.a[0].ptr;
     double *out = (double *)L.a[1].ptr;
+    // elements between vertically adjacent values: the row length, or the
+    // slab width of arrays partitioned along columns (both arguments alike)
+    const int64_t pitch = L.a[0].row_elems;
+    if (L.a[1].row_elems != pitch) return hipErrorInvalidValue;
     const bool filtered = L.own_hi > L.own_lo;  // FILTERED output: keep the owner rows only
     const int64_t own_lo = filtered ? L.own_lo : INT64_MIN, own_hi = filtered ? L.own_hi : INT64_MAX;
     if (c.vec == 2)
-        hipLaunchKernelGGL(jacobi2d_kernel<2>, grid, block, 0, s, in, out, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1],
-                           col0, c.tile, c.march, L.mir, gx, c.order, own_lo, own_hi);
+        hipLaunchKernelGGL(jacobi2d_kernel<2>, grid, block, 0, s, in, out, nx, pitch, L.lo[0], L.hi[0], L.lo[1],
+                           L.hi[1], col0, c.tile, c.march, L.mir, gx, c.order, own_lo, own_hi);
     else
-        hipLaunchKernelGGL(jacobi2d_kernel<1>, grid, block, 0, s, in, out, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1],
-                           col0, c.tile, c.march, L.mir, gx, c.order, own_lo, own_hi);
+        hipLaunchKernelGGL(jacobi2d_kernel<1>, grid, block, 0, s, in, out, nx, pitch, L.lo[0], L.hi[0], L.lo[1],
+                           L.hi[1], col0, c.tile, c.march, L.mir, gx, c.order, own_lo, own_hi);
     return hipGetLastError();
 }
 

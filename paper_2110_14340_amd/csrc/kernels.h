@@ -9,11 +9,14 @@ namespace jk {
 // One argument as a kernel sees it: `ptr` is the device address of global
 // row 0 of the array *as if* the slab started there (slab pointer minus
 // slab_lo rows), so kernels index with global row numbers; only rows
-// [slab_lo, slab_hi) may be touched.
+// [slab_lo, slab_hi) may be touched.  For a 2-D array partitioned along
+// dim 1 the slab holds columns [slab_lo, slab_hi) of every row, `ptr` is
+// the slab pointer minus slab_lo elements, and element (i, j) sits at
+// ptr + i*row_elems + j.
 struct Arg {
     const void *ptr;       // biased pointer (see above)
     int64_t slab_lo, slab_hi;
-    int64_t row_elems;     // elements per row of dim 0
+    int64_t row_elems;     // elements per row of dim 0 (the slab's width when split along dim 1)
 };
 
 struct Cfg {

@@ -204,8 +204,9 @@ struct Array {
     int K = 1;
     int home = 0;         // stream of partition 0 for transfers; partition p uses (home + p) mod streams
     int last_stream = -1;  // base stream of the last loop that wrote this array
-    int64_t E = 0, row_elems = 1;
+    int64_t E = 0, row_elems = 1;   // rows along the partitioned dimension; elements per row
     size_t esize = 8, row_bytes = 8;
+    int pdim = 0;  // partitioned dimension: 0, or 1 (a 2-D array split into column blocks)
     int refs = 1;
     bool whole = false;
     std::vector<Slab> slabs;
@@ -573,6 +574,39 @@ Array *lookup(jacc_ctx *c, const void *host) {
 
 // ---- copies ------------------------------------------------------------
 // Copy rows r of array A from slab q to slab p, on stream s.
+// Moves rows r between the host array and slab p (dir 1 host to device, 2
+// device to host) or from slab q to slab p (dir 3) on stream s.  A part_dim
+// 0 array's rows are contiguous in both; a part_dim 1 array's rows are
+// columns: a strided 2-D copy of (r.hi - r.lo) elements from each of its
+// extent[0] rows, with the host's row pitch and each slab's own.
+int move_rows(jacc_ctx *c, Array *A, int dir, int q, int p, Range r, int s) {
+    if (!live(c) || r.empty()) return JACC_OK;
+    if (r.lo < 0 || r.hi > A->E) return set_err(c, JACC_ERR_INVALID, "internal: rows outside array %d", A->id);
+    auto inside = [&](int pp) { return r.lo >= A->slabs[pp].rows.lo && r.hi <= A->slabs[pp].rows.hi; };
+    if ((dir != 1 && !inside(q)) || (dir != 2 && !inside(p)))
+        return set_err(c, JACC_ERR_INVALID, "internal: rows [%lld,%lld) outside a slab of array %d", (long long)r.lo,
+                       (long long)r.hi, A->id);
+    const hipMemcpyKind kind =
+        dir == 1 ? hipMemcpyHostToDevice : dir == 2 ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    const size_t unit = A->pdim == 0 ? A->row_bytes : A->esize;  // bytes of a row within one line
+    auto slab_ptr = [&](int pp) { return (char *)A->slabs[pp].dev + (size_t)(r.lo - A->slabs[pp].rows.lo) * unit; };
+    char *host = (char *)A->host + (size_t)r.lo * unit;
+    char *src = dir == 1 ? host : slab_ptr(q);
+    char *dst = dir == 2 ? host : slab_ptr(p);
+    if (A->pdim == 0) {
+        HIPCHK(c, hipMemcpyAsync(dst, src, (size_t)(r.hi - r.lo) * unit, kind, c->st[s].s), "hipMemcpyAsync");
+    } else {
+        const size_t host_pitch = (size_t)A->d.extent[1] * A->esize;
+        auto pitch = [&](int pp) { return (size_t)(A->slabs[pp].rows.hi - A->slabs[pp].rows.lo) * A->esize; };
+        const size_t spitch = dir == 1 ? host_pitch : pitch(q);
+        const size_t dpitch = dir == 2 ? host_pitch : pitch(p);
+        HIPCHK(c, hipMemcpy2DAsync(dst, dpitch, src, spitch, (size_t)(r.hi - r.lo) * A->esize, (size_t)A->d.extent[0],
+                                   kind, c->st[s].s),
+               "hipMemcpy2DAsync");
+    }
+    return JACC_OK;
+}
+
 int issue_copy(jacc_ctx *c, Array *A, int q, int p, Range r, int s) {
     int rc = hazard(c, A, q, r, false, s);
     if (rc) return rc;
@@ -582,14 +616,8 @@ int issue_copy(jacc_ctx *c, Array *A, int q, int p, Range r, int s) {
         c->status = JACC_ERR_DEVICE;
         return set_err(c, JACC_ERR_DEVICE, "injected fault in copy %lld", (long long)c->fault_count);
     }
-    const Slab &src = A->slabs[q];
-    const Slab &dst = A->slabs[p];
-    size_t bytes = (size_t)(r.hi - r.lo) * A->row_bytes;
-    if (live(c)) {
-        char *sp = (char *)src.dev + (size_t)(r.lo - src.rows.lo) * A->row_bytes;
-        char *dp = (char *)dst.dev + (size_t)(r.lo - dst.rows.lo) * A->row_bytes;
-        HIPCHK(c, hipMemcpyAsync(dp, sp, bytes, hipMemcpyDeviceToDevice, c->st[s].s), "hipMemcpyAsync(D2D)");
-    }
+    rc = move_rows(c, A, 3, q, p, r, s);
+    if (rc) return rc;
     c->st[s].seq++;
     trace(c, JACC_OP_COPY, s, A->id, q, p, 0, r.lo, r.hi, c->st[s].seq);
     return post_op(c);
@@ -677,14 +705,9 @@ int h2d_rows(jacc_ctx *c, Array *A, int p, Range r) {
     const int s = stream_of(c, A, p);
     int rc = hazard(c, A, p, r, true, s);
     if (rc) return rc;
-    const Slab &sl = A->slabs[p];
     ++A->version;
-    if (live(c)) {
-        char *dp = (char *)sl.dev + (size_t)(r.lo - sl.rows.lo) * A->row_bytes;
-        const char *hp = (const char *)A->host + (size_t)r.lo * A->row_bytes;
-        HIPCHK(c, hipMemcpyAsync(dp, hp, (size_t)(r.hi - r.lo) * A->row_bytes, hipMemcpyHostToDevice, c->st[s].s),
-               "hipMemcpyAsync(H2D)");
-    }
+    rc = move_rows(c, A, 1, -1, p, r, s);
+    if (rc) return rc;
     c->st[s].seq++;
     trace(c, JACC_OP_H2D, s, A->id, -1, p, 0, r.lo, r.hi, c->st[s].seq);
     return post_op(c);
@@ -694,13 +717,8 @@ int d2h_rows(jacc_ctx *c, Array *A, int p, Range r) {
     const int s = stream_of(c, A, p);
     int rc = hazard(c, A, p, r, false, s);
     if (rc) return rc;
-    const Slab &sl = A->slabs[p];
-    if (live(c)) {
-        const char *sp = (const char *)sl.dev + (size_t)(r.lo - sl.rows.lo) * A->row_bytes;
-        char *hp = (char *)A->host + (size_t)r.lo * A->row_bytes;
-        HIPCHK(c, hipMemcpyAsync(hp, sp, (size_t)(r.hi - r.lo) * A->row_bytes, hipMemcpyDeviceToHost, c->st[s].s),
-               "hipMemcpyAsync(D2H)");
-    }
+    rc = move_rows(c, A, 2, p, -1, r, s);
+    if (rc) return rc;
     c->st[s].seq++;
     trace(c, JACC_OP_D2H, s, A->id, p, -1, 0, r.lo, r.hi, c->st[s].seq);
     return post_op(c);
@@ -746,7 +764,7 @@ void free_array(jacc_ctx *c, Array *A) {
 
 bool desc_equal(const jacc_array_desc &a, const jacc_array_desc &b) {
     if (a.dtype != b.dtype || a.ndim != b.ndim || a.halo_lo != b.halo_lo || a.halo_hi != b.halo_hi ||
-        a.whole != b.whole || a.num_partitions != b.num_partitions)
+        a.whole != b.whole || a.num_partitions != b.num_partitions || a.part_dim != b.part_dim)
         return false;
     for (int i = 0; i < a.ndim; ++i)
         if (a.extent[i] != b.extent[i]) return false;
@@ -864,6 +882,14 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
         if (A->K != K) return set_err(c, JACC_ERR_UNSUPPORTED, "arguments are partitioned with different K");
         arr[i] = A;
     }
+    // arrays split along dimension 1 (column blocks) take the 2-D stencil
+    // only, with every argument split the same way
+    const int pd = arr[0]->pdim;
+    for (int i = 1; i < nargs; ++i)
+        if (arr[i]->pdim != pd)
+            return set_err(c, JACC_ERR_UNSUPPORTED, "arguments are partitioned along different dimensions");
+    if (pd != 0 && kind != JACC_LOOP_JACOBI2D)
+        return set_err(c, JACC_ERR_UNSUPPORTED, "loop kind %d does not take arrays split along dimension %d", kind, pd);
     auto is = [&](int i, int dt, int nd) { return arr[i]->d.dtype == dt && arr[i]->d.ndim == nd; };
     L = jk::Launch{};
     L.kind = kind;
@@ -877,7 +903,8 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
             if (!is(0, JACC_F64, 2) || !is(1, JACC_F64, 2) || arr[0]->d.extent[0] != arr[1]->d.extent[0] ||
                 arr[0]->d.extent[1] != arr[1]->d.extent[1])
                 return set_err(c, JACC_ERR_INVALID, "JACOBI2D takes two FP64 2-D arrays of equal shape");
-            if (b->hi[0] > arr[0]->E - 1 || b->lo[0] < 1 || b->lo[1] < 1 || b->hi[1] > arr[0]->d.extent[1] - 1)
+            if (b->hi[0] > arr[0]->d.extent[0] - 1 || b->lo[0] < 1 || b->lo[1] < 1 ||
+                b->hi[1] > arr[0]->d.extent[1] - 1)
                 return set_err(c, JACC_ERR_RANGE, "JACOBI2D bounds must lie inside the interior");
             primary = 1;
             break;
@@ -969,10 +996,13 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
     // filtered output entered whole is divided into owner blocks like a
     // partitioned one; its replicas hold every row.
     const bool filtered = (args[primary].mode & JACC_FILTERED) != 0;
+    if (pd != 0 && filtered)
+        return set_err(c, JACC_ERR_UNSUPPORTED, "a filtered output split along dimension %d", pd);
+    const Range all_iters{b->lo[pd], b->hi[pd]};  // iterations along the partitioned dimension
     plan.assign(K, PartPlan{});
     for (int p = 0; p < K; ++p) {
         Range own = (P->whole && !filtered) ? (p == 0 ? Range{0, P->E} : Range{0, 0}) : P->block(p);
-        plan[p].iters = (filtered || dup) ? Range{b->lo[0], b->hi[0]} : isect({b->lo[0], b->hi[0]}, own);
+        plan[p].iters = (filtered || dup) ? all_iters : isect(all_iters, own);
         if (filtered && !dup && own.empty()) plan[p].iters = Range{};
         plan[p].rng.resize(nargs);
         for (int i = 0; i < nargs; ++i) {
@@ -1020,8 +1050,18 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
     }
     jk::Cfg cf{0, 0, 0, 0, 0, 0, 0, 0};
     L.part_rows = 0;
-    for (const PartPlan &pp : plan) L.part_rows = std::max(L.part_rows, pp.iters.hi - pp.iters.lo);
+    for (const PartPlan &pp : plan)
+        L.part_rows = std::max(L.part_rows, pd == 0 ? pp.iters.hi - pp.iters.lo
+                                                    : (pp.iters.empty() ? 0 : b->hi[0] - b->lo[0]));
     if (cfg) cf = {cfg->bx, cfg->by, cfg->tile, cfg->vec, cfg->persistent, cfg->order, cfg->march, cfg->rows};
+    if (pd != 0) {
+        // a column slab's width decides the alignment of its rows: single
+        // lanes per column, eager launches only
+        if (cf.vec > 1) return set_err(c, JACC_ERR_INVALID, "arrays split along dimension 1 take vec 1");
+        if (cf.persistent)
+            return set_err(c, JACC_ERR_UNSUPPORTED, "persistent execution of arrays split along dimension 1");
+        cf.vec = 1;
+    }
     L.cfg = jk::default_config(kind, L, cf);
     if (kind == JACC_LOOP_SPMV_CSR && !cf.order && !c->cur && arr[3]->E >= kBandedMinCols) {
         // x far larger than an XCD's L2: the column-banded form, one band
@@ -1105,9 +1145,10 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     jacc_config picked;
     if (!cfg && c->model && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) && nargs == 2 && args) {
         // no configuration given: the attached cost model's pick for this
-        // loop on its arrays' partitions (cached per loop signature)
+        // loop on its arrays' partitions (cached per loop signature; arrays
+        // split along dimension 1 keep the defaults)
         Array *W = lookup(c, args[1].host);
-        if (W && W->host == (uintptr_t)args[1].host &&
+        if (W && W->host == (uintptr_t)args[1].host && W->pdim == 0 &&
             jr::model_config(c, kind, W->d.extent, W->d.ndim, W->K, &picked))
             cfg = &picked;
     }
@@ -1182,8 +1223,8 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
         if (args[i].mode & JACC_WRITE) arr[i]->last_stream = base;
     // mirrors: a stencil partition also writes the rows of its output that
     // other slabs hold as halo (at most one neighbour block on each side)
-    const bool can_mirror =
-        !c->lazy && !c->eager && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) && !P->whole && K > 1;
+    const bool can_mirror = !c->lazy && !c->eager && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) &&
+                            !P->whole && K > 1 && P->pdim == 0;
     const int red_slot = slot >= 0 ? slot : kSlots - 1;  // a synchronous-only reduction uses the last slot
     std::vector<int> order;       // partitions that reduce, in partition order
     std::vector<int> red_streams;  // their streams
@@ -1203,7 +1244,7 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     for (int d = 1; d < b->ndim; ++d) part_cells *= std::max<int64_t>(0, b->hi[d] - b->lo[d]);
     const bool auto_split = K <= 4 && !c->no_split && part_cells >= ((int64_t)1 << 22);
     const bool split = (c->split || auto_split) && !c->time_parts && !want_red && !persistent && !one_stream && K > 1 &&
-                       !(args[primary].mode & JACC_FILTERED) &&
+                       !(args[primary].mode & JACC_FILTERED) && P->pdim == 0 &&
                        (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D);
     if (split) {
         int e = 0;  // halo depth of the reads along dim 0
@@ -1256,18 +1297,22 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
                 if (rc) return rc;
             }
         jk::Launch LP = L;
-        LP.lo[0] = pp.iters.lo;
-        LP.hi[0] = pp.iters.hi;
-        for (int d = 1; d < b->ndim; ++d) {
+        for (int d = 0; d < b->ndim; ++d) {
             LP.lo[d] = b->lo[d];
             LP.hi[d] = b->hi[d];
         }
+        LP.lo[P->pdim] = pp.iters.lo;
+        LP.hi[P->pdim] = pp.iters.hi;
         for (int i = 0; i < nargs; ++i) {
+            // biased so that global indices address the slab: by whole rows,
+            // or by elements for column slabs (whose width is the row pitch)
             const Slab &sl = arr[i]->slabs[p];
-            LP.a[i].ptr = (const char *)sl.dev - (intptr_t)((size_t)sl.rows.lo * arr[i]->row_bytes);
+            const bool cols = arr[i]->pdim != 0;
+            const size_t unit = cols ? arr[i]->esize : arr[i]->row_bytes;
+            LP.a[i].ptr = (const char *)sl.dev - (intptr_t)((size_t)sl.rows.lo * unit);
             LP.a[i].slab_lo = sl.rows.lo;
             LP.a[i].slab_hi = sl.rows.hi;
-            LP.a[i].row_elems = arr[i]->row_elems;
+            LP.a[i].row_elems = cols ? sl.rows.hi - sl.rows.lo : arr[i]->row_elems;
         }
         if (args[primary].mode & JACC_FILTERED) {
             LP.own_lo = pp.rng[primary].lo;
@@ -1684,12 +1729,20 @@ int jacc_data_enter(jacc_ctx *c, void *host, const jacc_array_desc *d, int claus
             if (i > 0) row *= d->extent[i];
         }
         if (d->halo_lo < 0 || d->halo_hi < 0) return set_err(c, JACC_ERR_INVALID, "negative halo");
+        if (d->reserved != 0) return set_err(c, JACC_ERR_INVALID, "reserved descriptor field not 0");
+        if (d->part_dim != 0 && d->part_dim != 1) return set_err(c, JACC_ERR_INVALID, "part_dim must be 0 or 1");
+        if (d->part_dim == 1 && d->ndim != 2)
+            return set_err(c, JACC_ERR_UNSUPPORTED, "arrays are split along dimension 1 only when they are 2-D");
+        if (d->part_dim != 0 && d->whole)
+            return set_err(c, JACC_ERR_INVALID, "an array entered whole is not split: part_dim must be 0");
+        const int64_t E = d->extent[d->part_dim];
         int K = d->num_partitions ? d->num_partitions : c->K;
         // more partitions than streams is allowed: partition p then runs on
         // stream p mod the stream count
         if (K < 1 || K > kMaxK) return set_err(c, JACC_ERR_INVALID, "num_partitions %d not in [1,%d]", K, kMaxK);
-        if (!d->whole && K > d->extent[0])
-            return set_err(c, JACC_ERR_INVALID, "K=%d exceeds the %lld rows of dim 0", K, (long long)d->extent[0]);
+        if (!d->whole && K > E)
+            return set_err(c, JACC_ERR_INVALID, "K=%d exceeds the %lld rows of dimension %d", K, (long long)E,
+                           d->part_dim);
         size_t bytes = (size_t)d->extent[0] * (size_t)row * es;
         if (Array *A = lookup(c, host)) {
             if (A->host == (uintptr_t)host && A->bytes == bytes && desc_equal(A->d, *d)) {
@@ -1710,10 +1763,11 @@ int jacc_data_enter(jacc_ctx *c, void *host, const jacc_array_desc *d, int claus
         A->d = *d;
         A->K = K;
         A->home = (K == nstreams(c) || c->serialize) ? 0 : (c->next_home++ % nstreams(c));
-        A->E = d->extent[0];
-        A->row_elems = row;
+        A->pdim = d->part_dim;
+        A->E = E;
+        A->row_elems = A->pdim == 0 ? row : d->extent[0];  // a row of dimension 1 is a column
         A->esize = es;
-        A->row_bytes = (size_t)row * es;
+        A->row_bytes = (size_t)A->row_elems * es;
         A->whole = d->whole != 0;
         A->slabs.resize(K);
         A->valid.resize(K);

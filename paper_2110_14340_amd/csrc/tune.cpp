@@ -300,6 +300,8 @@ int loop_shape(jacc_ctx *c, int kind, int nargs, const jacc_arg *args, int64_t *
     if (rc) return rc;
     if (!stencil_kind(kind, d.ndim))
         return jr::error(c, JACC_ERR_UNSUPPORTED, "tuning covers JACOBI2D and HEAT3D loops");
+    if (d.part_dim != 0)
+        return jr::error(c, JACC_ERR_UNSUPPORTED, "tuning covers arrays split along dimension 0");
     *ndim = d.ndim;
     for (int i = 0; i < d.ndim; ++i) e[i] = d.extent[i];
     return JACC_OK;

@@ -37,7 +37,7 @@ _DTYPES = {np.dtype(np.float64): F64, np.dtype(np.float32): F32, np.dtype(np.int
 class ArrayDesc(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("ndim", ctypes.c_int32), ("extent", ctypes.c_int64 * 4),
                 ("halo_lo", ctypes.c_int32), ("halo_hi", ctypes.c_int32), ("whole", ctypes.c_int32),
-                ("num_partitions", ctypes.c_int32)]
+                ("num_partitions", ctypes.c_int32), ("part_dim", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Arg(ctypes.Structure):
@@ -382,7 +382,7 @@ class Context:
         self.close()
 
     # -- data ----------------------------------------------------------------
-    def enter(self, a, halo=(0, 0), whole=False, K=0, clause=COPYIN, raw=False):
+    def enter(self, a, halo=(0, 0), whole=False, K=0, clause=COPYIN, part_dim=0, raw=False):
         assert a.flags.c_contiguous
         d = ArrayDesc()
         d.dtype = _DTYPES[a.dtype]
@@ -392,6 +392,7 @@ class Context:
         d.halo_lo, d.halo_hi = halo
         d.whole = int(whole)
         d.num_partitions = K
+        d.part_dim = part_dim
         st = self.L.jacc_data_enter(self.ctx, self._ptr(a), ctypes.byref(d), clause)
         if raw:
             return st

@@ -16,14 +16,15 @@ def context(K, flags=0):
     return jacc.Context(K, streams="torch", allocator="torch", flags=flags)
 
 
-def run_jacobi(u0, steps, K, cfg=None, ctx_flags=0):
-    """T ping-pong Jacobi sweeps on the device with K partitions; returns the
-    final grid (gathered to the host)."""
+def run_jacobi(u0, steps, K, cfg=None, ctx_flags=0, part_dim=0):
+    """T ping-pong Jacobi sweeps on the device with K partitions (row blocks,
+    or column blocks with part_dim=1); returns the final grid (gathered to
+    the host)."""
     a = np.ascontiguousarray(u0, dtype=np.float64).copy()
     b = a.copy()
     with context(K, ctx_flags) as c:
-        c.enter(a, halo=(1, 1))
-        c.enter(b, halo=(1, 1))
+        c.enter(a, halo=(1, 1), part_dim=part_dim)
+        c.enter(b, halo=(1, 1), part_dim=part_dim)
         src, dst = a, b
         for _ in range(steps):
             c.jacobi2d(src, dst, cfg=cfg)

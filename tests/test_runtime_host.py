@@ -737,3 +737,96 @@ def test_heat_batch_with_residual_slots_on_their_own_streams():
     full = c.trace()
     assert race_check(full) == [] and freshness_check(full) == []
     c.close()
+
+
+# ------------------------------------------------------------------ arrays split along columns (dry run)
+@pytest.mark.parametrize("K", [2, 3, 8])
+@pytest.mark.parametrize("lazy", [True, False])
+def test_column_split_jacobi_plan_matches_model(K, lazy):
+    """A 2-D array split along dimension 1 holds column blocks with halo
+    columns; the plan is the row-split plan with columns in place of rows:
+    kernels cover each partition's interior columns, and a sweep reading the
+    last sweep's output pulls one halo column across each boundary side (as
+    strided copies; no mirror stores of columns)."""
+    ny, E = 20, 67
+    c = dry(K, lazy)
+    a = np.zeros((ny, E))
+    b = np.zeros((ny, E))
+    c.enter(a, halo=(1, 1), part_dim=1)
+    c.enter(b, halo=(1, 1), part_dim=1)
+    model = {"a": P.ArrayState(E, K, 1, 1), "b": P.ArrayState(E, K, 1, 1)}
+    names = {id(a): "a", id(b): "b"}
+    full = c.trace()
+    src, dst = a, b
+    for step in range(3):
+        tr = _loop_trace(c, lambda: c.jacobi2d(src, dst))
+        full += tr
+        ps = P.plan_loop(model, 1, E - 1, [(names[id(src)], "r", -1, 1, False), (names[id(dst)], "w", 0, 0, False)],
+                         refresh="pull")
+        kernels = [t for t in tr if t["op"] == "KERNEL"]
+        assert [(t["dst"], t["lo"], t["hi"]) for t in kernels] == \
+            [(p, min(pp["I"]), max(pp["I"]) + 1) for p, pp in enumerate(ps) if pp["I"]]
+        copies = sorted((t["dst"], t["src"], t["lo"], t["hi"]) for t in tr if t["op"] == "COPY")
+        assert copies == sorted((p, s, lo, hi) for p, pp in enumerate(ps) for (_, s, lo, hi) in pp["copies"])
+        assert len(copies) == (0 if step == 0 else 2 * (K - 1))
+        src, dst = dst, src
+    assert race_check(full) == [] and freshness_check(full) == []
+    c.close()
+
+
+def test_column_split_eager_coherence_sends_halo_columns():
+    K = 4
+    c = jacc.Context(K, flags=DRY | jacc.INIT_EAGER)
+    a = np.zeros((9, 40))
+    b = np.zeros((9, 40))
+    c.enter(a, halo=(1, 1), part_dim=1)
+    c.enter(b, halo=(1, 1), part_dim=1)
+    c.trace_clear()
+    c.jacobi2d(a, b)
+    c.jacobi2d(b, a)
+    ops = c.trace()
+    copies = [t for t in ops if t["op"] == "COPY"]
+    assert len(copies) == 2 * 2 * (K - 1) and all(t["hi"] - t["lo"] == 1 for t in copies)
+    assert race_check(ops) == [] and freshness_check(ops) == []
+    c.close()
+
+
+def test_column_split_refusals():
+    c = dry(4)
+    a2 = np.zeros((10, 40))
+    b2 = np.zeros((10, 40))
+    assert c.enter(np.zeros((4, 5, 6)), part_dim=1, raw=True) == jacc.ERR_UNSUPPORTED
+    assert c.enter(np.zeros((10, 40)), part_dim=1, whole=True, raw=True) == jacc.ERR_INVALID
+    assert c.enter(np.zeros((10, 40)), part_dim=2, raw=True) == jacc.ERR_INVALID
+    assert c.enter(np.zeros((40, 3)), part_dim=1, raw=True) == jacc.ERR_INVALID  # K=4 > 3 columns
+    c.enter(a2, halo=(1, 1), part_dim=1)
+    c.enter(b2, halo=(1, 1), part_dim=1)
+    b_rows = np.zeros((10, 40))
+    c.enter(b_rows, halo=(1, 1))
+    assert c.jacobi2d(a2, b_rows, raw=True) == jacc.ERR_UNSUPPORTED and "dimensions" in c.last_error()
+    assert c.sum(a2, raw=True) == jacc.ERR_UNSUPPORTED
+    assert c.jacobi2d(a2, b2, cfg=jacc.config(vec=2), raw=True) == jacc.ERR_INVALID
+    c.batch_begin()
+    assert c.jacobi2d(a2, b2, cfg=jacc.config(persistent=1), raw=True) == jacc.ERR_UNSUPPORTED
+    c.close()
+
+
+def test_column_split_update_ranges_index_columns():
+    """update(HOST) and update(DEVICE) ranges of a column-split array are
+    column ranges: a gather after one sweep copies each written column range
+    back from its partition."""
+    K = 3
+    c = dry(K)
+    a = np.zeros((6, 30))
+    b = np.zeros((6, 30))
+    c.enter(a, halo=(1, 1), part_dim=1)
+    c.enter(b, halo=(1, 1), part_dim=1)
+    c.jacobi2d(a, b)
+    c.trace_clear()
+    c.update(b, jacc.UPDATE_HOST, 0, 30)
+    d2h = [(t["src"], t["lo"], t["hi"]) for t in c.trace() if t["op"] in ("D2H", "GATHER")]
+    assert d2h, c.trace()
+    covered = sorted((lo, hi) for _, lo, hi in d2h)
+    assert covered[0][0] <= 1 and covered[-1][1] >= 29
+    assert c.update(b, jacc.UPDATE_HOST, 0, 31, raw=True) == jacc.ERR_INVALID
+    c.close()
