@@ -97,14 +97,15 @@ typedef enum { JACC_F64 = 0, JACC_F32 = 1, JACC_I32 = 2, JACC_I64 = 3 } jacc_dty
  * keeps a full replica in every partition.  num_partitions: K of this array
  * (0 = the context's K; at most 64; with more partitions than the context has
  * streams, partition p runs on stream p mod the stream count).
- * A partition's slab of a part_dim 1 array is its columns, stored as a
- * dense (extent[0] x slab columns) block; its transfers are strided 2-D
+ * A partition's slab of a part_dim 1 array holds its columns [lo, hi) as a
+ * row-major block of extent[0] rows that starts at the even column lo & ~1
+ * and has an even pitch ((hi - (lo & ~1) + 1) & ~1 elements), so that even
+ * global columns sit on 16-byte boundaries; its transfers are strided 2-D
  * copies.  Such arrays are never whole (JACC_ERR_INVALID) and take JACOBI2D
  * loops only, with both arguments split along dimension 1 (otherwise
- * JACC_ERR_UNSUPPORTED): one double per lane (vec 2: JACC_ERR_INVALID), no
- * mirror stores (halo columns are pulled, or sent under JACC_INIT_EAGER), no
- * FILTERED output, no persistent execution, no tuning or cost-model picks
- * (JACC_ERR_UNSUPPORTED). */
+ * JACC_ERR_UNSUPPORTED): no mirror stores (halo columns are pulled, or sent
+ * under JACC_INIT_EAGER), no FILTERED output, no persistent execution, no
+ * tuning or cost-model picks (JACC_ERR_UNSUPPORTED). */
 typedef struct {
     int32_t dtype;
     int32_t ndim;            /* 1..4 */
@@ -263,16 +264,44 @@ enum {
     JACC_INIT_EAGER = 1u << 6,     /* the paper's coherence: after every loop each partition
                                       sends the rows it wrote to every other slab holding them
                                       (device copies on its stream); no mirror stores, no pulls */
-    JACC_INIT_FORK_CAPTURE = 1u << 7 /* with JACC_INIT_DRYRUN only: plan batches with every
+    JACC_INIT_FORK_CAPTURE = 1u << 7, /* with JACC_INIT_DRYRUN only: plan batches with every
                                       partition on its own stream, forked from and joined
                                       into stream 0 around the capture (otherwise
                                       JACC_ERR_UNSUPPORTED: graphs are captured on one stream) */
+    JACC_INIT_POISON = 1u << 8,    /* debug: after each loop launched outside a persistent
+                                      group, the rows of FP64/FP32 slabs the loop left stale
+                                      (another partition wrote them and this slab was not
+                                      refreshed) are filled with 0xFF bytes (NaN) by a fill
+                                      kernel ordered like a write, so a read the runtime should
+                                      have preceded by a pull carries NaN into the results */
+    JACC_INIT_MARKERS = 1u << 9    /* roctx ranges around the host phases of each call (loop
+                                      planning, copies and launches, combines; data enter, exit,
+                                      update; batch capture and launch), for rocprofv3
+                                      --marker-trace */
 };
 
-/* Create a context with K partitions (1 <= K <= 64).  streams: K hipStream_t
- * handles owned by the caller, or NULL to let the library create K
- * non-blocking streams of default priority.  alloc: NULL selects hipMalloc.
- * On success *out receives the context. */
+/* Create a context with K partitions (1 <= K <= 64; K = 0 takes the
+ * environment's JACC_K).  streams: K hipStream_t handles owned by the
+ * caller, or NULL to let the library create K non-blocking streams of
+ * default priority.  alloc: NULL selects hipMalloc.  On success *out
+ * receives the context.
+ *
+ * Environment (read here; flags the caller passes win):
+ *   JACC_K=<1..64>            K when the K argument is 0
+ *   JACC_SERIALIZE=1, JACC_TRACE=1, JACC_DEBUG_POISON=1, JACC_ROCTX=1
+ *                             add JACC_INIT_SERIALIZE / _TRACE / _POISON / _MARKERS
+ *   JACC_COHERENCE=lazy|eager add JACC_INIT_LAZY / _EAGER unless the caller chose one
+ *   JACC_TUNE=model|off|exhaustive
+ *                             what a stencil loop called with cfg = NULL outside a batch
+ *                             runs: the attached model's pick (model, the default), the
+ *                             library defaults (off), or jacc_tune's best non-persistent
+ *                             candidate at the arrays' K, tuned once per loop signature
+ *                             and kept for the context (exhaustive)
+ *   JACC_TUNE_DB=<path>       timing database of the exhaustive mode
+ *   JACC_MODEL_PATH=<path>    a cost-model file loaded and attached at init; a file that
+ *                             does not load leaves the context without a model (the
+ *                             reason in jacc_last_error) and init still succeeds
+ * A malformed JACC_K, JACC_COHERENCE or JACC_TUNE value: JACC_ERR_INVALID. */
 int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator *alloc,
               unsigned flags);
 
@@ -391,8 +420,9 @@ int jacc_time_loop_parts(jacc_ctx *ctx, int kind, const jacc_bounds *bounds, int
 
 /* Device pointer of partition p's slab of the array containing `host`, and
  * the slab's first and one-past-last rows (columns for a part_dim 1 array,
- * whose slab is a dense extent[0] x (row_hi - row_lo) block).  For callers
- * that run their own kernels on the data (and for tests). */
+ * whose storage starts at column row_lo & ~1 with the even pitch given at
+ * jacc_array_desc).  For callers that run their own kernels on the data
+ * (and for tests). */
 int jacc_slab_info(jacc_ctx *ctx, void *host, int p, void **dev, int64_t *row_lo,
                    int64_t *row_hi);
 
@@ -578,9 +608,11 @@ enum {
                              private to that slab (a filtered loop's writes outside
                              the partition's owner block), 4 = write of the values
                              the same loop writes in the first partition's slab (a
-                             duplicated loop) */
-    JACC_OP_JOIN = 12     /* all streams joined: every later op is ordered after every
+                             duplicated loop), 5 = write of invalid values (POISON) */
+    JACC_OP_JOIN = 12,    /* all streams joined: every later op is ordered after every
                              earlier op (around graph launches and timed runs) */
+    JACC_OP_POISON = 13   /* stale rows [lo,hi) of slab dst of array filled with NaN bytes
+                             on stream (JACC_INIT_POISON) */
 };
 
 typedef struct {

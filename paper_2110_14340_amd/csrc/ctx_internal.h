@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 
+#include <map>
+#include <vector>
+
 #include "jacc.h"
 
 namespace jr {
@@ -27,4 +30,12 @@ void attach_model(jacc_ctx *c, void *model, void (*release_model)(void *));
 // configuration the attached model picks for a stencil loop run eagerly on
 // its arrays' K partitions (fills cfg, returns true), or false
 bool model_config(jacc_ctx *c, int kind, const int64_t *extent, int ndim, int K, jacc_config *cfg);
+// JACC_TUNE=exhaustive: the context's tuned picks per loop signature, the
+// timing database path (empty: none), and the configuration jacc_tune finds
+// best among the non-persistent candidates for a stencil loop call at its
+// arrays' K (tuned on first sight, outside batches; fills cfg, returns true)
+std::map<std::vector<int64_t>, jacc_config> &tuned_picks(jacc_ctx *c);
+const char *tune_db(const jacc_ctx *c);
+bool tuned_config(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc_arg *args,
+                  const double *scalars, int nscalars, jacc_config *cfg);
 }  // namespace jr

@@ -139,6 +139,10 @@ hipError_t launch_spmv_banded(const Launch &L, const BandBufs &bb, hipStream_t s
 hipError_t launch_scatter(const Launch &L, hipStream_t s);
 hipError_t launch_chain(const Launch &L, hipStream_t s);
 
+// Fills `height` lines of `width_bytes` bytes, `pitch_bytes` apart from
+// `base`, with 0xFF bytes (k_fill.hip; all three multiples of 4).
+hipError_t launch_poison(void *base, size_t pitch_bytes, size_t width_bytes, int64_t height, hipStream_t s);
+
 // ---- learned cost model (k_mlp.hip) ----------------------------------------
 constexpr int kMlpHidden = 64;
 constexpr int kMlpMaxFeatures = 16;

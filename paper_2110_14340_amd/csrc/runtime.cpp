@@ -16,6 +16,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
@@ -193,6 +195,10 @@ struct Access {
 struct Slab {
     void *dev = nullptr;
     Range rows;
+    // storage: rows [base, ...) from dev; a column slab (arrays split along
+    // dim 1) starts at an even column and has an even pitch (elements per
+    // stored row), so that even global columns sit on 16-byte boundaries
+    int64_t base = 0, pitch = 0;
     IntervalMap<Access> acc;
 };
 
@@ -314,6 +320,11 @@ struct jacc_ctx {
     bool eager = false;      // broadcast written rows to every holder after each loop
     bool fork_capture = false;  // plan batches with every partition on its own stream (dry run only)
     bool plan_only = false;  // planning pass without device work (batch replay check)
+    bool poison = false;     // fill the rows a loop leaves stale with NaN bytes (debug)
+    bool markers = false;    // roctx ranges around the host phases of each call
+    int tune_mode = 0;       // loops without a configuration: 0 model pick, 1 defaults, 2 tuned
+    std::string tune_db;     // timing database of tune_mode 2 (empty: none)
+    std::map<std::vector<int64_t>, jacc_config> tuned;  // tune_mode 2 picks per loop signature
     jacc_allocator alloc{};
     bool use_hipmalloc = true;
     bool own_streams = false;
@@ -358,6 +369,48 @@ struct jacc_ctx {
 namespace {
 
 bool live(const jacc_ctx *c) { return !c->dry && !c->plan_only; }
+
+// roctx ranges (JACC_INIT_MARKERS): the marker library is opened on first
+// use, so contexts without markers never load it.
+struct RoctxApi {
+    int (*push)(const char *) = nullptr;
+    int (*pop)() = nullptr;
+    bool ok = false;
+};
+const RoctxApi &roctx_api() {
+    static const RoctxApi api = [] {
+        RoctxApi a;
+        void *h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_GLOBAL);
+        if (!h) return a;
+        a.push = (int (*)(const char *))dlsym(h, "roctxRangePushA");
+        a.pop = (int (*)())dlsym(h, "roctxRangePop");
+        a.ok = a.push && a.pop;
+        return a;
+    }();
+    return api;
+}
+// A named host range for the lifetime of the object.
+class Marker {
+  public:
+    Marker(const jacc_ctx *c, const char *fmt, ...) {
+        if (!c || !c->markers || !roctx_api().ok) return;
+        char buf[96];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        roctx_api().push(buf);
+        on_ = true;
+    }
+    ~Marker() {
+        if (on_) roctx_api().pop();
+    }
+    Marker(const Marker &) = delete;
+    Marker &operator=(const Marker &) = delete;
+
+  private:
+    bool on_ = false;
+};
 
 int set_err(jacc_ctx *c, int code, const char *fmt, ...) {
     char buf[512];
@@ -589,7 +642,7 @@ int move_rows(jacc_ctx *c, Array *A, int dir, int q, int p, Range r, int s) {
     const hipMemcpyKind kind =
         dir == 1 ? hipMemcpyHostToDevice : dir == 2 ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     const size_t unit = A->pdim == 0 ? A->row_bytes : A->esize;  // bytes of a row within one line
-    auto slab_ptr = [&](int pp) { return (char *)A->slabs[pp].dev + (size_t)(r.lo - A->slabs[pp].rows.lo) * unit; };
+    auto slab_ptr = [&](int pp) { return (char *)A->slabs[pp].dev + (size_t)(r.lo - A->slabs[pp].base) * unit; };
     char *host = (char *)A->host + (size_t)r.lo * unit;
     char *src = dir == 1 ? host : slab_ptr(q);
     char *dst = dir == 2 ? host : slab_ptr(p);
@@ -597,7 +650,7 @@ int move_rows(jacc_ctx *c, Array *A, int dir, int q, int p, Range r, int s) {
         HIPCHK(c, hipMemcpyAsync(dst, src, (size_t)(r.hi - r.lo) * unit, kind, c->st[s].s), "hipMemcpyAsync");
     } else {
         const size_t host_pitch = (size_t)A->d.extent[1] * A->esize;
-        auto pitch = [&](int pp) { return (size_t)(A->slabs[pp].rows.hi - A->slabs[pp].rows.lo) * A->esize; };
+        auto pitch = [&](int pp) { return (size_t)A->slabs[pp].pitch * A->esize; };
         const size_t spitch = dir == 1 ? host_pitch : pitch(q);
         const size_t dpitch = dir == 2 ? host_pitch : pitch(p);
         HIPCHK(c, hipMemcpy2DAsync(dst, dpitch, src, spitch, (size_t)(r.hi - r.lo) * A->esize, (size_t)A->d.extent[0],
@@ -620,6 +673,27 @@ int issue_copy(jacc_ctx *c, Array *A, int q, int p, Range r, int s) {
     if (rc) return rc;
     c->st[s].seq++;
     trace(c, JACC_OP_COPY, s, A->id, q, p, 0, r.lo, r.hi, c->st[s].seq);
+    return post_op(c);
+}
+
+// Fills stale rows r of slab p with NaN bytes on stream s, ordered like a
+// write to them (JACC_INIT_POISON); the rows stay stale.
+int poison_rows(jacc_ctx *c, Array *A, int p, Range r, int s) {
+    if (r.empty()) return JACC_OK;
+    int rc = hazard(c, A, p, r, true, s, 5);
+    if (rc) return rc;
+    if (live(c)) {
+        const Slab &S = A->slabs[p];
+        const size_t unit = A->pdim == 0 ? A->row_bytes : A->esize;
+        char *at = (char *)S.dev + (size_t)(r.lo - S.base) * unit;
+        const size_t width = (size_t)(r.hi - r.lo) * unit;
+        HIPCHK(c,
+               A->pdim == 0 ? jk::launch_poison(at, width, width, 1, c->st[s].s)
+                            : jk::launch_poison(at, (size_t)S.pitch * A->esize, width, A->d.extent[0], c->st[s].s),
+               "poison fill");
+    }
+    c->st[s].seq++;
+    trace(c, JACC_OP_POISON, s, A->id, -1, p, 0, r.lo, r.hi, c->st[s].seq);
     return post_op(c);
 }
 
@@ -1054,14 +1128,8 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
         L.part_rows = std::max(L.part_rows, pd == 0 ? pp.iters.hi - pp.iters.lo
                                                     : (pp.iters.empty() ? 0 : b->hi[0] - b->lo[0]));
     if (cfg) cf = {cfg->bx, cfg->by, cfg->tile, cfg->vec, cfg->persistent, cfg->order, cfg->march, cfg->rows};
-    if (pd != 0) {
-        // a column slab's width decides the alignment of its rows: single
-        // lanes per column, eager launches only
-        if (cf.vec > 1) return set_err(c, JACC_ERR_INVALID, "arrays split along dimension 1 take vec 1");
-        if (cf.persistent)
-            return set_err(c, JACC_ERR_UNSUPPORTED, "persistent execution of arrays split along dimension 1");
-        cf.vec = 1;
-    }
+    if (pd != 0 && cf.persistent)
+        return set_err(c, JACC_ERR_UNSUPPORTED, "persistent execution of arrays split along dimension 1");
     L.cfg = jk::default_config(kind, L, cf);
     if (kind == JACC_LOOP_SPMV_CSR && !cf.order && !c->cur && arr[3]->E >= kBandedMinCols) {
         // x far larger than an XCD's L2: the column-banded form, one band
@@ -1143,14 +1211,20 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
               int nscalars, int slot, double *red_host, const jacc_config *cfg) {
     const bool want_red = slot >= 0 || red_host;
     jacc_config picked;
-    if (!cfg && c->model && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) && nargs == 2 && args) {
+    if (!cfg && c->tune_mode != 1 && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) && nargs == 2 &&
+        args) {
         // no configuration given: the attached cost model's pick for this
-        // loop on its arrays' partitions (cached per loop signature; arrays
-        // split along dimension 1 keep the defaults)
+        // loop on its arrays' partitions, or (JACC_TUNE=exhaustive) the
+        // tuner's, each cached per loop signature; arrays split along
+        // dimension 1 keep the defaults
         Array *W = lookup(c, args[1].host);
-        if (W && W->host == (uintptr_t)args[1].host && W->pdim == 0 &&
-            jr::model_config(c, kind, W->d.extent, W->d.ndim, W->K, &picked))
-            cfg = &picked;
+        if (W && W->host == (uintptr_t)args[1].host && W->pdim == 0) {
+            if (c->tune_mode == 2) {
+                if (jr::tuned_config(c, kind, b, nargs, args, scalars, nscalars, &picked)) cfg = &picked;
+            } else if (c->model && jr::model_config(c, kind, W->d.extent, W->d.ndim, W->K, &picked)) {
+                cfg = &picked;
+            }
+        }
     }
     if (slot >= kSlots) return set_err(c, JACC_ERR_INVALID, "reduction slot %d out of range", slot);
     if (red_host && c->cur) return set_err(c, JACC_ERR_INVALID, "a synchronous reduction inside a batch");
@@ -1159,8 +1233,13 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     std::vector<PartPlan> plan;
     int primary = -1;
     bool dup = false;
-    int rc = prepare_loop(c, kind, b, nargs, args, scalars, nscalars, want_red, cfg, arr, L, plan, &primary, &dup);
+    int rc;
+    {
+        Marker mk(c, "jacc plan kind=%d", kind);
+        rc = prepare_loop(c, kind, b, nargs, args, scalars, nscalars, want_red, cfg, arr, L, plan, &primary, &dup);
+    }
     if (rc) return rc;
+    Marker mk_issue(c, "jacc issue kind=%d K=%d", kind, arr[0]->K);
     const bool persistent = L.cfg.persistent != 0;
     // a pending persistent group is launched before anything that touches
     // its arrays, and before any non-persistent loop
@@ -1309,10 +1388,10 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             const Slab &sl = arr[i]->slabs[p];
             const bool cols = arr[i]->pdim != 0;
             const size_t unit = cols ? arr[i]->esize : arr[i]->row_bytes;
-            LP.a[i].ptr = (const char *)sl.dev - (intptr_t)((size_t)sl.rows.lo * unit);
+            LP.a[i].ptr = (const char *)sl.dev - (intptr_t)((size_t)sl.base * unit);
             LP.a[i].slab_lo = sl.rows.lo;
             LP.a[i].slab_hi = sl.rows.hi;
-            LP.a[i].row_elems = cols ? sl.rows.hi - sl.rows.lo : arr[i]->row_elems;
+            LP.a[i].row_elems = cols ? sl.pitch : arr[i]->row_elems;
         }
         if (args[primary].mode & JACC_FILTERED) {
             LP.own_lo = pp.rng[primary].lo;
@@ -1452,7 +1531,28 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             }
         }
     }
+    // debug: rows of floating-point slabs this loop left stale are filled
+    // with NaN, so a read that skipped its pull shows in the results
+    if (c->poison && !persistent && !dup) {
+        Marker mk(c, "jacc poison");
+        for (int i = 0; i < nargs; ++i) {
+            Array *A = arr[i];
+            if (!(args[i].mode & JACC_WRITE) || (A->d.dtype != JACC_F64 && A->d.dtype != JACC_F32)) continue;
+            for (int p = 0; p < K; ++p) {
+                if (plan[p].iters.empty()) continue;
+                for (int q = 0; q < K; ++q) {
+                    const Range x = isect(plan[p].rng[i], A->slabs[q].rows);
+                    if (x.empty()) continue;
+                    for (const Range &m : A->valid[q].missing(x)) {
+                        rc = poison_rows(c, A, q, m, stream_for(q));
+                        if (rc) return rc;
+                    }
+                }
+            }
+        }
+    }
     if (want_red) {
+        Marker mk(c, "jacc combine slot=%d", red_slot);
         const int s0 = one_stream ? 0 : base % ns;
         for (int s : red_streams) {
             rc = ensure_wait(c, s0, s, c->st[s].seq);
@@ -1566,9 +1666,47 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
     g_init_err.clear();
     if (!out) return JACC_ERR_INVALID;
     *out = nullptr;
+    // environment defaults; the caller's flags win
+    auto env_on = [](const char *name) {
+        const char *v = getenv(name);
+        return v && *v && strcmp(v, "0") != 0;
+    };
+    if (K == 0) {
+        const char *v = getenv("JACC_K");
+        char *end = nullptr;
+        const long k = (v && *v) ? strtol(v, &end, 10) : 0;
+        if (!v || !*v || *end || k < 1 || k > kMaxK) {
+            g_init_err = "K = 0 takes JACC_K, which must be an integer in [1, 64]";
+            return JACC_ERR_INVALID;
+        }
+        K = (int)k;
+    }
     if (K < 1 || K > kMaxK) {
         g_init_err = "K must lie in [1, 64]";
         return JACC_ERR_INVALID;
+    }
+    if (env_on("JACC_SERIALIZE")) flags |= JACC_INIT_SERIALIZE;
+    if (env_on("JACC_TRACE")) flags |= JACC_INIT_TRACE;
+    if (env_on("JACC_DEBUG_POISON")) flags |= JACC_INIT_POISON;
+    if (env_on("JACC_ROCTX")) flags |= JACC_INIT_MARKERS;
+    if (const char *v = getenv("JACC_COHERENCE")) {
+        const bool lz = !strcmp(v, "lazy"), eg = !strcmp(v, "eager");
+        if (!lz && !eg && strcmp(v, "mirror") != 0) {
+            g_init_err = "JACC_COHERENCE must be mirror, lazy or eager";
+            return JACC_ERR_INVALID;
+        }
+        if (!(flags & (JACC_INIT_LAZY | JACC_INIT_EAGER))) flags |= lz ? JACC_INIT_LAZY : eg ? JACC_INIT_EAGER : 0u;
+    }
+    int tune_mode = 0;
+    if (const char *v = getenv("JACC_TUNE")) {
+        if (!strcmp(v, "off"))
+            tune_mode = 1;
+        else if (!strcmp(v, "exhaustive"))
+            tune_mode = 2;
+        else if (strcmp(v, "model") != 0) {
+            g_init_err = "JACC_TUNE must be model, off or exhaustive";
+            return JACC_ERR_INVALID;
+        }
     }
     if (alloc && (!alloc->alloc || !alloc->free)) {
         g_init_err = "allocator without alloc/free";
@@ -1595,6 +1733,10 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
         c->no_split = (flags & JACC_INIT_NO_SPLIT) != 0;
         c->eager = (flags & JACC_INIT_EAGER) != 0;
         c->fork_capture = (flags & JACC_INIT_FORK_CAPTURE) != 0;
+        c->poison = (flags & JACC_INIT_POISON) != 0;
+        c->markers = (flags & JACC_INIT_MARKERS) != 0;
+        c->tune_mode = tune_mode;
+        if (const char *db = getenv("JACC_TUNE_DB")) c->tune_db = db;
         if (alloc) {
             c->alloc = *alloc;
             c->use_hipmalloc = false;
@@ -1648,6 +1790,10 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
             jacc_finalize(c);
             return rc;
         }
+        // a model file named by the environment: attached when it loads
+        // (a file that does not leaves its reason in jacc_last_error)
+        const char *mp = getenv("JACC_MODEL_PATH");
+        if (mp && *mp && !c->dry) (void)jacc_model_load(c, mp);
     } catch (const std::bad_alloc &) {
         delete c;
         g_init_err = "host allocation failed";
@@ -1716,6 +1862,7 @@ int jacc_finalize(jacc_ctx *c) {
 
 int jacc_data_enter(jacc_ctx *c, void *host, const jacc_array_desc *d, int clause) {
     GUARD(c);
+    Marker mk(c, "jacc enter");
     try {
         if (c->cur) return set_err(c, JACC_ERR_INVALID, "data regions cannot change inside a batch");
         if (!host || !d) return set_err(c, JACC_ERR_INVALID, "NULL host pointer or descriptor");
@@ -1779,10 +1926,15 @@ int jacc_data_enter(jacc_ctx *c, void *host, const jacc_array_desc *d, int claus
                 Range bl = A->block(p);
                 sl = {std::max<int64_t>(0, bl.lo - d->halo_lo), std::min<int64_t>(A->E, bl.hi + d->halo_hi)};
             }
-            A->slabs[p].rows = sl;
-            A->slabs[p].acc.init(sl.lo, sl.hi, Access{});
+            Slab &S = A->slabs[p];
+            S.rows = sl;
+            S.base = A->pdim == 0 ? sl.lo : (sl.lo & ~(int64_t)1);
+            S.pitch = A->pdim == 0 ? A->row_elems : ((sl.hi - S.base + 1) & ~(int64_t)1);
+            S.acc.init(sl.lo, sl.hi, Access{});
             A->valid[p].add(sl);
-            rc = dev_alloc(c, (size_t)(sl.hi - sl.lo) * A->row_bytes, &A->slabs[p].dev);
+            const size_t stored = A->pdim == 0 ? (size_t)(sl.hi - sl.lo) * A->row_bytes
+                                               : (size_t)S.pitch * (size_t)d->extent[0] * A->esize;
+            rc = dev_alloc(c, stored, &S.dev);
             if (!rc) trace(c, JACC_OP_ALLOC, -1, A->id, -1, p, 0, sl.lo, sl.hi, 0);
         }
         if (rc) {
@@ -1807,6 +1959,7 @@ int jacc_data_enter(jacc_ctx *c, void *host, const jacc_array_desc *d, int claus
 
 int jacc_data_exit(jacc_ctx *c, void *host, int clause) {
     GUARD(c);
+    Marker mk(c, "jacc exit");
     try {
         if (c->cur) return set_err(c, JACC_ERR_INVALID, "data regions cannot change inside a batch");
         if (clause != JACC_COPYOUT && clause != JACC_DELETE) return set_err(c, JACC_ERR_INVALID, "bad clause %d", clause);
@@ -1832,6 +1985,7 @@ int jacc_data_exit(jacc_ctx *c, void *host, int clause) {
 
 int jacc_update(jacc_ctx *c, void *host, int dir, int64_t row_lo, int64_t row_hi) {
     GUARD(c);
+    Marker mk(c, "jacc update dir=%d", dir);
     try {
         if (c->cur) return set_err(c, JACC_ERR_INVALID, "updates cannot run inside a batch");
         Array *A = lookup(c, host);
@@ -1872,6 +2026,7 @@ int jacc_parallel_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, c
 
 int jacc_wait(jacc_ctx *c) {
     GUARD(c);
+    Marker mk(c, "jacc wait");
     if (c->cur) return set_err(c, JACC_ERR_INVALID, "jacc_wait inside a batch");
     return sync_all(c);
 }
@@ -1909,6 +2064,7 @@ int jacc_reduction_read(jacc_ctx *c, int first, int count, double *out) {
 
 int jacc_batch_begin(jacc_ctx *c) {
     GUARD(c);
+    Marker mk(c, "jacc batch begin");
     if (c->cur) return set_err(c, JACC_ERR_INVALID, "a batch is already open");
     Batch *B = new Batch();
     int rc = dev_alloc(c, kTaskCapacity * sizeof(jk::PTask), (void **)&B->dev_tasks);
@@ -1937,6 +2093,7 @@ int jacc_batch_begin(jacc_ctx *c) {
 
 int jacc_batch_end(jacc_ctx *c, int *graph_id) {
     GUARD(c);
+    Marker mk(c, "jacc batch end");
     if (!c->cur) return set_err(c, JACC_ERR_INVALID, "no open batch");
     if (!graph_id) return set_err(c, JACC_ERR_INVALID, "NULL graph id");
     Batch *B = c->cur;
@@ -1981,6 +2138,7 @@ int jacc_batch_end(jacc_ctx *c, int *graph_id) {
 
 int jacc_batch_launch(jacc_ctx *c, int graph_id, int repeats) {
     GUARD(c);
+    Marker mk(c, "jacc batch launch graph=%d x%d", graph_id, repeats);
     if (c->cur) return set_err(c, JACC_ERR_INVALID, "batch launch inside an open batch");
     if (graph_id < 0 || graph_id >= (int)c->batches.size() || !c->batches[graph_id])
         return set_err(c, JACC_ERR_INVALID, "unknown graph %d", graph_id);
@@ -2196,6 +2354,8 @@ int array_info(jacc_ctx *c, const void *host, jacc_array_desc *d, size_t *bytes,
 }
 void set_thread_error(const char *msg) { g_init_err = msg ? msg : ""; }
 void *attached_model(const jacc_ctx *c) { return c->model; }
+std::map<std::vector<int64_t>, jacc_config> &tuned_picks(jacc_ctx *c) { return c->tuned; }
+const char *tune_db(const jacc_ctx *c) { return c->tune_db.c_str(); }
 void attach_model(jacc_ctx *c, void *model, void (*release_model)(void *)) {
     if (c->model && c->model_release) c->model_release(c->model);
     c->model = model;

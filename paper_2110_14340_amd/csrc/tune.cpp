@@ -531,6 +531,45 @@ bool model_config(jacc_ctx *c, int kind, const int64_t *extent, int ndim, int K,
     *cfg = best.cfg;
     return true;
 }
+
+bool tuned_config(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc_arg *args,
+                  const double *scalars, int nscalars, jacc_config *cfg) {
+    int64_t e[3];
+    int ndim = 0, K = 1;
+    if (!b || loop_shape(c, kind, nargs, args, e, &ndim, &K) != JACC_OK) return false;
+    std::vector<int64_t> sig = {kind, K};
+    sig.insert(sig.end(), e, e + ndim);
+    for (int d = 0; d < b->ndim && d < 3; ++d) {
+        sig.push_back(b->lo[d]);
+        sig.push_back(b->hi[d]);
+    }
+    auto &picks = tuned_picks(c);
+    auto it = picks.find(sig);
+    if (it != picks.end()) {
+        *cfg = it->second;
+        return true;
+    }
+    if (in_batch(c) || failed(c) || dry(c)) return false;
+    const std::vector<jacc_candidate> cands = enumerate(kind, e, ndim, &K, 1);
+    if (cands.empty()) return false;
+    std::vector<double> med(cands.size());
+    jacc_tune_opts o{};
+    const char *db = tune_db(c);
+    o.db_path = (db && *db) ? db : nullptr;
+    jacc_candidate best;
+    int n = 0;
+    if (jacc_tune(c, kind, b, nargs, args, scalars, nscalars, &o, &best, med.data(), (int)med.size(), &n) != JACC_OK)
+        return false;
+    // the smallest median among candidates that run outside a batch
+    // (persistent ones need one), ties to the lowest index
+    int bi = -1;
+    for (int i = 0; i < n && i < (int)med.size(); ++i)
+        if (!cands[(size_t)i].cfg.persistent && (bi < 0 || med[(size_t)i] < med[(size_t)bi])) bi = i;
+    if (bi < 0) return false;
+    picks[sig] = cands[(size_t)bi].cfg;
+    *cfg = cands[(size_t)bi].cfg;
+    return true;
+}
 }  // namespace jr
 
 extern "C" {

@@ -9,7 +9,8 @@ written) that calibrates the HBM byte counters:
   rocprofv3 --kernel-trace --stats -d <dir> -- python3 -m paper_2110_14340_amd.profile_driver jacobi
 
 Workloads: jacobi (8192^2), heat (512^3 with the residual), sum (512^3),
-gemm (4096^3), spmv (2^22 rows).
+gemm (4096^3), spmv (2^22 rows), jacobi_k4 (8192^2 on 4 partitions with
+roctx ranges around the runtime's host phases, for --marker-trace).
 """
 import sys
 
@@ -35,6 +36,17 @@ def main(which="jacobi", launches=20, cfg=None):
             for t in range(launches):
                 c.jacobi2d(a, b) if t % 2 == 0 else c.jacobi2d(b, a)
             c.wait()
+    elif which == "jacobi_k4":
+        n = 8192
+        u0 = inputs.jacobi_grid(n, n, seed=1)
+        a, b = u0.copy(), u0.copy()
+        with jacc.Context(4, flags=jacc.INIT_MARKERS) as c:
+            c.enter(a, halo=(1, 1))
+            c.enter(b, halo=(1, 1))
+            for t in range(launches):
+                c.jacobi2d(a, b) if t % 2 == 0 else c.jacobi2d(b, a)
+            c.wait()
+            c.update(a, jacc.UPDATE_HOST)
     elif which == "heat":
         n = 512
         u0 = inputs.heat_field(n, n, n, seed=2)

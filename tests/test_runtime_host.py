@@ -805,7 +805,10 @@ def test_column_split_refusals():
     c.enter(b_rows, halo=(1, 1))
     assert c.jacobi2d(a2, b_rows, raw=True) == jacc.ERR_UNSUPPORTED and "dimensions" in c.last_error()
     assert c.sum(a2, raw=True) == jacc.ERR_UNSUPPORTED
-    assert c.jacobi2d(a2, b2, cfg=jacc.config(vec=2), raw=True) == jacc.ERR_INVALID
+    odd_a, odd_b = np.zeros((10, 41)), np.zeros((10, 41))
+    c.enter(odd_a, halo=(1, 1), part_dim=1)
+    c.enter(odd_b, halo=(1, 1), part_dim=1)
+    assert c.jacobi2d(odd_a, odd_b, cfg=jacc.config(vec=2), raw=True) == jacc.ERR_INVALID  # odd row length
     c.batch_begin()
     assert c.jacobi2d(a2, b2, cfg=jacc.config(persistent=1), raw=True) == jacc.ERR_UNSUPPORTED
     c.close()
@@ -829,4 +832,106 @@ def test_column_split_update_ranges_index_columns():
     covered = sorted((lo, hi) for _, lo, hi in d2h)
     assert covered[0][0] <= 1 and covered[-1][1] >= 29
     assert c.update(b, jacc.UPDATE_HOST, 0, 31, raw=True) == jacc.ERR_INVALID
+    c.close()
+
+
+# ------------------------------------------------------------------ debug poison, environment
+@pytest.mark.parametrize("mode", ["lazy", "mirror", "eager"])
+@pytest.mark.parametrize("part_dim", [0, 1])
+def test_poison_fills_exactly_the_rows_left_stale(mode, part_dim):
+    """JACC_INIT_POISON: after each sweep, the halo rows the sweep left stale
+    in the neighbours' slabs are filled with NaN (one fill per boundary side
+    under lazy pulls; none when mirror stores or eager copies refresh them),
+    each fill ordered like a write, and the next sweep pulls over them
+    before reading: the traces stay race-free and fresh."""
+    K = 4
+    flags = DRY | jacc.INIT_POISON | {"lazy": jacc.INIT_LAZY, "mirror": 0, "eager": jacc.INIT_EAGER}[mode]
+    c = jacc.Context(K, flags=flags)
+    shape = (66, 20) if part_dim == 0 else (20, 66)
+    a = np.zeros(shape)
+    b = np.zeros(shape)
+    c.enter(a, halo=(1, 1), part_dim=part_dim)
+    c.enter(b, halo=(1, 1), part_dim=part_dim)
+    c.trace_clear()
+    src, dst = a, b
+    per_sweep = []
+    for _ in range(3):
+        tr = _loop_trace(c, lambda: c.jacobi2d(src, dst))
+        per_sweep.append(tr)
+        src, dst = dst, src
+    full = [t for tr in per_sweep for t in tr]
+    fills = [[t for t in tr if t["op"] == "POISON"] for tr in per_sweep]
+    # the written array of each sweep: b (id 1), a (0), b (1)
+    want = 2 * (K - 1) if (mode == "lazy" or (mode == "mirror" and part_dim == 1)) else 0
+    assert [len(f) for f in fills] == [want] * 3
+    for f, arr_id in zip(fills, (1, 0, 1)):
+        assert all(t["array"] == arr_id and t["hi"] - t["lo"] == 1 for t in f)
+    if want:
+        # every poisoned halo row is pulled before the next sweep reads it
+        pulls = {(t["dst"], t["lo"]) for t in per_sweep[1] if t["op"] == "COPY"}
+        assert {(t["dst"], t["lo"]) for t in fills[0]} == pulls
+    assert race_check(full) == [] and freshness_check(full) == []
+    c.close()
+
+
+def _env_ctx(monkeypatch, env, K=0, flags=DRY):
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    h = ctypes.c_void_p()
+    st = jacc.lib().jacc_init(ctypes.byref(h), K, None, None, flags)
+    return st, h
+
+
+def test_environment_configures_contexts(monkeypatch):
+    lib = jacc.lib()
+    # JACC_K: K = 0 takes it
+    st, h = _env_ctx(monkeypatch, {"JACC_K": "3", "JACC_TRACE": "1"})
+    assert st == jacc.OK
+    a = np.zeros((30, 8))
+    d = jacc.ArrayDesc()
+    d.dtype, d.ndim = 0, 2
+    d.extent[0], d.extent[1] = 30, 8
+    assert lib.jacc_data_enter(h, a.ctypes.data_as(ctypes.c_void_p), ctypes.byref(d), jacc.COPYIN) == jacc.OK
+    dev, lo, hi = ctypes.c_void_p(), ctypes.c_int64(), ctypes.c_int64()
+    assert lib.jacc_slab_info(h, a.ctypes.data_as(ctypes.c_void_p), 2, ctypes.byref(dev), ctypes.byref(lo),
+                              ctypes.byref(hi)) == jacc.OK and (lo.value, hi.value) == (20, 30)
+    assert lib.jacc_slab_info(h, a.ctypes.data_as(ctypes.c_void_p), 3, None, None, None) == jacc.ERR_INVALID
+    assert lib.jacc_trace_len(h) > 0  # JACC_TRACE=1 recorded the enter without the flag
+    lib.jacc_finalize(h)
+    # malformed values are refused with a reason
+    for env in ({"JACC_K": "0"}, {"JACC_K": "65"}, {"JACC_K": "4x"}):
+        st, _ = _env_ctx(monkeypatch, env)
+        assert st == jacc.ERR_INVALID and "JACC_K" in lib.jacc_last_error(None).decode()
+    monkeypatch.setenv("JACC_K", "2")
+    for name, bad in (("JACC_TUNE", "fast"), ("JACC_COHERENCE", "sometimes")):
+        st, _ = _env_ctx(monkeypatch, {name: bad}, K=2)
+        assert st == jacc.ERR_INVALID and name in lib.jacc_last_error(None).decode()
+        monkeypatch.delenv(name)
+
+
+@pytest.mark.parametrize("env,flags,copies", [
+    ({"JACC_COHERENCE": "lazy"}, 0, 2 * 3), ({"JACC_COHERENCE": "eager"}, 0, 4 * 3),
+    ({"JACC_COHERENCE": "mirror"}, 0, 0), ({"JACC_COHERENCE": "lazy"}, jacc.INIT_EAGER, 4 * 3),
+    ({"JACC_DEBUG_POISON": "1", "JACC_COHERENCE": "lazy"}, 0, 2 * 3),
+    ({"JACC_SERIALIZE": "1"}, 0, 0),
+])
+def test_environment_flags_reach_the_planner(monkeypatch, env, flags, copies):
+    """Coherence, serialisation and poison chosen through the environment
+    plan like the corresponding flags; a flag the caller passes wins."""
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    c = jacc.Context(4, flags=DRY | flags)
+    a = np.zeros((66, 20))
+    b = np.zeros((66, 20))
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    c.trace_clear()
+    c.jacobi2d(a, b)
+    c.jacobi2d(b, a)
+    ops = c.trace()
+    assert len([t for t in ops if t["op"] == "COPY"]) == copies
+    assert bool([t for t in ops if t["op"] == "POISON"]) == ("JACC_DEBUG_POISON" in env)
+    if "JACC_SERIALIZE" in env:
+        assert {t["stream"] for t in ops if t["op"] == "KERNEL"} == {0}
+    assert race_check(ops) == [] and freshness_check(ops) == []
     c.close()

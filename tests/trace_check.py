@@ -11,11 +11,11 @@
   to that row of the array (by any partition or the host).  A private write
   (a filtered loop's write outside the partition's owner block) leaves a
   value that is never the latest; a duplicated loop's later partitions write
-  the value its first partition wrote.
+  the value its first partition wrote; a POISON fill leaves invalid values.
 """
 from collections import defaultdict
 
-OPS_WITH_SEQ = {"COPY", "KERNEL", "H2D", "D2H", "COMBINE"}
+OPS_WITH_SEQ = {"COPY", "KERNEL", "H2D", "D2H", "COMBINE", "POISON"}
 
 
 def _max(a, b):
@@ -56,7 +56,7 @@ def race_check(trace, skip_wait=None):
             vc[d] = dict(v)
             op_vc[(d, n)] = dict(v)
             for a in pending.pop((d, n), []):
-                mode = "w" if a["kind"] in (2, 3, 4) else "r"
+                mode = "w" if a["kind"] in (2, 3, 4, 5) else "r"
                 for row in range(a["lo"], a["hi"]):
                     key = (a["array"], a["dst"], row)
                     for (ps, pn, pm) in hist[key]:
@@ -126,6 +126,10 @@ def freshness_check(trace):
                             written[key] = new_version()
                         logical[key] = written[key]
                         stored[(a["array"], a["dst"], row)] = written[key]
+        elif op == "POISON":
+            for row in range(t["lo"], t["hi"]):
+                stored[(t["array"], t["dst"], row)] = ("poison", new_version())
+            pending.pop((t["stream"], t["seq"]), None)
         elif op == "D2H":
             for row in range(t["lo"], t["hi"]):
                 want = logical.get((t["array"], row))
