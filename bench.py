@@ -292,19 +292,21 @@ def main():
         log(f"jacobi K={K}: warmup {args.warmup}, timed {args.steps}")
         wall, ev = run_jacobi(jacc, torch, u0, K, args.steps, args.warmup)
         per_k[K] = {"ms_per_step": round(wall / args.steps * 1e3, 5),
-                    "gbps": round(step_bytes * args.steps / wall / 1e9, 1)}
+                    "gbps": round(step_bytes * args.steps / wall / 1e9, 1),
+                    "event_us_per_step": round(ev / args.steps * 1e6, 2)}
         if K == 1:
             ev_k1 = ev
-    # the other coherence and issue modes, at the partitioned K's: halo rows
-    # pulled by copies before each read (lazy) instead of written through by
-    # the producing kernels; one launch per partition (the default splits
-    # 2-4 partitions into own-block rows first and edge rows after); split
-    # forced at every K
+    # the other issue and coherence modes, at the partitioned K's: a launch
+    # per partition on its own stream instead of one packed launch (with
+    # 2-4 partitions split into own-block rows first and edge rows after, or
+    # unsplit); halo rows pulled by copies before each read (lazy) instead of
+    # written through by the producing kernels; split forced at every K
     modes = {}
     for K in ks:
         if K == 1:
             continue
-        for name, fl in (("lazy_pull", jacc.INIT_LAZY), ("no_split", jacc.INIT_NO_SPLIT), ("split", jacc.INIT_SPLIT)):
+        for name, fl in (("streams", jacc.INIT_NO_PACK), ("lazy_pull", jacc.INIT_LAZY),
+                         ("streams_no_split", jacc.INIT_NO_PACK | jacc.INIT_NO_SPLIT), ("split", jacc.INIT_SPLIT)):
             log(f"jacobi K={K} {name}")
             wall, _ = run_jacobi(jacc, torch, u0, K, args.steps, args.warmup, flags=fl)
             modes.setdefault(name, {})[str(K)] = {"ms_per_step": round(wall / args.steps * 1e3, 5),
@@ -342,7 +344,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"jacobi2d_5pt {n}x{n}, {args.steps} iterations, K={main_k} row-block "
-                               f"partitions on separate streams, 1-row halo exchange per step",
+                               f"partitions in separate slabs, 1-row halo exchange per step (mirror stores); "
+                               f"the partitions of a step run as the tasks of one launch (per_k_modes.streams: "
+                               f"a launch per partition on K streams)",
                    "grid": [n, n], "K": main_k, "iterations": args.steps, "seed": 1},
         "frac_hbm_peak": round(value / HBM_PEAK_GBS, 4),
         "per_k": {str(k): v for k, v in per_k.items()},
@@ -361,6 +365,15 @@ def main():
                               "avg_launch_us": round(avg * 1e6, 2),
                               "bytes_per_launch": int(step_bytes),
                               "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)"}
+    if main_k > 1 and main_k <= 16:
+        # the headline K's one packed launch per step (all on stream 0): its
+        # average duration from the same HIP events
+        avg = per_k[main_k]["event_us_per_step"] / 1e6
+        ach = step_bytes / avg / 1e9
+        result["roofline_packed"] = {"kernel": f"packed_kernel<true> ({main_k} partitions as tasks, one launch per step)",
+                                     "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                                     "avg_launch_us": round(avg * 1e6, 2), "bytes_per_launch": int(step_bytes)}
     if not args.no_extra:
         log("secondary workloads")
         result["extra"] = extra_workloads(jacc, torch, inputs)

@@ -274,10 +274,18 @@ enum {
                                       refreshed) are filled with 0xFF bytes (NaN) by a fill
                                       kernel ordered like a write, so a read the runtime should
                                       have preceded by a pull carries NaN into the results */
-    JACC_INIT_MARKERS = 1u << 9    /* roctx ranges around the host phases of each call (loop
+    JACC_INIT_MARKERS = 1u << 9,   /* roctx ranges around the host phases of each call (loop
                                       planning, copies and launches, combines; data enter, exit,
                                       update; batch capture and launch), for rocprofv3
                                       --marker-trace */
+    JACC_INIT_NO_PACK = 1u << 10   /* a launch per partition on its own stream for every loop.
+                                      Default: outside batches, a JACOBI2D or HEAT3D loop of 2
+                                      to 16 row-split partitions without a reduction or FILTERED
+                                      output, whose configuration is the task kernel's shape
+                                      (bx 256, by 1, order 1, rows 1), runs its partitions as the
+                                      tasks of one launch on one stream (halo pulls before it,
+                                      mirror stores inside it); JACC_INIT_SPLIT, SERIALIZE and
+                                      per-partition timing keep a launch per partition */
 };
 
 /* Create a context with K partitions (1 <= K <= 64; K = 0 takes the

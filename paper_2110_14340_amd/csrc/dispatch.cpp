@@ -18,11 +18,10 @@ Cfg default_config(int kind, const Launch &L, Cfg c) {
         case JACC_LOOP_JACOBI2D:
             if (!c.bx) c.bx = 256;
             if (!c.by) c.by = 1;
-            // measured: 4-row tiles for eager launches at every partition
-            // count (8190-column grids, K = 1..8) and for task-kernel tiles
-            // of partitions below 1024 rows (512^2), 8-row task tiles from
-            // 1024 rows (8192^2 at K = 1..8)
-            if (!c.tile) c.tile = (!c.persistent || L.part_rows < 1024) ? 4 : 8;
+            // measured: 4-row tiles for eager launches and for task-kernel
+            // tiles at every partition count (8190-column grids and 512^2,
+            // K = 1..8)
+            if (!c.tile) c.tile = 4;
             if (!c.vec) c.vec = even ? 2 : 1;
             if (!c.order) c.order = 1;
             if (!c.march) c.march = 2;

@@ -84,8 +84,9 @@ template <int VEC>
 __device__ __forceinline__ void store_out(double *out, int64_t off, int64_t r, const Mirrors &mir,
                                           const double (&o)[VEC], bool all, const bool (&comp)[VEC]) {
     store_masked<VEC>(out + off, o, all, comp);
-    for (int k = 0; k < mir.n; ++k)
-        if (r >= mir.m[k].lo && r < mir.m[k].hi) store_masked<VEC>(mir.m[k].ptr + off, o, all, comp);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)  // unrolled: each mirror pointer stays a known global address
+        if (k < mir.n && r >= mir.m[k].lo && r < mir.m[k].hi) store_masked<VEC>(mir.m[k].ptr + off, o, all, comp);
 }
 
 // March direction of the wave's tile q: with march == 2 odd tiles run toward
@@ -446,32 +447,36 @@ heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t n
 }
 
 // ---------------------------------------------------------------------------
-// Persistent kernel: a fixed grid walks the tiles of all tasks in order
-// (workgroup b takes tiles b, b + grid, b + 2*grid, ...).  JONLY: a group of
-// Jacobi tasks only; without the heat bodies the kernel needs fewer
-// registers, so more workgroups are resident at once.
+// Persistent kernel: one launch runs the tiles of every task of a group
+// (workgroup b takes tiles b, b + grid, b + 2*grid, ...; the grid normally
+// has one workgroup per tile).  JONLY: a group of Jacobi tasks only; without
+// the heat bodies the kernel needs fewer registers, so more workgroups are
+// resident at once.
 // ---------------------------------------------------------------------------
 // One tile (local index `local`) of task T.
 template <bool JONLY>
 __device__ __forceinline__ void persistent_tile(const PTask &T, int64_t local) {
     const int64_t bxi = local % T.gx;
     const int64_t rest = local / T.gx;
+    const double *in = T.in;
+    double *out = T.out;
+    const Mirrors mir = T.mir;
     if (JONLY || T.kind == JACC_LOOP_JACOBI2D) {
         if (T.vec == 2)
-            jacobi_tile<2>(T.in, T.out, T.e1, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, T.mir, bxi,
+            jacobi_tile<2>(in, out, T.e1, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, mir, bxi,
                            rest, threadIdx.x, 0, kPersistentThreads, 1);
         else
-            jacobi_tile<1>(T.in, T.out, T.e1, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, T.mir, bxi,
+            jacobi_tile<1>(in, out, T.e1, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, mir, bxi,
                            rest, threadIdx.x, 0, kPersistentThreads, 1);
     } else if constexpr (!JONLY) {
         const int64_t byi = rest % T.gy, bzi = rest / T.gy;
         if (T.vec == 2)
-            (void)heat_tile<2, false>(T.in, T.out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2], T.hi[2],
-                                      T.col0, T.tile, T.march, T.alpha, T.mir, bxi, byi, bzi, threadIdx.x, 0,
+            (void)heat_tile<2, false>(in, out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2], T.hi[2],
+                                      T.col0, T.tile, T.march, T.alpha, mir, bxi, byi, bzi, threadIdx.x, 0,
                                       kPersistentThreads, 1);
         else
-            (void)heat_tile<1, false>(T.in, T.out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2], T.hi[2],
-                                      T.col0, T.tile, T.march, T.alpha, T.mir, bxi, byi, bzi, threadIdx.x, 0,
+            (void)heat_tile<1, false>(in, out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2], T.hi[2],
+                                      T.col0, T.tile, T.march, T.alpha, mir, bxi, byi, bzi, threadIdx.x, 0,
                                       kPersistentThreads, 1);
     }
 }
@@ -479,19 +484,75 @@ __device__ __forceinline__ void persistent_tile(const PTask &T, int64_t local) {
 // Workgroup b runs tile b of the concatenated tile list of all tasks (the
 // task found by a binary search over the tasks' first tiles); with fewer
 // workgroups than tiles it would take tiles b, b + grid, ... .
+// The task table is read through the constant address space: the data
+// pointers loaded from it are then known to address global memory (as
+// kernel arguments are), so the tile bodies use global loads and stores.
+// Read as generic pointers they would become flat operations, which also
+// count against the counter the cross-lane shuffles wait on, so every
+// shuffle would wait for all the loads in flight.
+typedef const __attribute__((address_space(4))) PTask ConstTask;
+
+// Field-by-field copy (the implicit copy constructor takes a generic
+// reference).
+__device__ __forceinline__ PTask load_task(ConstTask *p) {
+    PTask T;
+    T.kind = p->kind;
+    T.vec = p->vec;
+    T.tile = p->tile;
+    T.march = p->march;
+    T.in = p->in;
+    T.out = p->out;
+    T.e1 = p->e1;
+    T.e2 = p->e2;
+    for (int d = 0; d < 3; ++d) {
+        T.lo[d] = p->lo[d];
+        T.hi[d] = p->hi[d];
+    }
+    T.col0 = p->col0;
+    T.alpha = p->alpha;
+    T.gx = p->gx;
+    T.gy = p->gy;
+    T.gz = p->gz;
+    T.ntiles = p->ntiles;
+    T.tile_begin = p->tile_begin;
+    T.mir.n = p->mir.n;
+    for (int k = 0; k < 2; ++k) {
+        T.mir.m[k].ptr = p->mir.m[k].ptr;
+        T.mir.m[k].lo = p->mir.m[k].lo;
+        T.mir.m[k].hi = p->mir.m[k].hi;
+    }
+    return T;
+}
+
 template <bool JONLY>
 __global__ void __launch_bounds__(kPersistentThreads)
 persistent_kernel(const PTask *__restrict__ tasks, int ntasks, int64_t total) {
+    ConstTask *ct = (ConstTask *)tasks;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         int lo = 0, hi = ntasks - 1;  // last task whose first tile is <= t
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (tasks[mid].tile_begin <= t)
+            if (ct[mid].tile_begin <= t)
                 lo = mid;
             else
                 hi = mid - 1;
         }
-        persistent_tile<JONLY>(tasks[lo], t - tasks[lo].tile_begin);
+        const PTask T = load_task(ct + lo);
+        persistent_tile<JONLY>(T, t - T.tile_begin);
+    }
+}
+
+// The same over a task table passed as a kernel argument (one eager loop's
+// partitions; the argument lives in the constant address space).
+template <bool JONLY>
+__global__ void __launch_bounds__(kPersistentThreads) packed_kernel(TaskPack pack, int64_t total) {
+    ConstTask *ct = (ConstTask *)&pack.t[0];
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0;  // last task whose first tile is <= t
+        for (int k = 1; k < pack.n; ++k)
+            if (ct[k].tile_begin <= t) lo = k;
+        const PTask T = load_task(ct + lo);
+        persistent_tile<JONLY>(T, t - T.tile_begin);
     }
 }
 
@@ -630,16 +691,24 @@ bool make_task(const Launch &L, PTask *t) {
     return true;
 }
 
-// Workgroups of the persistent kernel that are resident at once on the
-// current device (occupancy x compute units): a larger grid would leave a
-// second, partial generation of workgroups running after the first, with
-// part of the chip idle.  Queried once per device and kernel variant.
 // One workgroup per tile (measured: 2.5-5 % faster on 8192^2 steps than a
 // resident-sized grid walking static rounds of tiles), up to the largest
-// one-dimensional grid.
+// one-dimensional grid; beyond it workgroups take further tiles in strides
+// of the grid.
 int64_t persistent_grid(int64_t tiles, bool /*jacobi_only*/) {
     const int64_t max_grid = (int64_t)INT32_MAX;
     return tiles < max_grid ? tiles : max_grid;
+}
+
+hipError_t launch_packed(const TaskPack &pack, int64_t tiles, bool jacobi_only, hipStream_t s) {
+    if (pack.n <= 0 || tiles <= 0) return hipSuccess;
+    if (pack.n > kMaxPack) return hipErrorInvalidValue;
+    const int64_t grid = persistent_grid(tiles, jacobi_only);
+    if (jacobi_only)
+        hipLaunchKernelGGL(packed_kernel<true>, dim3((unsigned)grid), dim3(kPersistentThreads), 0, s, pack, tiles);
+    else
+        hipLaunchKernelGGL(packed_kernel<false>, dim3((unsigned)grid), dim3(kPersistentThreads), 0, s, pack, tiles);
+    return hipGetLastError();
 }
 
 hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, int64_t grid, bool jacobi_only,

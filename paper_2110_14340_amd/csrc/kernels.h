@@ -107,6 +107,16 @@ int64_t persistent_grid(int64_t tiles, bool jacobi_only);
 hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, int64_t grid, bool jacobi_only,
                              hipStream_t s);
 
+// The partitions of one eager stencil loop as tasks of one launch, the task
+// records passed as kernel arguments (at most kMaxPack; tile_begin set by
+// the caller, tiles = the sum of their ntiles).
+constexpr int kMaxPack = 16;
+struct TaskPack {
+    PTask t[kMaxPack];
+    int32_t n;
+};
+hipError_t launch_packed(const TaskPack &pack, int64_t tiles, bool jacobi_only, hipStream_t s);
+
 // Number of workgroups the loop's reduction writes partials for (for
 // sizing; <= wg_capacity is required).
 int64_t reduction_workgroups(const Launch &L);

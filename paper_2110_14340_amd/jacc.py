@@ -24,7 +24,7 @@ UPDATE_HOST, UPDATE_DEVICE = 1, 2
 READ, WRITE, READWRITE, FILTERED = 1, 2, 3, 4
 JACOBI2D, HEAT3D, SUM, GEMM, SPMV_CSR, SCATTER_SQ, PRED_CHAIN = 1, 2, 3, 4, 5, 6, 7
 INIT_DRYRUN, INIT_TRACE, INIT_SERIALIZE, INIT_LAZY, INIT_SPLIT, INIT_NO_SPLIT, INIT_EAGER = 1, 2, 4, 8, 16, 32, 64
-INIT_FORK_CAPTURE, INIT_POISON, INIT_MARKERS = 128, 256, 512
+INIT_FORK_CAPTURE, INIT_POISON, INIT_MARKERS, INIT_NO_PACK = 128, 256, 512, 1024
 OP_NAMES = {1: "ALLOC", 2: "FREE", 3: "H2D", 4: "D2H", 5: "COPY", 6: "KERNEL", 7: "RECORD", 8: "WAIT",
             9: "SYNC", 10: "COMBINE", 11: "ACCESS", 12: "JOIN", 13: "POISON"}
 STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOT_PRESENT", -3: "ALREADY_PRESENT", -4: "RANGE", -5: "ALLOC",

@@ -326,7 +326,7 @@ print(rc, rc2, rc3, c.close())
     env = dict(os.environ, JACC_FAULT_INJECT="copy:3")
     out = subprocess.run([sys.executable, "-c", code, ROOT], capture_output=True, text=True, env=env)
     assert out.stdout.split() == [str(jacc.ERR_DEVICE)] * 4, out.stderr
-    env = dict(os.environ, JACC_FAULT_INJECT="launch:6")
+    env = dict(os.environ, JACC_FAULT_INJECT="launch:2")  # the second sweep's (packed) launch
     out = subprocess.run([sys.executable, "-c", code, ROOT], capture_output=True, text=True, env=env)
     assert out.stdout.split() == [str(jacc.ERR_DEVICE)] * 4, out.stderr
 
@@ -934,4 +934,52 @@ def test_environment_flags_reach_the_planner(monkeypatch, env, flags, copies):
     if "JACC_SERIALIZE" in env:
         assert {t["stream"] for t in ops if t["op"] == "KERNEL"} == {0}
     assert race_check(ops) == [] and freshness_check(ops) == []
+    c.close()
+
+
+# ------------------------------------------------------------------ packed eager launches
+@pytest.mark.parametrize("K", [2, 8, 16])
+def test_packed_stencil_loop_is_one_launch_on_one_stream(K):
+    """Outside batches a Jacobi sweep of K partitions is one launch: every
+    partition's KERNEL entry shares one stream and one sequence number, the
+    pulls (lazy) precede it on that stream, and the plan still matches the
+    set model (same iterations and copies) and stays race-free and fresh.
+    With JACC_INIT_NO_PACK, SPLIT or an explicit non-task launch shape each
+    partition launches on its own stream."""
+    E = 8 * K + 3
+    for flags, packed in ((0, True), (jacc.INIT_LAZY, True), (jacc.INIT_NO_PACK, False),
+                          (jacc.INIT_SPLIT, False), ("shape", False)):
+        c = jacc.Context(K, flags=DRY | (flags if flags != "shape" else 0))
+        a = np.zeros((E, 20))
+        b = np.zeros((E, 20))
+        c.enter(a, halo=(1, 1))
+        c.enter(b, halo=(1, 1))
+        cfg = jacc.config(bx=64, by=2) if flags == "shape" else None
+        c.trace_clear()
+        c.jacobi2d(a, b, cfg=cfg)
+        c.jacobi2d(b, a, cfg=cfg)
+        ops = c.trace()
+        kern = [t for t in ops if t["op"] == "KERNEL"]
+        keys = {(t["stream"], t["seq"]) for t in kern}
+        if packed:
+            assert len(kern) == 2 * K and len(keys) == 2 and len({t["stream"] for t in kern}) == 1
+        else:
+            assert len(keys) >= 2 * K
+        assert race_check(ops) == [] and freshness_check(ops) == []
+        c.close()
+
+
+def test_heat_default_and_reductions_keep_a_launch_per_partition():
+    c = jacc.Context(4, flags=DRY)
+    a = np.zeros((18, 10, 66))
+    b = np.zeros((18, 10, 66))
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    c.trace_clear()
+    c.heat3d(a, b, 0.1)                       # default heat shape: several rows per wave
+    c.heat3d(b, a, 0.1, cfg=jacc.config(bx=256, by=1, rows=1, order=1))  # the task shape: packed
+    c.heat3d(a, b, 0.1, slot=0, cfg=jacc.config(bx=256, by=1, rows=1, order=1))  # a reduction: not packed
+    kern = [t for t in c.trace() if t["op"] == "KERNEL"]
+    assert [len({(t["stream"], t["seq"]) for t in kern[i:i + 4]}) for i in (0, 4, 8)] == [4, 1, 4]
+    assert race_check(c.trace()) == [] and freshness_check(c.trace()) == []
     c.close()
