@@ -280,12 +280,16 @@ enum {
                                       --marker-trace */
     JACC_INIT_NO_PACK = 1u << 10   /* a launch per partition on its own stream for every loop.
                                       Default: outside batches, a JACOBI2D or HEAT3D loop of 2
-                                      to 16 row-split partitions without a reduction or FILTERED
-                                      output, whose configuration is the task kernel's shape
-                                      (bx 256, by 1, order 1, rows 1), runs its partitions as the
-                                      tasks of one launch on one stream (halo pulls before it,
-                                      mirror stores inside it); JACC_INIT_SPLIT, SERIALIZE and
-                                      per-partition timing keep a launch per partition */
+                                      to 16 row-split partitions without a FILTERED output runs
+                                      all its partitions in one launch on one stream, each
+                                      partition's tiles a run of the workgroups, in the loop's
+                                      configuration (halo pulls before it, mirror stores inside
+                                      it; a residual's partitions finalised by one launch and
+                                      combined in partition order: the same bits as a launch per
+                                      partition); JACC_INIT_SPLIT, SERIALIZE, per-partition
+                                      timing, and residuals whose workgroup partials of all
+                                      partitions exceed the stream's buffer keep a launch per
+                                      partition */
 };
 
 /* Create a context with K partitions (1 <= K <= 64; K = 0 takes the

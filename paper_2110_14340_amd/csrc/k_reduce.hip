@@ -50,9 +50,8 @@ sum_kernel(const double *__restrict__ x, int64_t begin, int64_t n, double *__res
 constexpr int kFinThreads = 1024;
 constexpr int kFinUnroll = 8;
 
-__global__ void __launch_bounds__(kFinThreads)
-finalise_kernel(const double *__restrict__ p, int64_t n, double *__restrict__ out) {
-    __shared__ double sh[kFinThreads / kWave];
+__device__ __forceinline__ void finalise_block(const double *__restrict__ p, int64_t n, double *__restrict__ out,
+                                               double *sh) {
     double a[kFinUnroll];
 #pragma unroll
     for (int u = 0; u < kFinUnroll; ++u) a[u] = 0.0;
@@ -69,6 +68,19 @@ finalise_kernel(const double *__restrict__ p, int64_t n, double *__restrict__ ou
     const double t = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     const double s = block_sum(t, sh);
     if (threadIdx.x == 0) *out = s;
+}
+
+__global__ void __launch_bounds__(kFinThreads)
+finalise_kernel(const double *__restrict__ p, int64_t n, double *__restrict__ out) {
+    __shared__ double sh[kFinThreads / kWave];
+    finalise_block(p, n, out, sh);
+}
+
+// Workgroup k finalises segment k (the same additions as finalise_kernel).
+__global__ void __launch_bounds__(kFinThreads) finalise_many_kernel(const double *__restrict__ base, Segments seg) {
+    __shared__ double sh[kFinThreads / kWave];
+    const int k = blockIdx.x;
+    finalise_block(base + seg.off[k], seg.n[k], seg.out[k], sh);
 }
 
 __global__ void combine_kernel(const double *__restrict__ partials, CombineList list, double *__restrict__ out) {
@@ -104,6 +116,13 @@ hipError_t launch_sum(const Launch &L, hipStream_t s) {
 
 hipError_t launch_finalise(const double *partials, int64_t n, double *out, hipStream_t s) {
     hipLaunchKernelGGL(finalise_kernel, dim3(1), dim3(kFinThreads), 0, s, partials, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalise_many(const double *base, const Segments &seg, hipStream_t s) {
+    if (seg.count <= 0) return hipSuccess;
+    if (seg.count > kMaxPack) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(finalise_many_kernel, dim3((unsigned)seg.count), dim3(kFinThreads), 0, s, base, seg);
     return hipGetLastError();
 }
 

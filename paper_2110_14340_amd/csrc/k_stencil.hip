@@ -542,17 +542,96 @@ persistent_kernel(const PTask *__restrict__ tasks, int ntasks, int64_t total) {
     }
 }
 
-// The same over a task table passed as a kernel argument (one eager loop's
-// partitions; the argument lives in the constant address space).
-template <bool JONLY>
-__global__ void __launch_bounds__(kPersistentThreads) packed_kernel(TaskPack pack, int64_t total) {
-    ConstTask *ct = (ConstTask *)&pack.t[0];
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int lo = 0;  // last task whose first tile is <= t
-        for (int k = 1; k < pack.n; ++k)
-            if (ct[k].tile_begin <= t) lo = k;
-        const PTask T = load_task(ct + lo);
-        persistent_tile<JONLY>(T, t - T.tile_begin);
+// ---------------------------------------------------------------------------
+// Packed partitions: the K partitions of one eager stencil loop in one
+// launch.  Partition q's tiles take workgroups [begin, begin + span) of the
+// grid (begin and span multiples of 8, so workgroup b still runs on XCD
+// b mod 8 and the XCD-aware orders map tiles within the partition as a
+// launch of its own would); workgroups past its tile count return at once.
+// The descriptors are read through the constant address space, so their
+// pointers are known to address global memory.
+// ---------------------------------------------------------------------------
+struct PartDesc {
+    const double *in;
+    double *out;
+    int64_t lo0, hi0;     // the partition's iterations along dim 0
+    int64_t tiles, begin;  // its tile count and first workgroup
+    int64_t partial_off;   // its first workgroup partial (heat residual)
+    Mirrors mir;
+};
+struct PartPack {
+    PartDesc p[kMaxPack];
+    int32_t n;
+};
+typedef const __attribute__((address_space(4))) PartDesc ConstPart;
+
+__device__ __forceinline__ PartDesc load_part(ConstPart *p) {
+    PartDesc d;
+    d.in = p->in;
+    d.out = p->out;
+    d.lo0 = p->lo0;
+    d.hi0 = p->hi0;
+    d.tiles = p->tiles;
+    d.begin = p->begin;
+    d.partial_off = p->partial_off;
+    d.mir.n = p->mir.n;
+    for (int k = 0; k < 2; ++k) {
+        d.mir.m[k].ptr = p->mir.m[k].ptr;
+        d.mir.m[k].lo = p->mir.m[k].lo;
+        d.mir.m[k].hi = p->mir.m[k].hi;
+    }
+    return d;
+}
+
+// The partition of this workgroup and its tile within the partition (-1:
+// a padding workgroup).
+__device__ __forceinline__ int64_t part_tile(const PartPack &pk, int order, PartDesc &d) {
+    ConstPart *cp = (ConstPart *)&pk.p[0];
+    const int64_t b = blockIdx.x;
+    int q = 0;
+    for (int k = 1; k < pk.n; ++k)
+        if (cp[k].begin <= b) q = k;
+    d = load_part(cp + q);
+    const int64_t span = (q + 1 < pk.n ? cp[q + 1].begin : (int64_t)gridDim.x) - d.begin;
+    const int64_t local = b - d.begin;
+    const int64_t t = order >= 2 ? (local & 7) * (span >> 3) + (local >> 3) : local;
+    return t < d.tiles ? t : -1;
+}
+
+template <int VEC>
+__global__ void __launch_bounds__(1024)
+jacobi2d_parts_kernel(PartPack pk, int64_t nx, int64_t c_lo, int64_t c_hi, int64_t col0, int tile, int march,
+                      int64_t gx, int order) {
+    PartDesc d;
+    const int64_t t = part_tile(pk, order, d);
+    if (t < 0) return;
+    jacobi_tile<VEC>(d.in, d.out, nx, nx, d.lo0, d.hi0, c_lo, c_hi, col0, tile, march, d.mir, t % gx, t / gx,
+                     threadIdx.x, threadIdx.y, blockDim.x, blockDim.y);
+}
+
+template <int VEC, int R, bool RES>
+__global__ void __launch_bounds__(R == 1 ? 1024 : 256)
+heat3d_parts_kernel(PartPack pk, int64_t ny, int64_t nx, int64_t y_lo, int64_t y_hi, int64_t x_lo, int64_t x_hi,
+                    int64_t col0, int tile, int march, double alpha, double *__restrict__ wg_partials, int64_t gx,
+                    int64_t gy, int order) {
+    __shared__ double sh[16];
+    PartDesc d;
+    const int64_t t = part_tile(pk, order == 3 ? 2 : order, d);
+    if (t < 0) return;  // the whole workgroup: no barrier is left waiting
+    const int64_t gz = d.tiles / (gx * gy);
+    int64_t bxi, byi, bzi;
+    heat_coords(t, gx, gy, gz, order, bxi, byi, bzi);
+    double acc;
+    if constexpr (R == 1)
+        acc = heat_tile<VEC, RES>(d.in, d.out, ny, nx, d.lo0, d.hi0, y_lo, y_hi, x_lo, x_hi, col0, tile, march, alpha,
+                                  d.mir, bxi, byi, bzi, threadIdx.x, threadIdx.y, blockDim.x, blockDim.y);
+    else
+        acc = heat_rows_tile<VEC, R, RES>(d.in, d.out, ny, nx, d.lo0, d.hi0, y_lo, y_hi, x_lo, x_hi, col0, tile,
+                                          march, alpha, d.mir, bxi, byi, bzi, threadIdx.x, threadIdx.y, blockDim.x,
+                                          blockDim.y, INT64_MIN, INT64_MAX);
+    if (RES) {
+        const double sum = block_sum(acc, sh);
+        if (threadIdx.x == 0 && threadIdx.y == 0) wg_partials[d.partial_off + t] = sum;  // in tile order
     }
 }
 
@@ -654,6 +733,104 @@ hipError_t launch_heat3d(const Launch &L, hipStream_t s) {
     return hipGetLastError();
 }
 
+int64_t parts_partials(const Launch *L, int n) {
+    int64_t total = 0;
+    for (int k = 0; k < n; ++k) total += heat3d_workgroups(L[k]);
+    return total;
+}
+
+hipError_t launch_parts(const Launch *L, int n, double *wg_partials, int64_t wg_capacity, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (n > kMaxPack) return hipErrorInvalidValue;
+    const Launch &L0 = L[0];
+    const Cfg &c = L0.cfg;
+    const bool heat = L0.kind == JACC_LOOP_HEAT3D;
+    if (!heat && L0.kind != JACC_LOOP_JACOBI2D) return hipErrorInvalidValue;
+    const bool res = heat && L0.part_out != nullptr;
+    const bool xcd = heat ? c.order >= 2 : c.order == 2;
+    const int64_t col0 = col_start(L0.lo[heat ? 2 : 1], c.vec);
+    int64_t gx, gy = 1;
+    if (heat) {
+        const dim3 g3 = heat_grid(L0, col0);
+        gx = g3.x;
+        gy = g3.y;
+    } else {
+        gx = cdiv(L0.hi[1] - col0, (int64_t)c.bx * c.vec);
+    }
+    PartPack pk{};
+    Segments seg{};
+    int64_t begin = 0, partial = 0;
+    for (int k = 0; k < n; ++k) {
+        const Launch &Lk = L[k];
+        int64_t tiles = 0;
+        if (heat)
+            tiles = heat_empty(Lk) ? 0 : heat3d_workgroups(Lk);
+        else if (Lk.hi[0] > Lk.lo[0] && Lk.hi[1] > Lk.lo[1])
+            tiles = gx * cdiv(Lk.hi[0] - Lk.lo[0], (int64_t)c.by * c.tile);
+        if (res) {  // every reducing partition gets its sum, 0 when it has no tiles
+            seg.off[seg.count] = partial;
+            seg.n[seg.count] = tiles;
+            seg.out[seg.count] = Lk.part_out;
+            ++seg.count;
+        }
+        if (tiles == 0) continue;
+        PartDesc &d = pk.p[pk.n++];
+        d.in = (const double *)Lk.a[0].ptr;
+        d.out = (double *)Lk.a[1].ptr;
+        d.lo0 = Lk.lo[0];
+        d.hi0 = Lk.hi[0];
+        d.tiles = tiles;
+        d.begin = begin;
+        d.partial_off = partial;
+        d.mir = Lk.mir;
+        begin += xcd ? (tiles + 7) / 8 * 8 : tiles;
+        if (res) partial += tiles;
+    }
+    if (partial > wg_capacity || begin > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    if (pk.n > 0) {
+        const dim3 grid((unsigned)begin), block(c.bx, c.by);
+        if (!heat) {
+            if (c.vec == 2)
+                hipLaunchKernelGGL(jacobi2d_parts_kernel<2>, grid, block, 0, s, pk, L0.ext[1], L0.lo[1], L0.hi[1],
+                                   col0, c.tile, c.march, gx, c.order);
+            else
+                hipLaunchKernelGGL(jacobi2d_parts_kernel<1>, grid, block, 0, s, pk, L0.ext[1], L0.lo[1], L0.hi[1],
+                                   col0, c.tile, c.march, gx, c.order);
+        } else {
+#define PARTS_ARGS                                                                                                \
+    pk, L0.ext[1], L0.ext[2], L0.lo[1], L0.hi[1], L0.lo[2], L0.hi[2], col0, c.tile, c.march, L0.scalars[0], \
+        wg_partials, gx, gy, c.order
+#define PARTS_LAUNCH(V, R)                                                                          \
+    do {                                                                                            \
+        if (res)                                                                                    \
+            hipLaunchKernelGGL((heat3d_parts_kernel<V, R, true>), grid, block, 0, s, PARTS_ARGS);  \
+        else                                                                                        \
+            hipLaunchKernelGGL((heat3d_parts_kernel<V, R, false>), grid, block, 0, s, PARTS_ARGS); \
+    } while (0)
+            if (c.vec == 2) {
+                switch (c.rows) {
+                    case 1: PARTS_LAUNCH(2, 1); break;
+                    case 2: PARTS_LAUNCH(2, 2); break;
+                    case 4: PARTS_LAUNCH(2, 4); break;
+                    default: PARTS_LAUNCH(2, 8); break;
+                }
+            } else {
+                switch (c.rows) {
+                    case 1: PARTS_LAUNCH(1, 1); break;
+                    case 2: PARTS_LAUNCH(1, 2); break;
+                    case 4: PARTS_LAUNCH(1, 4); break;
+                    default: PARTS_LAUNCH(1, 8); break;
+                }
+            }
+#undef PARTS_LAUNCH
+#undef PARTS_ARGS
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return res ? launch_finalise_many(wg_partials, seg, s) : hipSuccess;
+}
+
 bool make_task(const Launch &L, PTask *t) {
     *t = PTask{};
     t->kind = L.kind;
@@ -698,17 +875,6 @@ bool make_task(const Launch &L, PTask *t) {
 int64_t persistent_grid(int64_t tiles, bool /*jacobi_only*/) {
     const int64_t max_grid = (int64_t)INT32_MAX;
     return tiles < max_grid ? tiles : max_grid;
-}
-
-hipError_t launch_packed(const TaskPack &pack, int64_t tiles, bool jacobi_only, hipStream_t s) {
-    if (pack.n <= 0 || tiles <= 0) return hipSuccess;
-    if (pack.n > kMaxPack) return hipErrorInvalidValue;
-    const int64_t grid = persistent_grid(tiles, jacobi_only);
-    if (jacobi_only)
-        hipLaunchKernelGGL(packed_kernel<true>, dim3((unsigned)grid), dim3(kPersistentThreads), 0, s, pack, tiles);
-    else
-        hipLaunchKernelGGL(packed_kernel<false>, dim3((unsigned)grid), dim3(kPersistentThreads), 0, s, pack, tiles);
-    return hipGetLastError();
 }
 
 hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, int64_t grid, bool jacobi_only,

@@ -107,15 +107,28 @@ int64_t persistent_grid(int64_t tiles, bool jacobi_only);
 hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, int64_t grid, bool jacobi_only,
                              hipStream_t s);
 
-// The partitions of one eager stencil loop as tasks of one launch, the task
-// records passed as kernel arguments (at most kMaxPack; tile_begin set by
-// the caller, tiles = the sum of their ntiles).
+// The partitions of one eager stencil loop in one launch ("packed"): the
+// launches of its partitions (the same kind, configuration and box apart
+// from the dim-0 range, pointers, mirrors and reduction target), at most
+// kMaxPack.  Each partition's tiles take a run of workgroups starting at a
+// multiple of 8, so the XCD-aware tile orders hold within it.  With a
+// residual, partition p's workgroup partials go to wg_partials + (its first
+// tile among all partitions') and one finaliser launch writes every
+// partition's ordered sum to its part_out.  Returns hipErrorInvalidValue
+// for more than kMaxPack launches or more than wg_capacity partials.
 constexpr int kMaxPack = 16;
-struct TaskPack {
-    PTask t[kMaxPack];
-    int32_t n;
+hipError_t launch_parts(const Launch *L, int n, double *wg_partials, int64_t wg_capacity, hipStream_t s);
+// Workgroup partials a packed heat launch with a residual writes.
+int64_t parts_partials(const Launch *L, int n);
+
+// out[k] = ordered sum of base[off[k] .. off[k] + n[k]) for k < count, each
+// in the finaliser's order (one workgroup per segment).
+struct Segments {
+    int64_t off[kMaxPack], n[kMaxPack];
+    double *out[kMaxPack];
+    int32_t count;
 };
-hipError_t launch_packed(const TaskPack &pack, int64_t tiles, bool jacobi_only, hipStream_t s);
+hipError_t launch_finalise_many(const double *base, const Segments &seg, hipStream_t s);
 
 // Number of workgroups the loop's reduction writes partials for (for
 // sizing; <= wg_capacity is required).

@@ -1288,18 +1288,30 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     // graph); the partitions of a stencil step become tiles of one
     // persistent launch when the configuration asks for it
     const bool one_stream = c->serialize || (c->cur != nullptr && !c->fork_capture);
-    // packed: outside batches, the partitions of a stencil loop without a
-    // reduction run as the tasks of one launch on one stream (measured on
-    // 8192^2 Jacobi at K = 8: 5.9-6.0 TB/s, against 4.9-5.6 for a launch per
-    // partition on K streams, whose kernels contend for the device's
-    // hardware queues); launch shapes other than the task kernel's 256 x 1
-    // threads in row-major tile order keep a launch per partition
-    const bool packed = !c->cur && !c->no_pack && !c->serialize && !c->time_parts && !c->split && K > 1 &&
-                        K <= jk::kMaxPack && !want_red && !persistent && !dup &&
-                        (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) &&
-                        !(args[primary].mode & JACC_FILTERED) && P->pdim == 0 && !P->whole &&
-                        L.cfg.bx == jk::kPersistentThreads && L.cfg.by == 1 && L.cfg.order == 1 &&
-                        (kind == JACC_LOOP_JACOBI2D || L.cfg.rows == 1);
+    // packed: outside batches, the partitions of a stencil loop run in one
+    // launch on one stream, each partition's tiles a run of its workgroups
+    // (measured on 8192^2 Jacobi at K = 8: 5.9-6.0 TB/s, against 4.9-5.6
+    // for a launch per partition on K streams, whose kernels contend for the
+    // device's hardware queues); a residual's workgroup partials of all
+    // partitions must fit the stream's partial buffer
+    bool packed = !c->cur && !c->no_pack && !c->serialize && !c->time_parts && !c->split && K > 1 &&
+                  K <= jk::kMaxPack && !persistent && !dup && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) &&
+                  !(args[primary].mode & JACC_FILTERED) && P->pdim == 0 && !P->whole;
+    if (packed && want_red) {
+        int64_t total = 0;
+        for (int p = 0; p < K; ++p) {
+            if (plan[p].iters.empty()) continue;
+            jk::Launch T = L;
+            for (int d = 0; d < b->ndim; ++d) {
+                T.lo[d] = b->lo[d];
+                T.hi[d] = b->hi[d];
+            }
+            T.lo[0] = plan[p].iters.lo;
+            T.hi[0] = plan[p].iters.hi;
+            total += jk::reduction_workgroups(T);
+        }
+        packed = total <= kWgCapacity;
+    }
     auto stream_for = [&](int p) { return (one_stream || persistent) ? 0 : (base + (packed ? 0 : p)) % ns; };
     // rows of its slab a partition may write: a filtered output entered
     // whole takes private writes anywhere in the partition's replica
@@ -1428,15 +1440,12 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
                     if (rc) return rc;
                 }
         }
-        jk::TaskPack pack;
-        pack.n = 0;
-        int64_t tiles = 0;
-        bool jacobi_only = true;
+        std::vector<jk::Launch> lps;
         std::vector<std::vector<std::pair<int, Range>>> mirs((size_t)K);
         for (int p = 0; p < K; ++p) {
             const PartPlan &pp = plan[p];
             if (pp.iters.empty()) continue;
-            const jk::Launch LP = piece_launch(p, pp, mirs[(size_t)p]);
+            jk::Launch LP = piece_launch(p, pp, mirs[(size_t)p]);
             for (int i = 0; i < nargs; ++i) {
                 if (args[i].mode & JACC_READ) {
                     rc = hazard(c, arr[i], p, pp.rng[i], false, s);
@@ -1451,19 +1460,25 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
                 rc = hazard(c, P, m.first, m.second, true, s);
                 if (rc) return rc;
             }
-            jk::PTask t;
-            if (!jk::make_task(LP, &t)) return set_err(c, JACC_ERR_INVALID, "internal: loop kind %d not packable", kind);
-            if (t.ntiles <= 0) continue;
-            t.tile_begin = tiles;
-            tiles += t.ntiles;
-            jacobi_only = jacobi_only && t.kind == JACC_LOOP_JACOBI2D;
-            pack.t[pack.n++] = t;
+            if (want_red) {  // as in a launch per partition: partials[slot][p] free, sum written there
+                const size_t pi = (size_t)red_slot * kMaxK + p;
+                rc = ensure_wait(c, s, c->partial_reader[pi].s, c->partial_reader[pi].seq);
+                if (rc) return rc;
+                LP.part_out = c->partials + pi;
+                order.push_back(p);
+                red_streams.push_back(s);
+            }
+            lps.push_back(LP);
         }
         if (inject_fault(c, 2)) {
             c->status = JACC_ERR_DEVICE;
             return set_err(c, JACC_ERR_DEVICE, "injected fault in launch %lld", (long long)c->fault_count);
         }
-        if (live(c)) HIPCHK(c, jk::launch_packed(pack, tiles, jacobi_only, c->st[s].s), "kernel launch");
+        if (live(c))
+            HIPCHK(c,
+                   jk::launch_parts(lps.data(), (int)lps.size(), c->wg + (size_t)s * kWgCapacity, kWgCapacity,
+                                    c->st[s].s),
+                   "kernel launch");
         c->st[s].seq++;
         for (int p = 0; p < K; ++p)
             if (!plan[p].iters.empty())

@@ -944,17 +944,16 @@ def test_packed_stencil_loop_is_one_launch_on_one_stream(K):
     partition's KERNEL entry shares one stream and one sequence number, the
     pulls (lazy) precede it on that stream, and the plan still matches the
     set model (same iterations and copies) and stays race-free and fresh.
-    With JACC_INIT_NO_PACK, SPLIT or an explicit non-task launch shape each
-    partition launches on its own stream."""
+    Any launch shape packs; JACC_INIT_NO_PACK or SPLIT keeps a launch per
+    partition on its own stream."""
     E = 8 * K + 3
-    for flags, packed in ((0, True), (jacc.INIT_LAZY, True), (jacc.INIT_NO_PACK, False),
-                          (jacc.INIT_SPLIT, False), ("shape", False)):
-        c = jacc.Context(K, flags=DRY | (flags if flags != "shape" else 0))
+    for flags, cfg, packed in ((0, None, True), (jacc.INIT_LAZY, None, True), (0, jacc.config(bx=64, by=2), True),
+                               (jacc.INIT_NO_PACK, None, False), (jacc.INIT_SPLIT, None, False)):
+        c = jacc.Context(K, flags=DRY | flags)
         a = np.zeros((E, 20))
         b = np.zeros((E, 20))
         c.enter(a, halo=(1, 1))
         c.enter(b, halo=(1, 1))
-        cfg = jacc.config(bx=64, by=2) if flags == "shape" else None
         c.trace_clear()
         c.jacobi2d(a, b, cfg=cfg)
         c.jacobi2d(b, a, cfg=cfg)
@@ -969,17 +968,26 @@ def test_packed_stencil_loop_is_one_launch_on_one_stream(K):
         c.close()
 
 
-def test_heat_default_and_reductions_keep_a_launch_per_partition():
-    c = jacc.Context(4, flags=DRY)
-    a = np.zeros((18, 10, 66))
-    b = np.zeros((18, 10, 66))
-    c.enter(a, halo=(1, 1))
-    c.enter(b, halo=(1, 1))
-    c.trace_clear()
-    c.heat3d(a, b, 0.1)                       # default heat shape: several rows per wave
-    c.heat3d(b, a, 0.1, cfg=jacc.config(bx=256, by=1, rows=1, order=1))  # the task shape: packed
-    c.heat3d(a, b, 0.1, slot=0, cfg=jacc.config(bx=256, by=1, rows=1, order=1))  # a reduction: not packed
-    kern = [t for t in c.trace() if t["op"] == "KERNEL"]
-    assert [len({(t["stream"], t["seq"]) for t in kern[i:i + 4]}) for i in (0, 4, 8)] == [4, 1, 4]
-    assert race_check(c.trace()) == [] and freshness_check(c.trace()) == []
-    c.close()
+@pytest.mark.parametrize("flags", [0, jacc.INIT_LAZY, jacc.INIT_EAGER])
+def test_heat_loops_pack_with_and_without_residual(flags):
+    """Heat steps pack too, with or without the fused residual (one launch
+    per step, then the per-slot combine); JACC_INIT_NO_PACK restores a
+    launch per partition."""
+    for no_pack in (False, True):
+        c = jacc.Context(4, flags=DRY | flags | (jacc.INIT_NO_PACK if no_pack else 0))
+        a = np.zeros((18, 10, 66))
+        b = np.zeros((18, 10, 66))
+        c.enter(a, halo=(1, 1))
+        c.enter(b, halo=(1, 1))
+        c.trace_clear()
+        c.heat3d(a, b, 0.1)
+        c.heat3d(b, a, 0.1, slot=0)
+        c.heat3d(a, b, 0.1, slot=1, cfg=jacc.config(bx=256, by=1, rows=1, order=1))
+        ops = c.trace()
+        kern = [t for t in ops if t["op"] == "KERNEL"]
+        assert len(kern) == 12
+        per_loop = [len({(t["stream"], t["seq"]) for t in kern[i:i + 4]}) for i in (0, 4, 8)]
+        assert per_loop == ([4, 4, 4] if no_pack else [1, 1, 1])
+        assert len([t for t in ops if t["op"] == "COMBINE"]) == 2
+        assert race_check(ops) == [] and freshness_check(ops) == []
+        c.close()
