@@ -345,8 +345,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"jacobi2d_5pt {n}x{n}, {args.steps} iterations, K={main_k} row-block "
                                f"partitions in separate slabs, 1-row halo exchange per step (mirror stores); "
-                               f"the partitions of a step run as the tasks of one launch (per_k_modes.streams: "
-                               f"a launch per partition on K streams)",
+                               f"the partitions of a step run in one launch (per_k_modes.streams: a launch per "
+                               f"partition on K streams)",
                    "grid": [n, n], "K": main_k, "iterations": args.steps, "seed": 1},
         "frac_hbm_peak": round(value / HBM_PEAK_GBS, 4),
         "per_k": {str(k): v for k, v in per_k.items()},
@@ -370,7 +370,7 @@ def main():
         # average duration from the same HIP events
         avg = per_k[main_k]["event_us_per_step"] / 1e6
         ach = step_bytes / avg / 1e9
-        result["roofline_packed"] = {"kernel": f"packed_kernel<true> ({main_k} partitions as tasks, one launch per step)",
+        result["roofline_packed"] = {"kernel": f"jacobi2d_parts_kernel<2> ({main_k} partitions, one launch per step)",
                                      "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                                      "avg_launch_us": round(avg * 1e6, 2), "bytes_per_launch": int(step_bytes)}

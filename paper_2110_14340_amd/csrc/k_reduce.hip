@@ -43,6 +43,52 @@ sum_kernel(const double *__restrict__ x, int64_t begin, int64_t n, double *__res
     if (threadIdx.x == 0) wg_partials[blockIdx.x] = s;
 }
 
+// The partitions of one SUM loop in one launch: partition q's workgroups
+// [wg_begin, wg_begin + nb) run exactly the grid-stride walk its own launch
+// of nb workgroups would, so every partial has the same bits.
+struct SumPart {
+    const double *x;
+    int64_t begin, n;  // the partition's elements x[begin .. begin + n)
+    int64_t wg_begin, nb;
+    double *partials;  // its nb workgroup partials
+};
+struct SumParts {
+    SumPart p[kMaxPack];
+    int32_t n;
+};
+typedef const __attribute__((address_space(4))) SumPart ConstSumPart;
+
+template <bool SQ>
+__global__ void __launch_bounds__(kSumThreads) sum_parts_kernel(SumParts sp) {
+    __shared__ double sh[kSumThreads / kWave];
+    ConstSumPart *cp = (ConstSumPart *)&sp.p[0];
+    const int64_t b = blockIdx.x;
+    int q = 0;
+    for (int k = 1; k < sp.n; ++k)
+        if (cp[k].wg_begin <= b) q = k;
+    const double *x = cp[q].x;
+    double *partials = cp[q].partials;
+    const int64_t begin = cp[q].begin, n = cp[q].n, nb = cp[q].nb, local = b - cp[q].wg_begin;
+    const int64_t chunk = (int64_t)kSumThreads * kSumUnroll;
+    const int64_t stride = chunk * nb;
+    double a[kSumUnroll];
+#pragma unroll
+    for (int u = 0; u < kSumUnroll; ++u) a[u] = 0.0;
+    for (int64_t base = local * chunk; base < n; base += stride) {
+        double v[kSumUnroll];
+#pragma unroll
+        for (int u = 0; u < kSumUnroll; ++u) {
+            const int64_t e = base + threadIdx.x + (int64_t)u * kSumThreads;
+            v[u] = e < n ? x[begin + e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSumUnroll; ++u) a[u] += SQ ? v[u] * v[u] : v[u];
+    }
+    const double t = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    const double s = block_sum(t, sh);
+    if (threadIdx.x == 0) partials[local] = s;
+}
+
 // out = ordered sum of p[0..n): thread t keeps 8 running sums, sum u taking
 // p[t + (8j+u)*1024] for j = 0, 1, ... (eight independent loads in flight
 // per step instead of one dependent chain), adds them pairwise, then the
@@ -112,6 +158,38 @@ hipError_t launch_sum(const Launch &L, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_finalise(L.wg_partials, nb, L.part_out, s);
+}
+
+hipError_t launch_sum_parts(const Launch *L, int n, double *wg_partials, int64_t wg_capacity, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (n > kMaxPack) return hipErrorInvalidValue;
+    SumParts sp{};
+    Segments seg{};
+    int64_t wg = 0;
+    for (int k = 0; k < n; ++k) {
+        const Launch &Lk = L[k];
+        const int64_t nb = sum_workgroups(Lk);
+        SumPart &d = sp.p[sp.n++];
+        d.x = (const double *)Lk.a[0].ptr;
+        d.begin = Lk.lo[0] * Lk.a[0].row_elems;
+        d.n = (Lk.hi[0] - Lk.lo[0]) * Lk.a[0].row_elems;
+        d.wg_begin = wg;
+        d.nb = nb;
+        d.partials = wg_partials + wg;
+        seg.off[seg.count] = wg;
+        seg.n[seg.count] = nb;
+        seg.out[seg.count] = Lk.part_out;
+        ++seg.count;
+        wg += nb;
+    }
+    if (wg > wg_capacity) return hipErrorInvalidValue;
+    if (L[0].scalars[0] != 0.0)
+        hipLaunchKernelGGL(sum_parts_kernel<true>, dim3((unsigned)wg), dim3(kSumThreads), 0, s, sp);
+    else
+        hipLaunchKernelGGL(sum_parts_kernel<false>, dim3((unsigned)wg), dim3(kSumThreads), 0, s, sp);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalise_many(wg_partials, seg, s);
 }
 
 hipError_t launch_finalise(const double *partials, int64_t n, double *out, hipStream_t s) {

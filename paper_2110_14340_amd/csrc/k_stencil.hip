@@ -743,6 +743,7 @@ hipError_t launch_parts(const Launch *L, int n, double *wg_partials, int64_t wg_
     if (n <= 0) return hipSuccess;
     if (n > kMaxPack) return hipErrorInvalidValue;
     const Launch &L0 = L[0];
+    if (L0.kind == JACC_LOOP_SUM) return launch_sum_parts(L, n, wg_partials, wg_capacity, s);
     const Cfg &c = L0.cfg;
     const bool heat = L0.kind == JACC_LOOP_HEAT3D;
     if (!heat && L0.kind != JACC_LOOP_JACOBI2D) return hipErrorInvalidValue;

@@ -107,7 +107,7 @@ int64_t persistent_grid(int64_t tiles, bool jacobi_only);
 hipError_t launch_persistent(const PTask *tasks, int ntasks, int64_t tiles, int64_t grid, bool jacobi_only,
                              hipStream_t s);
 
-// The partitions of one eager stencil loop in one launch ("packed"): the
+// The partitions of one eager stencil (or SUM) loop in one launch ("packed"): the
 // launches of its partitions (the same kind, configuration and box apart
 // from the dim-0 range, pointers, mirrors and reduction target), at most
 // kMaxPack.  Each partition's tiles take a run of workgroups starting at a
@@ -129,6 +129,9 @@ struct Segments {
     int32_t count;
 };
 hipError_t launch_finalise_many(const double *base, const Segments &seg, hipStream_t s);
+// The partitions of one SUM loop in one launch, then their finalisers (the
+// same bits as a launch per partition).
+hipError_t launch_sum_parts(const Launch *L, int n, double *wg_partials, int64_t wg_capacity, hipStream_t s);
 
 // Number of workgroups the loop's reduction writes partials for (for
 // sizing; <= wg_capacity is required).

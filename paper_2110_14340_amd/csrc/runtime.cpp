@@ -1295,7 +1295,8 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     // device's hardware queues); a residual's workgroup partials of all
     // partitions must fit the stream's partial buffer
     bool packed = !c->cur && !c->no_pack && !c->serialize && !c->time_parts && !c->split && K > 1 &&
-                  K <= jk::kMaxPack && !persistent && !dup && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) &&
+                  K <= jk::kMaxPack && !persistent && !dup &&
+                  (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D || kind == JACC_LOOP_SUM) &&
                   !(args[primary].mode & JACC_FILTERED) && P->pdim == 0 && !P->whole;
     if (packed && want_red) {
         int64_t total = 0;

@@ -41,6 +41,22 @@ def test_sum_512_cubed_k1_k4():
         assert abs(s - ref) <= 1e-13 * ref
 
 
+@pytest.mark.parametrize("n,K", [(2_000_003, 3), (1 << 24, 8), (5_000_000, 16)])
+def test_sum_packed_partitions_equal_a_launch_per_partition(n, K):
+    """One launch over all partitions (the default) and a launch per
+    partition on its own stream add in the same order: the sums are
+    bit-identical, and within the oracle's bound."""
+    say(f"sum packed vs per-partition n={n} K={K}")
+    x = inputs.uniform(n, seed=n + K, lo=-1.0, hi=1.0)
+    got = []
+    for flags in (0, jacc.INIT_NO_PACK):
+        with context(K, flags) as c:
+            c.enter(x)
+            got.append((c.sum(x), c.sum(x, squares=True)))
+    assert got[0] == got[1]
+    assert abs(got[0][0] - oracle.sum_(x)) <= 1e-13 * float(np.abs(x).sum())
+
+
 def test_sum_integer_exact_and_deferred_slots():
     say("sum integer exact")
     x = (np.arange(1 << 20) % 1024).astype(np.float64)

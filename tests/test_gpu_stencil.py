@@ -127,7 +127,7 @@ def heat_512():
     return u0, ref, ref_res
 
 
-@pytest.mark.parametrize("K,flags", [(4, 0), (1, 0), (4, jacc.INIT_LAZY)])
+@pytest.mark.parametrize("K,flags", [(4, 0), (1, 0), (4, jacc.INIT_LAZY), (4, jacc.INIT_NO_PACK)])
 def test_heat_512_100_steps_full_oracle(heat_512, K, flags):
     """The whole 512^3 field after 100 steps equal to the oracle's, and every
     one of the 100 per-step residuals within 1e-13 relative."""
@@ -290,3 +290,16 @@ def test_heat_packed_partitions_bit_exact(shape, K, flags):
         c.exit(a, jacc.COPYOUT)
         c.exit(b, jacc.COPYOUT)
     assert np.array_equal(src, oracle.heat3d(u0, 5, 0.1)[0])
+
+
+@pytest.mark.parametrize("shape,K", [((66, 40, 130), 3), ((130, 34, 66), 4), ((40, 20, 258), 8)])
+def test_heat_residuals_packed_equal_a_launch_per_partition(shape, K):
+    """Fields and every residual bit-identical between one launch over all
+    partitions (the default) and a launch per partition on its own stream."""
+    say(f"heat residual packed vs per-partition {shape} K={K}")
+    u0 = inputs.heat_field(*shape, seed=43)
+    packed = run_heat(u0, 6, 0.1, K)
+    per_part = run_heat(u0, 6, 0.1, K, ctx_flags=jacc.INIT_NO_PACK)
+    assert np.array_equal(packed[0], per_part[0]) and np.array_equal(packed[1], per_part[1])
+    ref, ref_res = oracle.heat3d(u0, 6, 0.1)
+    assert np.array_equal(packed[0], ref) and _rel_close(packed[1], ref_res)

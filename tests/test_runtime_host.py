@@ -991,3 +991,18 @@ def test_heat_loops_pack_with_and_without_residual(flags):
         assert len([t for t in ops if t["op"] == "COMBINE"]) == 2
         assert race_check(ops) == [] and freshness_check(ops) == []
         c.close()
+
+
+def test_sum_packs_its_partitions():
+    for no_pack, keys in ((False, 1), (True, 4)):
+        c = jacc.Context(4, flags=DRY | (jacc.INIT_NO_PACK if no_pack else 0))
+        x = np.zeros(1000)
+        c.enter(x)
+        c.trace_clear()
+        c.sum(x, slot=3, sync=False)
+        ops = c.trace()
+        kern = [t for t in ops if t["op"] == "KERNEL"]
+        assert len(kern) == 4 and len({(t["stream"], t["seq"]) for t in kern}) == keys
+        assert len([t for t in ops if t["op"] == "COMBINE"]) == 1
+        assert race_check(ops) == [] and freshness_check(ops) == []
+        c.close()
