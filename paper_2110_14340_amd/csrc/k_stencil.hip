@@ -78,15 +78,58 @@ __device__ __forceinline__ void store_masked(double *q, const double (&o)[VEC], 
     }
 }
 
+// A mirror store goes through a global-address-space pointer: a mirror
+// pointer read from a descriptor table and picked by a loop index is
+// otherwise a generic pointer, stored through with flat operations, which
+// count against the counter the cross-lane shuffles wait on.
+template <int VEC>
+__device__ __forceinline__ void store_masked_global(double *p, const double (&o)[VEC], bool all,
+                                                    const bool (&comp)[VEC]) {
+    typedef __attribute__((address_space(1))) double GDouble;
+    typedef __attribute__((address_space(1))) dvec2 GDvec2;
+    GDouble *q = (GDouble *)p;
+    if (all) {
+        if constexpr (VEC == 2) {
+            dvec2 t;
+            t.x = o[0];
+            t.y = o[1];
+            __builtin_nontemporal_store(t, (GDvec2 *)q);
+        } else {
+            __builtin_nontemporal_store(o[0], q);
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+            if (comp[v]) q[v] = o[v];
+    }
+}
+
+// Mirror handling of a kernel (MM): 0 the launch writes no mirrors (the
+// code is left out), 1 a loop over mirrors passed as kernel arguments, 2
+// the two mirrors of a descriptor read from memory, unrolled (a loop index
+// into a descriptor held in registers puts the whole descriptor in scratch
+// memory: 40 % slower).  The forms schedule differently: without the loop
+// the compiler keeps more loads in flight in more registers (the Jacobi
+// tile 100 registers and four waves per SIMD, against 80 and six with the
+// loop), which measured 2 % faster on 8192^2 sweeps but 7 % slower on heat
+// 512^3 and 20-40 % slower on batches of small grids; so only large Jacobi
+// launches without mirrors take form 0.
+//
 // Stores an output row (or plane) `r` at offset `off` from its row start,
 // and again into every mirror holding row r (uniform test per row).
-template <int VEC>
+template <int VEC, int MM>
 __device__ __forceinline__ void store_out(double *out, int64_t off, int64_t r, const Mirrors &mir,
                                           const double (&o)[VEC], bool all, const bool (&comp)[VEC]) {
     store_masked<VEC>(out + off, o, all, comp);
+    if constexpr (MM == 1) {
+        for (int k = 0; k < mir.n; ++k)
+            if (r >= mir.m[k].lo && r < mir.m[k].hi) store_masked_global<VEC>(mir.m[k].ptr + off, o, all, comp);
+    } else if constexpr (MM == 2) {
 #pragma unroll
-    for (int k = 0; k < 2; ++k)  // unrolled: each mirror pointer stays a known global address
-        if (k < mir.n && r >= mir.m[k].lo && r < mir.m[k].hi) store_masked<VEC>(mir.m[k].ptr + off, o, all, comp);
+        for (int k = 0; k < 2; ++k)
+            if (k < mir.n && r >= mir.m[k].lo && r < mir.m[k].hi)
+                store_masked_global<VEC>(mir.m[k].ptr + off, o, all, comp);
+    }
 }
 
 // March direction of the wave's tile q: with march == 2 odd tiles run toward
@@ -100,7 +143,7 @@ __device__ __forceinline__ int64_t march_dir(int march, int64_t q) { return (mar
 // ---------------------------------------------------------------------------
 // Jacobi-2D tile: lanes [tx] of row-group [ty] of workgroup tile (bxi, byi)
 // ---------------------------------------------------------------------------
-template <int VEC>
+template <int VEC, int MM>
 __device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, double *__restrict__ out, int64_t nx,
                                             int64_t pitch, int64_t r_lo, int64_t r_hi, int64_t c_lo, int64_t c_hi,
                                             int64_t col0, int tile, int march, const Mirrors &mir, int64_t bxi,
@@ -154,7 +197,7 @@ __device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, doubl
                 }
                 // write guard of a filtered loop (every partition computes the
                 // whole box and keeps its owner rows); uniform per row
-                if (row >= own_lo && row < own_hi) store_out<VEC>(out, row * pitch + j, row, mir, o, all, comp);
+                if (row >= own_lo && row < own_hi) store_out<VEC, MM>(out, row * pitch + j, row, mir, o, all, comp);
             }
         }
 #pragma unroll
@@ -173,13 +216,13 @@ __device__ __forceinline__ int64_t tile_of(int order) {
     return b;
 }
 
-template <int VEC>
+template <int VEC, int MM>
 __global__ void __launch_bounds__(1024)
 jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t nx, int64_t pitch, int64_t r_lo,
                 int64_t r_hi, int64_t c_lo, int64_t c_hi, int64_t col0, int tile, int march, Mirrors mir, int64_t gx,
                 int order, int64_t own_lo, int64_t own_hi) {
     const int64_t t = tile_of(order);
-    jacobi_tile<VEC>(in, out, nx, pitch, r_lo, r_hi, c_lo, c_hi, col0, tile, march, mir, t % gx, t / gx, threadIdx.x,
+    jacobi_tile<VEC, MM>(in, out, nx, pitch, r_lo, r_hi, c_lo, c_hi, col0, tile, march, mir, t % gx, t / gx, threadIdx.x,
                      threadIdx.y, blockDim.x, blockDim.y, own_lo, own_hi);
 }
 
@@ -187,7 +230,7 @@ jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t
 // Heat-3D tile: row y = y_lo + byi*bdy + ty, planes [z_lo + bzi*tile, +tile)
 // Returns this lane's sum of (u'-u)^2 when RES.
 // ---------------------------------------------------------------------------
-template <int VEC, bool RES>
+template <int VEC, bool RES, int MM>
 __device__ __forceinline__ double heat_tile(const double *__restrict__ in, double *__restrict__ out, int64_t ny,
                                             int64_t nx, int64_t z_lo, int64_t z_hi, int64_t y_lo, int64_t y_hi,
                                             int64_t x_lo, int64_t x_hi, int64_t col0, int tile, int march, double alpha,
@@ -260,7 +303,7 @@ __device__ __forceinline__ double heat_tile(const double *__restrict__ in, doubl
                         acc += dd * dd;
                     }
                 }
-                if (keep) store_out<VEC>(out, z * plane + y * nx + x, z, mir, o, all, comp);
+                if (keep) store_out<VEC, MM>(out, z * plane + y * nx + x, z, mir, o, all, comp);
             }
         }
 #pragma unroll
@@ -311,7 +354,7 @@ __device__ __forceinline__ void load_plane(const double *__restrict__ p, int64_t
     }
 }
 
-template <int VEC, int R, bool RES>
+template <int VEC, int R, bool RES, int MM>
 __device__ __forceinline__ double heat_rows_tile(const double *__restrict__ in, double *__restrict__ out, int64_t ny,
                                                  int64_t nx, int64_t z_lo, int64_t z_hi, int64_t y_lo, int64_t y_hi,
                                                  int64_t x_lo, int64_t x_hi, int64_t col0, int tile, int march,
@@ -378,7 +421,7 @@ __device__ __forceinline__ double heat_rows_tile(const double *__restrict__ in, 
                         acc += dd * dd;
                     }
                 }
-                if (keep) store_out<VEC>(out, z * plane + (yb + i) * nx + x, z, mir, o, all, comp);
+                if (keep) store_out<VEC, MM>(out, z * plane + (yb + i) * nx + x, z, mir, o, all, comp);
             }
         }
     };
@@ -421,7 +464,7 @@ __device__ __forceinline__ void heat_coords(int64_t t, int64_t gx, int64_t gy, i
     }
 }
 
-template <int VEC, int R, bool RES>
+template <int VEC, int R, bool RES, int MM>
 __global__ void __launch_bounds__(R == 1 ? 1024 : 256)
 heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t ny, int64_t nx, int64_t z_lo,
               int64_t z_hi, int64_t y_lo, int64_t y_hi, int64_t x_lo, int64_t x_hi, int64_t col0, int tile,
@@ -434,10 +477,10 @@ heat3d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t n
     heat_coords(t, gx, gy, gz, order, bxi, byi, bzi);
     double acc;
     if constexpr (R == 1)
-        acc = heat_tile<VEC, RES>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, march, alpha, mir,
+        acc = heat_tile<VEC, RES, MM>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, march, alpha, mir,
                                   bxi, byi, bzi, threadIdx.x, threadIdx.y, blockDim.x, blockDim.y, own_lo, own_hi);
     else
-        acc = heat_rows_tile<VEC, R, RES>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, march,
+        acc = heat_rows_tile<VEC, R, RES, MM>(in, out, ny, nx, z_lo, z_hi, y_lo, y_hi, x_lo, x_hi, col0, tile, march,
                                           alpha, mir, bxi, byi, bzi, threadIdx.x, threadIdx.y, blockDim.x,
                                           blockDim.y, own_lo, own_hi);
     if (RES) {
@@ -463,19 +506,19 @@ __device__ __forceinline__ void persistent_tile(const PTask &T, int64_t local) {
     const Mirrors mir = T.mir;
     if (JONLY || T.kind == JACC_LOOP_JACOBI2D) {
         if (T.vec == 2)
-            jacobi_tile<2>(in, out, T.e1, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, mir, bxi,
+            jacobi_tile<2, 2>(in, out, T.e1, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, mir, bxi,
                            rest, threadIdx.x, 0, kPersistentThreads, 1);
         else
-            jacobi_tile<1>(in, out, T.e1, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, mir, bxi,
+            jacobi_tile<1, 2>(in, out, T.e1, T.e1, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.col0, T.tile, T.march, mir, bxi,
                            rest, threadIdx.x, 0, kPersistentThreads, 1);
     } else if constexpr (!JONLY) {
         const int64_t byi = rest % T.gy, bzi = rest / T.gy;
         if (T.vec == 2)
-            (void)heat_tile<2, false>(in, out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2], T.hi[2],
+            (void)heat_tile<2, false, 2>(in, out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2], T.hi[2],
                                       T.col0, T.tile, T.march, T.alpha, mir, bxi, byi, bzi, threadIdx.x, 0,
                                       kPersistentThreads, 1);
         else
-            (void)heat_tile<1, false>(in, out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2], T.hi[2],
+            (void)heat_tile<1, false, 2>(in, out, T.e1, T.e2, T.lo[0], T.hi[0], T.lo[1], T.hi[1], T.lo[2], T.hi[2],
                                       T.col0, T.tile, T.march, T.alpha, mir, bxi, byi, bzi, threadIdx.x, 0,
                                       kPersistentThreads, 1);
     }
@@ -598,18 +641,18 @@ __device__ __forceinline__ int64_t part_tile(const PartPack &pk, int order, Part
     return t < d.tiles ? t : -1;
 }
 
-template <int VEC>
+template <int VEC, int MM>
 __global__ void __launch_bounds__(1024)
 jacobi2d_parts_kernel(PartPack pk, int64_t nx, int64_t c_lo, int64_t c_hi, int64_t col0, int tile, int march,
                       int64_t gx, int order) {
     PartDesc d;
     const int64_t t = part_tile(pk, order, d);
     if (t < 0) return;
-    jacobi_tile<VEC>(d.in, d.out, nx, nx, d.lo0, d.hi0, c_lo, c_hi, col0, tile, march, d.mir, t % gx, t / gx,
+    jacobi_tile<VEC, MM>(d.in, d.out, nx, nx, d.lo0, d.hi0, c_lo, c_hi, col0, tile, march, d.mir, t % gx, t / gx,
                      threadIdx.x, threadIdx.y, blockDim.x, blockDim.y);
 }
 
-template <int VEC, int R, bool RES>
+template <int VEC, int R, bool RES, int MM>
 __global__ void __launch_bounds__(R == 1 ? 1024 : 256)
 heat3d_parts_kernel(PartPack pk, int64_t ny, int64_t nx, int64_t y_lo, int64_t y_hi, int64_t x_lo, int64_t x_hi,
                     int64_t col0, int tile, int march, double alpha, double *__restrict__ wg_partials, int64_t gx,
@@ -623,10 +666,10 @@ heat3d_parts_kernel(PartPack pk, int64_t ny, int64_t nx, int64_t y_lo, int64_t y
     heat_coords(t, gx, gy, gz, order, bxi, byi, bzi);
     double acc;
     if constexpr (R == 1)
-        acc = heat_tile<VEC, RES>(d.in, d.out, ny, nx, d.lo0, d.hi0, y_lo, y_hi, x_lo, x_hi, col0, tile, march, alpha,
+        acc = heat_tile<VEC, RES, MM>(d.in, d.out, ny, nx, d.lo0, d.hi0, y_lo, y_hi, x_lo, x_hi, col0, tile, march, alpha,
                                   d.mir, bxi, byi, bzi, threadIdx.x, threadIdx.y, blockDim.x, blockDim.y);
     else
-        acc = heat_rows_tile<VEC, R, RES>(d.in, d.out, ny, nx, d.lo0, d.hi0, y_lo, y_hi, x_lo, x_hi, col0, tile,
+        acc = heat_rows_tile<VEC, R, RES, MM>(d.in, d.out, ny, nx, d.lo0, d.hi0, y_lo, y_hi, x_lo, x_hi, col0, tile,
                                           march, alpha, d.mir, bxi, byi, bzi, threadIdx.x, threadIdx.y, blockDim.x,
                                           blockDim.y, INT64_MIN, INT64_MAX);
     if (RES) {
@@ -662,12 +705,23 @@ hipError_t launch_jacobi2d(const Launch &L, hipStream_t s) {
     if (L.a[1].row_elems != pitch) return hipErrorInvalidValue;
     const bool filtered = L.own_hi > L.own_lo;  // FILTERED output: keep the owner rows only
     const int64_t own_lo = filtered ? L.own_lo : INT64_MIN, own_hi = filtered ? L.own_hi : INT64_MAX;
-    if (c.vec == 2)
-        hipLaunchKernelGGL(jacobi2d_kernel<2>, grid, block, 0, s, in, out, nx, pitch, L.lo[0], L.hi[0], L.lo[1],
-                           L.hi[1], col0, c.tile, c.march, L.mir, gx, c.order, own_lo, own_hi);
-    else
-        hipLaunchKernelGGL(jacobi2d_kernel<1>, grid, block, 0, s, in, out, nx, pitch, L.lo[0], L.hi[0], L.lo[1],
-                           L.hi[1], col0, c.tile, c.march, L.mir, gx, c.order, own_lo, own_hi);
+#define JACOBI_LAUNCH(V, M)                                                                                   \
+    hipLaunchKernelGGL((jacobi2d_kernel<V, M>), grid, block, 0, s, in, out, nx, pitch, L.lo[0], L.hi[0], L.lo[1], \
+                       L.hi[1], col0, c.tile, c.march, L.mir, gx, c.order, own_lo, own_hi)
+    // the mirror-free form for launches of at least 2^22 cells without mirrors
+    const bool lean = L.mir.n == 0 && nrows * (L.hi[1] - L.lo[1]) >= ((int64_t)1 << 22);
+    if (c.vec == 2) {
+        if (lean)
+            JACOBI_LAUNCH(2, 0);
+        else
+            JACOBI_LAUNCH(2, 1);
+    } else {
+        if (lean)
+            JACOBI_LAUNCH(1, 0);
+        else
+            JACOBI_LAUNCH(1, 1);
+    }
+#undef JACOBI_LAUNCH
     return hipGetLastError();
 }
 
@@ -706,12 +760,12 @@ hipError_t launch_heat3d(const Launch &L, hipStream_t s) {
 #define HEAT_ARGS                                                                                                    \
     in, out, ny, nx, L.lo[0], L.hi[0], L.lo[1], L.hi[1], L.lo[2], L.hi[2], col0, c.tile, c.march, alpha,             \
         L.wg_partials, L.mir, gx, gy, c.order, own_lo, own_hi
-#define HEAT_LAUNCH(V, R)                                                                 \
-    do {                                                                                  \
-        if (res)                                                                          \
-            hipLaunchKernelGGL((heat3d_kernel<V, R, true>), grid, block, 0, s, HEAT_ARGS);  \
-        else                                                                              \
-            hipLaunchKernelGGL((heat3d_kernel<V, R, false>), grid, block, 0, s, HEAT_ARGS); \
+#define HEAT_LAUNCH(V, R)                                                                    \
+    do {                                                                                     \
+        if (res)                                                                             \
+            hipLaunchKernelGGL((heat3d_kernel<V, R, true, 1>), grid, block, 0, s, HEAT_ARGS);  \
+        else                                                                                 \
+            hipLaunchKernelGGL((heat3d_kernel<V, R, false, 1>), grid, block, 0, s, HEAT_ARGS); \
     } while (0)
     if (c.vec == 2) {
         switch (c.rows) {
@@ -791,22 +845,24 @@ hipError_t launch_parts(const Launch *L, int n, double *wg_partials, int64_t wg_
     if (pk.n > 0) {
         const dim3 grid((unsigned)begin), block(c.bx, c.by);
         if (!heat) {
+#define JPARTS_LAUNCH(V, M)                                                                                   \
+    hipLaunchKernelGGL((jacobi2d_parts_kernel<V, M>), grid, block, 0, s, pk, L0.ext[1], L0.lo[1], L0.hi[1], col0, \
+                       c.tile, c.march, gx, c.order)
             if (c.vec == 2)
-                hipLaunchKernelGGL(jacobi2d_parts_kernel<2>, grid, block, 0, s, pk, L0.ext[1], L0.lo[1], L0.hi[1],
-                                   col0, c.tile, c.march, gx, c.order);
+                JPARTS_LAUNCH(2, 2);
             else
-                hipLaunchKernelGGL(jacobi2d_parts_kernel<1>, grid, block, 0, s, pk, L0.ext[1], L0.lo[1], L0.hi[1],
-                                   col0, c.tile, c.march, gx, c.order);
+                JPARTS_LAUNCH(1, 2);
+#undef JPARTS_LAUNCH
         } else {
 #define PARTS_ARGS                                                                                                \
     pk, L0.ext[1], L0.ext[2], L0.lo[1], L0.hi[1], L0.lo[2], L0.hi[2], col0, c.tile, c.march, L0.scalars[0], \
         wg_partials, gx, gy, c.order
-#define PARTS_LAUNCH(V, R)                                                                          \
-    do {                                                                                            \
-        if (res)                                                                                    \
-            hipLaunchKernelGGL((heat3d_parts_kernel<V, R, true>), grid, block, 0, s, PARTS_ARGS);  \
-        else                                                                                        \
-            hipLaunchKernelGGL((heat3d_parts_kernel<V, R, false>), grid, block, 0, s, PARTS_ARGS); \
+#define PARTS_LAUNCH(V, R)                                                                             \
+    do {                                                                                               \
+        if (res)                                                                                       \
+            hipLaunchKernelGGL((heat3d_parts_kernel<V, R, true, 2>), grid, block, 0, s, PARTS_ARGS);  \
+        else                                                                                           \
+            hipLaunchKernelGGL((heat3d_parts_kernel<V, R, false, 2>), grid, block, 0, s, PARTS_ARGS); \
     } while (0)
             if (c.vec == 2) {
                 switch (c.rows) {

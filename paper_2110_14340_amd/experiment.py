@@ -32,7 +32,8 @@ def _sweep(ctx, u, v, cfg):
 
 def graph_time(shapes, datas, configs, reps=10, keep_outputs=False):
     """Enters every loop's arrays with its configuration's K, captures all
-    sweeps into one graph, and returns (median ms of `reps` replays, outputs)."""
+    sweeps into one graph, and returns (median ms of `reps` replays, the
+    batch's launch counts, outputs or None)."""
     K = max(c["K"] for c in configs)
     ctx = jacc.Context(max(2, K))
     ins, outs = [], []
