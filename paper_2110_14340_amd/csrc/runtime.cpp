@@ -19,6 +19,7 @@
 #include <dlfcn.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -326,6 +327,20 @@ struct jacc_ctx {
     int tune_mode = 0;       // loops without a configuration: 0 model pick, 1 defaults, 2 tuned
     std::string tune_db;     // timing database of tune_mode 2 (empty: none)
     std::map<std::vector<int64_t>, jacc_config> tuned;  // tune_mode 2 picks per loop signature
+    // per-loop records (JACC_LOG): JSON lines; with JACC_LOG_TIMES a loop
+    // that runs on one stream is timed by events around its work, read back
+    // at the next synchronisation (or when many are pending)
+    FILE *log = nullptr;
+    bool log_times = false;
+    int64_t log_seq = 0;
+    int64_t log_copies = 0, log_copy_bytes = 0;  // running totals of device copies
+    struct LogRec {
+        std::string json;  // the record without its timing fields and closing brace
+        double work = 0;   // algorithmic bytes (or flop when flop)
+        bool flop = false;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+    };
+    std::vector<LogRec> log_pending;
     jacc_allocator alloc{};
     bool use_hipmalloc = true;
     bool own_streams = false;
@@ -672,6 +687,8 @@ int issue_copy(jacc_ctx *c, Array *A, int q, int p, Range r, int s) {
     }
     rc = move_rows(c, A, 3, q, p, r, s);
     if (rc) return rc;
+    c->log_copies++;
+    c->log_copy_bytes += (r.hi - r.lo) * (int64_t)(A->pdim == 0 ? A->row_bytes : A->esize * A->d.extent[0]);
     c->st[s].seq++;
     trace(c, JACC_OP_COPY, s, A->id, q, p, 0, r.lo, r.hi, c->st[s].seq);
     return post_op(c);
@@ -1208,8 +1225,19 @@ int band_cache(jacc_ctx *c, Array **arr, int p, Range rows, int bands, BandCache
     return JACC_OK;
 }
 
+// What a loop call did, for its JACC_LOG record.
+struct LoopNote {
+    int K = 0, nrun = 0;
+    bool packed = false;
+    jk::Cfg cfg{};
+    double cells = 0;  // iterations of the box
+    double work = 0;   // algorithmic bytes (flop for GEMM); 0 where none is defined
+    bool flop = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;  // around the loop's work on its one stream
+};
+
 int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc_arg *args, const double *scalars,
-              int nscalars, int slot, double *red_host, const jacc_config *cfg) {
+              int nscalars, int slot, double *red_host, const jacc_config *cfg, LoopNote *note = nullptr) {
     const bool want_red = slot >= 0 || red_host;
     jacc_config picked;
     if (!cfg && c->tune_mode != 1 && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) && nargs == 2 &&
@@ -1314,6 +1342,38 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
         packed = total <= kWgCapacity;
     }
     auto stream_for = [&](int p) { return (one_stream || persistent) ? 0 : (base + (packed ? 0 : p)) % ns; };
+    if (note) {
+        note->K = K;
+        note->packed = packed;
+        note->cfg = L.cfg;
+        for (int p = 0; p < K; ++p) note->nrun += !plan[p].iters.empty();
+        double cells = 1;
+        for (int d = 0; d < b->ndim; ++d) cells *= (double)(b->hi[d] - b->lo[d]);
+        note->cells = cells;
+        switch (kind) {
+            case JACC_LOOP_JACOBI2D:
+            case JACC_LOOP_HEAT3D: note->work = 16.0 * cells; break;
+            case JACC_LOOP_SUM: note->work = 8.0 * cells * (double)arr[0]->row_elems; break;
+            case JACC_LOOP_GEMM:
+                note->work = 2.0 * cells * (double)arr[0]->d.extent[1];
+                note->flop = true;
+                break;
+            case JACC_LOOP_SPMV_CSR: {  // nnz of the rows from the caller's row_ptr
+                const int32_t *rp = (const int32_t *)args[0].host;
+                const double nnz = (double)rp[b->hi[0]] - (double)rp[b->lo[0]];
+                note->work = 4.0 * (cells + 1) + 12.0 * nnz + 16.0 * cells;
+                break;
+            }
+            case JACC_LOOP_SCATTER_SQ: note->work = 20.0 * cells; break;
+            default: break;
+        }
+        if (c->log_times && live(c) && (packed || K == 1 || one_stream)) {
+            const int s0 = stream_for(0);
+            HIPCHK(c, hipEventCreate(&note->e0), "hipEventCreate");
+            HIPCHK(c, hipEventCreate(&note->e1), "hipEventCreate");
+            HIPCHK(c, hipEventRecord(note->e0, c->st[s0].s), "hipEventRecord");
+        }
+    }
     // rows of its slab a partition may write: a filtered output entered
     // whole takes private writes anywhere in the partition's replica
     int first_run = 0;  // first partition with iterations (a duplicated loop's reference replica)
@@ -1685,7 +1745,77 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
                 *red_host = 0.0;
         }
     }
+    if (note && note->e1) HIPCHK(c, hipEventRecord(note->e1, c->st[stream_for(0)].s), "hipEventRecord");
     return JACC_OK;
+}
+
+const char *kind_name(int kind) {
+    switch (kind) {
+        case JACC_LOOP_JACOBI2D: return "JACOBI2D";
+        case JACC_LOOP_HEAT3D: return "HEAT3D";
+        case JACC_LOOP_SUM: return "SUM";
+        case JACC_LOOP_GEMM: return "GEMM";
+        case JACC_LOOP_SPMV_CSR: return "SPMV_CSR";
+        case JACC_LOOP_SCATTER_SQ: return "SCATTER_SQ";
+        case JACC_LOOP_PRED_CHAIN: return "PRED_CHAIN";
+        default: return "?";
+    }
+}
+
+// Writes one JSON line: the record's fields plus its timing (ms < 0: none).
+void log_write(jacc_ctx *c, const jacc_ctx::LogRec &r, double ms) {
+    std::string line = r.json;
+    char buf[160];
+    if (ms < 0 || r.work <= 0) {
+        snprintf(buf, sizeof buf, ", \"ms\": %s}\n", ms < 0 ? "null" : std::to_string(ms).c_str());
+    } else if (r.flop) {
+        snprintf(buf, sizeof buf, ", \"ms\": %.6f, \"tflops\": %.3f}\n", ms, r.work / (ms * 1e-3) / 1e12);
+    } else {
+        const double gbps = r.work / (ms * 1e-3) / 1e9;
+        snprintf(buf, sizeof buf, ", \"ms\": %.6f, \"gbps\": %.1f, \"frac_hbm_peak\": %.4f}\n", ms, gbps,
+                 gbps / 8000.0);
+    }
+    line += buf;
+    fputs(line.c_str(), c->log);
+}
+
+// Resolves and writes the pending timed records (their events complete).
+void log_flush(jacc_ctx *c) {
+    if (!c->log) return;
+    for (auto &r : c->log_pending) {
+        float ms = -1.0f;
+        if (r.e1 && hipEventSynchronize(r.e1) == hipSuccess && hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess)
+            ms = -1.0f;
+        log_write(c, r, ms);
+        if (r.e0) (void)hipEventDestroy(r.e0);
+        if (r.e1) (void)hipEventDestroy(r.e1);
+    }
+    c->log_pending.clear();
+    fflush(c->log);
+}
+
+void log_loop(jacc_ctx *c, int kind, const LoopNote &n, int64_t copies, int64_t copy_bytes, double issue_us) {
+    char buf[512];
+    snprintf(buf, sizeof buf,
+             "{\"loop\": %lld, \"kind\": \"%s\", \"K\": %d, \"partitions_run\": %d, \"packed\": %s, "
+             "\"cfg\": {\"bx\": %d, \"by\": %d, \"tile\": %d, \"vec\": %d, \"order\": %d, \"march\": %d, "
+             "\"rows\": %d, \"persistent\": %d}, \"cells\": %.0f, \"copies\": %lld, \"copy_bytes\": %lld, "
+             "\"%s\": %.0f, \"issue_us\": %.2f",
+             (long long)c->log_seq++, kind_name(kind), n.K, n.nrun, n.packed ? "true" : "false", n.cfg.bx, n.cfg.by,
+             n.cfg.tile, n.cfg.vec, n.cfg.order, n.cfg.march, n.cfg.rows, n.cfg.persistent, n.cells,
+             (long long)copies, (long long)copy_bytes, n.flop ? "flop" : "algorithmic_bytes", n.work, issue_us);
+    jacc_ctx::LogRec r;
+    r.json = buf;
+    r.work = n.work;
+    r.flop = n.flop;
+    r.e0 = n.e0;
+    r.e1 = n.e1;
+    if (!r.e1) {
+        log_write(c, r, -1.0);
+        return;
+    }
+    c->log_pending.push_back(r);
+    if (c->log_pending.size() >= 256) log_flush(c);
 }
 
 // ---- batches ----------------------------------------------------------------
@@ -1840,6 +1970,17 @@ int jacc_init(jacc_ctx **out, int K, void *const *streams, const jacc_allocator 
         c->markers = (flags & JACC_INIT_MARKERS) != 0;
         c->tune_mode = tune_mode;
         if (const char *db = getenv("JACC_TUNE_DB")) c->tune_db = db;
+        if (const char *lp = getenv("JACC_LOG")) {
+            if (*lp) {
+                c->log = fopen(lp, "a");
+                if (!c->log) {
+                    g_init_err = std::string("cannot open JACC_LOG file ") + lp;
+                    delete c;
+                    return JACC_ERR_INVALID;
+                }
+            }
+        }
+        c->log_times = env_on("JACC_LOG_TIMES");
         if (alloc) {
             c->alloc = *alloc;
             c->use_hipmalloc = false;
@@ -1914,6 +2055,14 @@ int jacc_finalize(jacc_ctx *c) {
     if (!c) return JACC_ERR_INVALID;
     int status = c->status;
     try {
+        if (c->log) {
+            if (!c->status && !c->dry)
+                for (auto &S : c->st)
+                    if (S.s) (void)hipStreamSynchronize(S.s);
+            log_flush(c);
+            fclose(c->log);
+            c->log = nullptr;
+        }
         if (c->model && c->model_release) c->model_release(c->model);  // its buffers come from this context
         c->model = nullptr;
         if (c->cur) {  // abandon an open capture
@@ -2098,7 +2247,11 @@ int jacc_update(jacc_ctx *c, void *host, int dir, int64_t row_lo, int64_t row_hi
             return set_err(c, JACC_ERR_INVALID, "bad row range [%lld,%lld)", (long long)row_lo, (long long)row_hi);
         Range r{row_lo, row_hi};
         if (r.empty()) return JACC_OK;
-        if (dir == JACC_UPDATE_HOST) return gather(c, A, r);
+        if (dir == JACC_UPDATE_HOST) {
+            const int rc = gather(c, A, r);
+            if (!rc) log_flush(c);
+            return rc;
+        }
         if (dir != JACC_UPDATE_DEVICE) return set_err(c, JACC_ERR_INVALID, "bad direction %d", dir);
         for (int p = 0; p < A->K; ++p) {
             Range x = isect(r, A->slabs[p].rows);
@@ -2119,7 +2272,19 @@ int jacc_parallel_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, c
                        const jacc_config *cfg) {
     GUARD(c);
     try {
-        return loop_impl(c, kind, b, nargs, args, scalars, nscalars, reduce_slot, reduce_host, cfg);
+        if (!c->log || c->cur) return loop_impl(c, kind, b, nargs, args, scalars, nscalars, reduce_slot, reduce_host, cfg);
+        LoopNote note;
+        const int64_t c0 = c->log_copies, b0 = c->log_copy_bytes;
+        const auto t0 = std::chrono::steady_clock::now();
+        const int rc = loop_impl(c, kind, b, nargs, args, scalars, nscalars, reduce_slot, reduce_host, cfg, &note);
+        const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+        if (rc != JACC_OK) {
+            if (note.e0) (void)hipEventDestroy(note.e0);
+            if (note.e1) (void)hipEventDestroy(note.e1);
+            return rc;
+        }
+        log_loop(c, kind, note, c->log_copies - c0, c->log_copy_bytes - b0, us);
+        return rc;
     } catch (const std::bad_alloc &) {
         return set_err(c, JACC_ERR_ALLOC, "host allocation failed");
     } catch (...) {
@@ -2131,7 +2296,9 @@ int jacc_wait(jacc_ctx *c) {
     GUARD(c);
     Marker mk(c, "jacc wait");
     if (c->cur) return set_err(c, JACC_ERR_INVALID, "jacc_wait inside a batch");
-    return sync_all(c);
+    const int rc = sync_all(c);
+    if (!rc) log_flush(c);
+    return rc;
 }
 
 int jacc_reduction_get(jacc_ctx *c, int slot, double *out) {

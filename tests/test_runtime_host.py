@@ -1006,3 +1006,46 @@ def test_sum_packs_its_partitions():
         assert len([t for t in ops if t["op"] == "COMBINE"]) == 1
         assert race_check(ops) == [] and freshness_check(ops) == []
         c.close()
+
+
+# ------------------------------------------------------------------ per-loop records
+def test_loop_log_records_plan_facts(monkeypatch, tmp_path):
+    """JACC_LOG: one JSON line per loop call outside batches, with the
+    partition count, packing, launch configuration, cells, the device
+    copies and bytes the call issued (equal to the trace's copies) and the
+    algorithmic bytes; timing fields are null without the device."""
+    import json
+    path = tmp_path / "loops.jsonl"
+    monkeypatch.setenv("JACC_LOG", str(path))
+    c = jacc.Context(4, flags=DRY | jacc.INIT_LAZY)
+    a = np.zeros((66, 20))
+    b = np.zeros((66, 20))
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    c.trace_clear()
+    c.jacobi2d(a, b)
+    c.jacobi2d(b, a)
+    x = np.zeros(1000)
+    c.enter(x)
+    c.sum(x, slot=0, sync=False)
+    copies = [t for t in c.trace() if t["op"] == "COPY"]
+    c.batch_begin()
+    c.jacobi2d(a, b)  # inside a batch: no record
+    c.batch_end()
+    c.close()
+    recs = [json.loads(line) for line in path.read_text().splitlines()]
+    assert [r["kind"] for r in recs] == ["JACOBI2D", "JACOBI2D", "SUM"]
+    assert [r["loop"] for r in recs] == [0, 1, 2]
+    assert all(r["K"] == 4 and r["packed"] and r["partitions_run"] == 4 and r["ms"] is None for r in recs)
+    assert recs[0]["cells"] == 64 * 18 and recs[0]["algorithmic_bytes"] == 16 * 64 * 18
+    assert recs[2]["algorithmic_bytes"] == 8 * 1000
+    assert recs[0]["copies"] == 0 and recs[1]["copies"] == 6 and recs[1]["copy_bytes"] == 6 * 20 * 8
+    assert sum(r["copies"] for r in recs) == len(copies)
+    assert recs[0]["cfg"]["bx"] == 256 and recs[0]["cfg"]["tile"] == 4
+
+
+def test_loop_log_unwritable_path_refused(monkeypatch, tmp_path):
+    monkeypatch.setenv("JACC_LOG", str(tmp_path / "missing_dir" / "x.jsonl"))
+    h = ctypes.c_void_p()
+    assert jacc.lib().jacc_init(ctypes.byref(h), 2, None, None, DRY) == jacc.ERR_INVALID
+    assert "JACC_LOG" in jacc.lib().jacc_last_error(None).decode()
