@@ -380,7 +380,8 @@ def main():
     if not args.no_learned:
         log("batched / learned experiment")
         from paper_2110_14340_amd import experiment
-        result["learned"], _ = experiment.run(log=log)
+        # 96 training shapes (48 2-D, 48 3-D), medians of 3 amortised samples
+        result["learned"], _ = experiment.run(log=log, train2d=48, train3d=48, tune_reps=3)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(u0)

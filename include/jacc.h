@@ -377,9 +377,11 @@ const char *jacc_last_error(const jacc_ctx *ctx);
  *
  * jacc_batch_begin starts stream capture on stream 0: the following
  * jacc_parallel_loop calls are planned as usual (copies, launches) but
- * recorded into a single-stream graph instead of executed.  Loops whose configuration has persistent = 1 are not
- * launched one by one: consecutive independent ones are packed into one
- * persistent-kernel launch that walks a task table of all their tiles.  No
+ * recorded into a single-stream graph instead of executed.  Loops whose
+ * configuration has persistent = 1 are not launched one by one: they gather
+ * into one persistent-kernel launch that walks a task table of all their
+ * tiles, launched when a later loop touches one of their arrays or the
+ * batch ends (loops on other arrays are recorded ahead of it).  No
  * data_enter/exit, update, wait or synchronous reduction is allowed inside.
  *
  * jacc_batch_end closes the capture, instantiates the graph, runs it once
@@ -535,9 +537,12 @@ typedef struct {
  * and scalars as for jacc_parallel_loop; the arguments must be present and
  * give the shapes and halos).  Every candidate runs on scratch replicas of
  * the two arrays entered with the candidate's K (the caller's arrays are
- * never written), as a one-loop captured graph replayed `warmup` times
- * untimed and `reps` times timed with HIP events; candidates already in the
- * database are not run again.  The choice is the smallest median, ties to
+ * never written), as a captured graph of S sweeps alternating between the
+ * two replicas, replayed `warmup` times untimed and `reps` times timed with
+ * HIP events; each replay's time divided by S is a sample (S even, at most
+ * 8, chosen from a one-sweep graph of the first candidate so that a replay
+ * lasts about 0.1 ms: small loops are then timed by their work more than by
+ * the graph launch).  Candidates already in the database are not run again.  The choice is the smallest median, ties to
  * the lowest candidate index.  *best receives it; medians (optional, `cap`
  * doubles) each candidate's median in ms and *ncand their number.
  * JACC_ERR_UNSUPPORTED for other loop kinds and in dry-run contexts. */

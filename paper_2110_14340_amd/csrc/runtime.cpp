@@ -1271,8 +1271,10 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     Marker mk_issue(c, "jacc issue kind=%d K=%d", kind, arr[0]->K);
     const bool persistent = L.cfg.persistent != 0;
     // a pending persistent group is launched before anything that touches
-    // its arrays, and before any non-persistent loop
-    bool conflict = !persistent;
+    // its arrays; loops on other arrays (persistent or not) go ahead of it,
+    // so the small loops of a batch gather into few launches whatever the
+    // order they are issued in
+    bool conflict = false;
     for (int i = 0; i < nargs && !conflict; ++i) conflict = pending_touches(c, arr[i]);
     if (conflict) {
         rc = flush_group(c);

@@ -276,21 +276,43 @@ int make_replica(jacc_ctx *c, const jacc_arg *args, int K, Replica &r) {
 }
 
 // One candidate as a one-loop captured graph, timed by replays.
+// Times one candidate: a graph of `sweeps` captured sweeps, alternating
+// between the two scratch arrays, replayed `warmup` times untimed and
+// `reps` times timed; ms receives the per-sweep time of each replay (the
+// graph launch's own cost spread over the sweeps, so that small loops are
+// not timed as launch overhead).
 int time_candidate(jacc_ctx *c, int kind, const jacc_bounds *b, const jacc_arg *args, const double *scalars,
-                   int nscalars, const jacc_config &cfg, int warmup, int reps, std::vector<double> &ms) {
+                   int nscalars, const jacc_config &cfg, int warmup, int reps, int sweeps, std::vector<double> &ms) {
     int rc = jacc_batch_begin(c);
     if (rc) return rc;
-    rc = jacc_parallel_loop(c, kind, b, 2, args, scalars, nscalars, -1, nullptr, &cfg);
+    jacc_arg back[2] = {args[0], args[1]};  // the reverse sweep: out read, in written
+    back[0].host = args[1].host;
+    back[1].host = args[0].host;
+    for (int k = 0; k < sweeps && !rc; ++k)
+        rc = jacc_parallel_loop(c, kind, b, 2, (k & 1) ? back : args, scalars, nscalars, -1, nullptr, &cfg);
     int g = -1;
     const int rc_end = jacc_batch_end(c, &g);
     if (!rc) rc = rc_end;
     ms.assign((size_t)reps, 0.0);
     if (!rc) rc = jacc_batch_time(c, g, warmup, reps, ms.data());
+    if (!rc)
+        for (double &v : ms) v /= sweeps;
     if (g >= 0) {
         const int rc2 = jacc_batch_destroy(c, g);
         if (!rc) rc = rc2;
     }
     return rc;
+}
+
+// Sweeps per timed graph: enough that one replay lasts about 0.1 ms (the
+// estimate from a one-sweep graph of the first candidate), even, at most 8
+// (longer graphs cost more to capture and instantiate than they gain).
+int sweeps_for(double one_sweep_ms) {
+    if (!(one_sweep_ms > 0)) return 1;
+    int n = (int)std::ceil(0.1 / one_sweep_ms);
+    if (n <= 1) return 1;
+    n = std::min(8, n + (n & 1));
+    return n;
 }
 
 int loop_shape(jacc_ctx *c, int kind, int nargs, const jacc_arg *args, int64_t *e, int *ndim, int *K) {
@@ -648,6 +670,7 @@ int jacc_tune(jacc_ctx *ctx, int kind, const jacc_bounds *b, int nargs, const ja
         auto &sec = db.sections[build_key(ctx)];
         std::vector<double> med(cands.size());
         bool added = false;
+        int sweeps = 0;  // per timed graph, set from the first candidate timed
         size_t i = 0;
         while (i < cands.size()) {  // candidates are grouped by K
             const int K = cands[i].K;
@@ -668,7 +691,13 @@ int jacc_tune(jacc_ctx *ctx, int kind, const jacc_bounds *b, int nargs, const ja
                 auto hit = sec.find(k);
                 if (hit == sec.end()) {
                     std::vector<double> ms;
-                    rc = time_candidate(ctx, kind, b, targs, scalars, nscalars, cands[q].cfg, warmup, reps, ms);
+                    if (sweeps == 0) {
+                        rc = time_candidate(ctx, kind, b, targs, scalars, nscalars, cands[q].cfg, 1, 3, 1, ms);
+                        if (rc) return rc;
+                        sweeps = sweeps_for(median_of(ms));
+                    }
+                    rc = time_candidate(ctx, kind, b, targs, scalars, nscalars, cands[q].cfg, warmup, reps, sweeps,
+                                        ms);
                     if (rc) return rc;
                     hit = sec.emplace(k, ms).first;
                     added = true;

@@ -118,7 +118,7 @@ def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=300, members=3, tune_re
         t0 = time.perf_counter()
         for li, sh in enumerate(train_shapes):
             tuner.tune(ctx, sh, _data(sh, 1000 + li), db_path=train_db, reps=tune_reps)
-            if li % 16 == 15:
+            if li % 8 == 7:
                 log(f"  tuned {li + 1}/{len(train_shapes)} training shapes")
         t_train_tune = time.perf_counter() - t0
         # 2. the GPU-trained ensemble, from the database, into a model file
@@ -149,7 +149,7 @@ def run(n2d=128, n3d=128, train2d=64, train3d=64, epochs=300, members=3, tune_re
             k_rule = eq1_partitions(t_dup, 8.0 * float(np.prod([d - 2 for d in sh])), nmax, peak)
             at_k = [i for i, c in enumerate(cands) if c["K"] == k_rule]
             rule.append(cands[min(at_k, key=lambda i: (meds[i], i))])
-            if li % 32 == 31:
+            if li % 8 == 7:
                 log(f"  tuned {li + 1}/{len(test_shapes)} test shapes")
         t_test_tune = time.perf_counter() - t0
     finally:
