@@ -275,7 +275,6 @@ int make_replica(jacc_ctx *c, const jacc_arg *args, int K, Replica &r) {
     return JACC_OK;
 }
 
-// One candidate as a one-loop captured graph, timed by replays.
 // Times one candidate: a graph of `sweeps` captured sweeps, alternating
 // between the two scratch arrays, replayed `warmup` times untimed and
 // `reps` times timed; ms receives the per-sweep time of each replay (the

@@ -2,8 +2,8 @@
 C entry points (jacc_candidates, jacc_features, jacc_tune, jacc_model_train,
 jacc_model_load, jacc_model_pick, jacc_choose).
 
-The candidate set, the features, the timing of candidates (one-loop captured
-graphs on scratch replicas, HIP events), the median and tie rule, the timing
+The candidate set, the features, the timing of candidates (captured graphs
+of several sweeps on scratch replicas, HIP events), the median and tie rule, the timing
 database keyed by device, HIP runtime and library build, the training of the
 GPU networks, the model file, the ensemble mean and the argmin all live in
 the library (csrc/tune.cpp, csrc/model.cpp, csrc/k_mlp.hip).  What stays here
