@@ -218,10 +218,10 @@ def extra_workloads(jacc, torch, inputs):
     # GEMM 4096^3 FP64 MFMA
     A, B = inputs.gemm_inputs(4096, 4096, 4096, seed=3)
     C = np.zeros((4096, 4096))
-    for K in (1, 4):
+    for K, whole, tag in ((1, True, ""), (4, True, ""), (4, jacc.SHARED, "_shared")):
         c = jacc.Context(K)
         c.enter(A)
-        c.enter(B, whole=True)
+        c.enter(B, whole=whole)
         c.enter(C, clause=jacc.CREATE)
 
         # HIP events around back-to-back launches, median of 10
@@ -229,7 +229,7 @@ def extra_workloads(jacc, torch, inputs):
         dt = float(np.median(c.time_loop(jacc.GEMM, jacc.bounds((0, 4096), (0, 4096)), gargs, warmup=2,
                                           reps=10))) / 1e3
         tf = 2 * 4096 ** 3 / dt / 1e12
-        out[f"gemm_4096_K{K}"] = {"tflops": round(tf, 2), "ms": round(dt * 1e3, 3),
+        out[f"gemm_4096_K{K}{tag}"] = {"tflops": round(tf, 2), "ms": round(dt * 1e3, 3),
                                   "frac_fp64_peak": round(tf / FP64_MFMA_PEAK_TFLOPS, 3)}
         c.close()
     del A, B, C
@@ -238,12 +238,13 @@ def extra_workloads(jacc, torch, inputs):
     rp, col, val, xv = inputs.csr_matrix(nr, nr, 16, seed=4)
     y = np.zeros(nr)
     alg = rp.nbytes + col.nbytes + val.nbytes + xv.nbytes + y.nbytes
-    for K in (1, 4):
+    # col, val and x replicated per partition, or one shared read-only copy
+    for K, whole, tag in ((1, True, ""), (4, True, ""), (4, jacc.SHARED, "_shared")):
         c = jacc.Context(K)
         c.enter(rp, halo=(1, 1))
-        c.enter(col, whole=True)
-        c.enter(val, whole=True)
-        c.enter(xv, whole=True)
+        c.enter(col, whole=whole)
+        c.enter(val, whole=whole)
+        c.enter(xv, whole=whole)
         c.enter(y, clause=jacc.CREATE)
 
         def sp():
@@ -251,7 +252,8 @@ def extra_workloads(jacc, torch, inputs):
             c.wait()
 
         dt = timed(sp, 10)
-        out[f"spmv_2^22_K{K}"] = {"gbps": round(alg / dt / 1e9, 1), "ms": round(dt * 1e3, 4), "nnz": int(col.size)}
+        out[f"spmv_2^22_K{K}{tag}"] = {"gbps": round(alg / dt / 1e9, 1), "ms": round(dt * 1e3, 4),
+                                       "nnz": int(col.size)}
         c.close()
     del rp, col, val, xv, y
     # 96 independent Jacobi grids (sides 64..1024), 2 sweeps each per pass:

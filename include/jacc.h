@@ -93,8 +93,13 @@ typedef enum { JACC_F64 = 0, JACC_F32 = 1, JACC_I32 = 2, JACC_I64 = 3 } jacc_dty
  * column of extent[0] elements, extent[1] apart in the host array.  Row
  * ranges everywhere in this interface (owner blocks, halos, access offsets,
  * updates) count such rows.  halo_lo/halo_hi are the largest distances (in
- * rows) below and above the owner block that loops will read.  whole != 0
- * keeps a full replica in every partition.  num_partitions: K of this array
+ * rows) below and above the owner block that loops will read.  whole = 1
+ * keeps a full replica in every partition (the paper's replicated
+ * allocation); whole = 2 keeps one full copy on the device that every
+ * partition reads (one GPU holds all partitions, so read-only data need not
+ * be duplicated): loops may only read it (a writing argument is
+ * JACC_ERR_INVALID) and update(DEVICE) refreshes the one copy.
+ * num_partitions: K of this array
  * (0 = the context's K; at most 64; with more partitions than the context has
  * streams, partition p runs on stream p mod the stream count).
  * A partition's slab of a part_dim 1 array holds its columns [lo, hi) as a
@@ -279,17 +284,18 @@ enum {
                                       update; batch capture and launch), for rocprofv3
                                       --marker-trace */
     JACC_INIT_NO_PACK = 1u << 10   /* a launch per partition on its own stream for every loop.
-                                      Default: outside batches, a JACOBI2D or HEAT3D loop of 2
-                                      to 16 row-split partitions without a FILTERED output runs
-                                      all its partitions in one launch on one stream, each
-                                      partition's tiles a run of the workgroups, in the loop's
-                                      configuration (halo pulls before it, mirror stores inside
-                                      it; a residual's partitions finalised by one launch and
-                                      combined in partition order: the same bits as a launch per
-                                      partition); JACC_INIT_SPLIT, SERIALIZE, per-partition
-                                      timing, and residuals whose workgroup partials of all
-                                      partitions exceed the stream's buffer keep a launch per
-                                      partition */
+                                      Default: outside batches, a JACOBI2D, HEAT3D, SUM or
+                                      column-banded SPMV_CSR loop of 2 to 16 row-split partitions
+                                      without a FILTERED output runs all its partitions in one
+                                      launch on one stream, each partition's tiles a run of the
+                                      workgroups, in the loop's configuration (halo pulls before
+                                      it, mirror stores inside it; reductions finalised per
+                                      partition by one launch and combined in partition order,
+                                      banded products combined by one launch: the same bits as a
+                                      launch per partition); JACC_INIT_SPLIT, SERIALIZE,
+                                      per-partition timing, and reductions whose workgroup
+                                      partials of all partitions exceed the stream's buffer keep
+                                      a launch per partition */
 };
 
 /* Create a context with K partitions (1 <= K <= 64; K = 0 takes the

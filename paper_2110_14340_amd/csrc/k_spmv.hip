@@ -149,12 +149,13 @@ __global__ void band_fill_kernel(const int32_t *__restrict__ rp, const int32_t *
 }
 
 // partial[b*n + r] = sum over row r's entries of band b (G lanes per row,
-// entries k, k+G, ... per lane, then a fixed butterfly)
+// entries k, k+G, ... per lane, then a fixed butterfly); `wg` is the
+// workgroup's index within the partition's launch (a multiple of 8 from
+// the grid's start, so wg & 7 is still the XCD it runs on)
 template <int G>
-__global__ void __launch_bounds__(kBandThreads)
-spmv_band_kernel(const int32_t *__restrict__ bptr, const int32_t *__restrict__ bcol, const double *__restrict__ bval,
-                 const double *__restrict__ x, double *__restrict__ part, int64_t n, int S, int64_t chunks) {
-    const int64_t wg = blockIdx.x;
+__device__ __forceinline__ void band_block(const int32_t *__restrict__ bptr, const int32_t *__restrict__ bcol,
+                                           const double *__restrict__ bval, const double *__restrict__ x,
+                                           double *__restrict__ part, int64_t n, int S, int64_t chunks, int64_t wg) {
     const int xcd = (int)(wg & 7);
     const int64_t t = wg >> 3;
     const int pass = (int)(t / chunks);
@@ -171,6 +172,56 @@ spmv_band_kernel(const int32_t *__restrict__ bptr, const int32_t *__restrict__ b
 #pragma unroll
     for (int m = 1; m < G; m <<= 1) s += __shfl_xor(s, m, kWave);
     if (r < n && g == 0) part[(int64_t)band * n + r] = s;
+}
+
+template <int G>
+__global__ void __launch_bounds__(kBandThreads)
+spmv_band_kernel(const int32_t *__restrict__ bptr, const int32_t *__restrict__ bcol, const double *__restrict__ bval,
+                 const double *__restrict__ x, double *__restrict__ part, int64_t n, int S, int64_t chunks) {
+    band_block<G>(bptr, bcol, bval, x, part, n, S, chunks, blockIdx.x);
+}
+
+// The partitions of one banded product in one launch: partition q's
+// workgroups [wg_begin, wg_begin + 8*S*chunks) and, for the combine,
+// [comb_begin, comb_begin + ceil(n / kBandThreads)).  Descriptors are read
+// through the constant address space (their pointers are then known to be
+// global).
+struct SpmvPart {
+    const int32_t *bptr, *bcol;
+    const double *bval, *x;
+    double *part, *y;
+    int64_t n, r0, chunks, wg_begin, comb_begin;
+};
+struct SpmvParts {
+    SpmvPart p[kMaxPack];
+    int32_t n;
+};
+typedef const __attribute__((address_space(4))) SpmvPart ConstSpmvPart;
+
+template <int G>
+__global__ void __launch_bounds__(kBandThreads) spmv_band_parts_kernel(SpmvParts sp, int S) {
+    ConstSpmvPart *cp = (ConstSpmvPart *)&sp.p[0];
+    const int64_t b = blockIdx.x;
+    int q = 0;
+    for (int k = 1; k < sp.n; ++k)
+        if (cp[k].wg_begin <= b) q = k;
+    band_block<G>(cp[q].bptr, cp[q].bcol, cp[q].bval, cp[q].x, cp[q].part, cp[q].n, S, cp[q].chunks,
+                  b - cp[q].wg_begin);
+}
+
+__global__ void band_combine_parts_kernel(SpmvParts sp, int B) {
+    ConstSpmvPart *cp = (ConstSpmvPart *)&sp.p[0];
+    const int64_t b = blockIdx.x;
+    int q = 0;
+    for (int k = 1; k < sp.n; ++k)
+        if (cp[k].comb_begin <= b) q = k;
+    const double *part = cp[q].part;
+    double *y = cp[q].y;
+    const int64_t n = cp[q].n, r = (b - cp[q].comb_begin) * kBandThreads + threadIdx.x;
+    if (r >= n) return;
+    double s = 0.0;
+    for (int k = 0; k < B; ++k) s += part[(int64_t)k * n + r];
+    y[cp[q].r0 + r] = s;
 }
 
 // One lane per row and band, R rows per lane (rows r, r + blockDim, ...):
@@ -309,6 +360,51 @@ hipError_t launch_spmv_banded(const Launch &L, const BandBufs &bb, hipStream_t s
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(band_combine_kernel, dim3((unsigned)((n + kBandThreads - 1) / kBandThreads)), dim3(kBandThreads),
                        0, s, bb.part, n, bb.bands, (double *)L.a[4].ptr, r0);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_banded_parts(const Launch *L, const BandBufs *bb, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (n > kMaxPack) return hipErrorInvalidValue;
+    const int G = L[0].cfg.tile;
+    const int S = bb[0].bands / 8;
+    if (G != 1 && G != 2 && G != 4 && G != 8 && G != 16) return hipErrorInvalidValue;
+    SpmvParts sp{};
+    int64_t wg = 0, comb = 0;
+    for (int k = 0; k < n; ++k) {
+        const int64_t rows = L[k].hi[0] - L[k].lo[0];
+        if (rows <= 0) continue;
+        if (bb[k].bands != bb[0].bands) return hipErrorInvalidValue;
+        SpmvPart &d = sp.p[sp.n++];
+        d.bptr = bb[k].bptr;
+        d.bcol = bb[k].bcol;
+        d.bval = bb[k].bval;
+        d.x = (const double *)L[k].a[3].ptr;
+        d.part = bb[k].part;
+        d.y = (double *)L[k].a[4].ptr;
+        d.n = rows;
+        d.r0 = L[k].lo[0];
+        d.chunks = (rows + kBandThreads / G - 1) / (kBandThreads / G);
+        d.wg_begin = wg;
+        d.comb_begin = comb;
+        wg += 8 * (int64_t)S * d.chunks;
+        comb += (rows + kBandThreads - 1) / kBandThreads;
+    }
+    if (sp.n == 0) return hipSuccess;
+    if (wg > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+#define SPMV_BAND_PARTS(GG) \
+    hipLaunchKernelGGL((spmv_band_parts_kernel<GG>), dim3((unsigned)wg), dim3(kBandThreads), 0, s, sp, S)
+    switch (G) {
+        case 1: SPMV_BAND_PARTS(1); break;
+        case 2: SPMV_BAND_PARTS(2); break;
+        case 4: SPMV_BAND_PARTS(4); break;
+        case 16: SPMV_BAND_PARTS(16); break;
+        default: SPMV_BAND_PARTS(8); break;
+    }
+#undef SPMV_BAND_PARTS
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(band_combine_parts_kernel, dim3((unsigned)comb), dim3(kBandThreads), 0, s, sp, bb[0].bands);
     return hipGetLastError();
 }
 

@@ -162,6 +162,10 @@ int64_t band_width(int64_t ncols, int bands);
 int64_t band_scan_blocks(int64_t len);
 hipError_t build_bands(const Launch &L, const BandBufs &bb, hipStream_t s);
 hipError_t launch_spmv_banded(const Launch &L, const BandBufs &bb, hipStream_t s);
+// The banded products of n partitions (their band-major copies bb[k], the
+// same band count) in one launch, then one combine launch (the same bits as
+// a launch per partition).
+hipError_t launch_spmv_banded_parts(const Launch *L, const BandBufs *bb, int n, hipStream_t s);
 hipError_t launch_scatter(const Launch &L, hipStream_t s);
 hipError_t launch_chain(const Launch &L, hipStream_t s);
 

@@ -216,6 +216,7 @@ struct Array {
     int pdim = 0;  // partitioned dimension: 0, or 1 (a 2-D array split into column blocks)
     int refs = 1;
     bool whole = false;
+    bool shared = false;  // whole == 2: one device copy that every partition reads (never written by loops)
     std::vector<Slab> slabs;
     IntervalMap<int32_t> writer;  // -1: host data, valid in every holder
     std::vector<IntervalSet> valid;
@@ -586,6 +587,7 @@ int fork_from0(jacc_ctx *c) {
 // after the first).
 int hazard(jacc_ctx *c, Array *A, int p, Range r, bool write, int s, int wkind = 2) {
     if (r.empty()) return JACC_OK;
+    if (A->shared) p = 0;  // every partition's slab is the one copy
     Slab &sl = A->slabs[p];
     static thread_local std::vector<std::pair<int, int64_t>> need;  // (stream, op) to wait for
     need.clear();
@@ -847,7 +849,7 @@ void drop_bands(jacc_ctx *c, int array_id) {
 
 void free_array(jacc_ctx *c, Array *A) {
     drop_bands(c, A->id);
-    for (int p = 0; p < A->K; ++p) {
+    for (int p = 0; p < (A->shared ? 1 : A->K); ++p) {
         trace(c, JACC_OP_FREE, -1, A->id, -1, p, 0, A->slabs[p].rows.lo, A->slabs[p].rows.hi, 0);
         dev_free(c, A->slabs[p].dev);
     }
@@ -972,6 +974,9 @@ int prepare_loop(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const j
             return set_err(c, JACC_ERR_UNSUPPORTED, "argument %d is an interior pointer of array %d", i, A->id);
         if (K < 0) K = A->K;
         if (A->K != K) return set_err(c, JACC_ERR_UNSUPPORTED, "arguments are partitioned with different K");
+        if ((args[i].mode & JACC_WRITE) && A->shared)
+            return set_err(c, JACC_ERR_INVALID, "argument %d writes array %d, entered as one shared read-only copy",
+                           i, A->id);
         arr[i] = A;
     }
     // arrays split along dimension 1 (column blocks) take the 2-D stencil
@@ -1326,7 +1331,8 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
     // partitions must fit the stream's partial buffer
     bool packed = !c->cur && !c->no_pack && !c->serialize && !c->time_parts && !c->split && K > 1 &&
                   K <= jk::kMaxPack && !persistent && !dup &&
-                  (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D || kind == JACC_LOOP_SUM) &&
+                  (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D || kind == JACC_LOOP_SUM ||
+                   (kind == JACC_LOOP_SPMV_CSR && L.cfg.order == 4 && L.cfg.rows <= 1)) &&
                   !(args[primary].mode & JACC_FILTERED) && P->pdim == 0 && !P->whole;
     if (packed && want_red) {
         int64_t total = 0;
@@ -1504,6 +1510,7 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
                 }
         }
         std::vector<jk::Launch> lps;
+        std::vector<jk::BandBufs> bbs;  // banded SpMV: each partition's band-major copy
         std::vector<std::vector<std::pair<int, Range>>> mirs((size_t)K);
         for (int p = 0; p < K; ++p) {
             const PartPlan &pp = plan[p];
@@ -1531,6 +1538,14 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
                 order.push_back(p);
                 red_streams.push_back(s);
             }
+            if (kind == JACC_LOOP_SPMV_CSR) {
+                BandCache *bc = nullptr;
+                rc = band_cache(c, arr, p, pp.iters, 8 * LP.cfg.by, &bc);
+                if (rc) return rc;
+                if (live(c) && !bc->built) HIPCHK(c, jk::build_bands(LP, bc->bb, c->st[s].s), "banded SpMV build");
+                bc->built = true;
+                bbs.push_back(bc->bb);
+            }
             lps.push_back(LP);
         }
         if (inject_fault(c, 2)) {
@@ -1539,8 +1554,10 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
         }
         if (live(c))
             HIPCHK(c,
-                   jk::launch_parts(lps.data(), (int)lps.size(), c->wg + (size_t)s * kWgCapacity, kWgCapacity,
-                                    c->st[s].s),
+                   kind == JACC_LOOP_SPMV_CSR
+                       ? jk::launch_spmv_banded_parts(lps.data(), bbs.data(), (int)lps.size(), c->st[s].s)
+                       : jk::launch_parts(lps.data(), (int)lps.size(), c->wg + (size_t)s * kWgCapacity, kWgCapacity,
+                                          c->st[s].s),
                    "kernel launch");
         c->st[s].seq++;
         for (int p = 0; p < K; ++p)
@@ -2134,6 +2151,7 @@ int jacc_data_enter(jacc_ctx *c, void *host, const jacc_array_desc *d, int claus
         if (d->part_dim != 0 && d->part_dim != 1) return set_err(c, JACC_ERR_INVALID, "part_dim must be 0 or 1");
         if (d->part_dim == 1 && d->ndim != 2)
             return set_err(c, JACC_ERR_UNSUPPORTED, "arrays are split along dimension 1 only when they are 2-D");
+        if (d->whole < 0 || d->whole > 2) return set_err(c, JACC_ERR_INVALID, "whole must be 0, 1 or 2");
         if (d->part_dim != 0 && d->whole)
             return set_err(c, JACC_ERR_INVALID, "an array entered whole is not split: part_dim must be 0");
         const int64_t E = d->extent[d->part_dim];
@@ -2170,6 +2188,7 @@ int jacc_data_enter(jacc_ctx *c, void *host, const jacc_array_desc *d, int claus
         A->esize = es;
         A->row_bytes = (size_t)A->row_elems * es;
         A->whole = d->whole != 0;
+        A->shared = d->whole == 2;
         A->slabs.resize(K);
         A->valid.resize(K);
         A->writer.init(0, A->E, -1);
@@ -2186,19 +2205,23 @@ int jacc_data_enter(jacc_ctx *c, void *host, const jacc_array_desc *d, int claus
             S.pitch = A->pdim == 0 ? A->row_elems : ((sl.hi - S.base + 1) & ~(int64_t)1);
             S.acc.init(sl.lo, sl.hi, Access{});
             A->valid[p].add(sl);
+            if (A->shared && p > 0) {  // the same device copy as partition 0
+                S.dev = A->slabs[0].dev;
+                continue;
+            }
             const size_t stored = A->pdim == 0 ? (size_t)(sl.hi - sl.lo) * A->row_bytes
                                                : (size_t)S.pitch * (size_t)d->extent[0] * A->esize;
             rc = dev_alloc(c, stored, &S.dev);
             if (!rc) trace(c, JACC_OP_ALLOC, -1, A->id, -1, p, 0, sl.lo, sl.hi, 0);
         }
         if (rc) {
-            for (int p = 0; p < K; ++p) dev_free(c, A->slabs[p].dev);
+            for (int p = 0; p < (A->shared ? 1 : K); ++p) dev_free(c, A->slabs[p].dev);
             delete A;
             return rc;
         }
         c->present[A->host] = A;
         if (clause == JACC_COPYIN || clause == JACC_COPY) {
-            for (int p = 0; p < K; ++p) {
+            for (int p = 0; p < (A->shared ? 1 : K); ++p) {
                 rc = h2d_rows(c, A, p, A->slabs[p].rows);
                 if (rc) return rc;
             }
@@ -2258,8 +2281,10 @@ int jacc_update(jacc_ctx *c, void *host, int dir, int64_t row_lo, int64_t row_hi
         for (int p = 0; p < A->K; ++p) {
             Range x = isect(r, A->slabs[p].rows);
             if (x.empty()) continue;
-            int rc = h2d_rows(c, A, p, x);
-            if (rc) return rc;
+            if (!A->shared || p == 0) {
+                int rc = h2d_rows(c, A, p, x);
+                if (rc) return rc;
+            }
             A->valid[p].add(x);
         }
         A->writer.assign(r, -1);

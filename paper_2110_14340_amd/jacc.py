@@ -25,6 +25,7 @@ READ, WRITE, READWRITE, FILTERED = 1, 2, 3, 4
 JACOBI2D, HEAT3D, SUM, GEMM, SPMV_CSR, SCATTER_SQ, PRED_CHAIN = 1, 2, 3, 4, 5, 6, 7
 INIT_DRYRUN, INIT_TRACE, INIT_SERIALIZE, INIT_LAZY, INIT_SPLIT, INIT_NO_SPLIT, INIT_EAGER = 1, 2, 4, 8, 16, 32, 64
 INIT_FORK_CAPTURE, INIT_POISON, INIT_MARKERS, INIT_NO_PACK = 128, 256, 512, 1024
+SHARED = 2  # jacc_array_desc.whole: one read-only copy for every partition
 OP_NAMES = {1: "ALLOC", 2: "FREE", 3: "H2D", 4: "D2H", 5: "COPY", 6: "KERNEL", 7: "RECORD", 8: "WAIT",
             9: "SYNC", 10: "COMBINE", 11: "ACCESS", 12: "JOIN", 13: "POISON"}
 STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOT_PRESENT", -3: "ALREADY_PRESENT", -4: "RANGE", -5: "ALLOC",
@@ -383,6 +384,8 @@ class Context:
 
     # -- data ----------------------------------------------------------------
     def enter(self, a, halo=(0, 0), whole=False, K=0, clause=COPYIN, part_dim=0, raw=False):
+        """jacc_data_enter; whole: False (partitioned), True (a replica per
+        partition) or SHARED (one read-only copy for every partition)."""
         assert a.flags.c_contiguous
         d = ArrayDesc()
         d.dtype = _DTYPES[a.dtype]

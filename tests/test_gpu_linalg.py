@@ -70,11 +70,11 @@ def test_sum_integer_exact_and_deferred_slots():
 
 
 # ------------------------------------------------------------------ GEMM
-def _gemm_dev(A, B, K, slab=0, threads=0):
+def _gemm_dev(A, B, K, slab=0, threads=0, whole=True):
     C = np.zeros((A.shape[0], B.shape[1]))
     with context(K) as c:
         c.enter(A)
-        c.enter(B, whole=True)
+        c.enter(B, whole=whole)
         c.enter(C, clause=jacc.CREATE)
         c.gemm(A, B, C, cfg=jacc.config(tile=slab, bx=threads) if (slab or threads) else None)
         c.exit(C, jacc.COPYOUT)
@@ -119,13 +119,13 @@ def test_gemm_4096_full_frobenius_and_integer_exact():
 
 
 # ------------------------------------------------------------------ SpMV
-def _spmv_dev(rp, col, val, x, K, cfg=None):
+def _spmv_dev(rp, col, val, x, K, cfg=None, whole=True):
     y = np.zeros(rp.size - 1)
     with context(K) as c:
         c.enter(rp, halo=(1, 1))
-        c.enter(col, whole=True)
-        c.enter(val, whole=True)
-        c.enter(x, whole=True)
+        c.enter(col, whole=whole)
+        c.enter(val, whole=whole)
+        c.enter(x, whole=whole)
         c.enter(y, clause=jacc.CREATE)
         c.spmv(rp, col, val, x, y, cfg=cfg)
         c.exit(y, jacc.COPYOUT)
@@ -214,6 +214,9 @@ def test_spmv_2_22_rows_k1_k4_every_row():
         assert np.array_equal(_spmv_dev(rp, col, val, x, 4, cfg), b1)  # band boundaries do not depend on K
         bad = np.flatnonzero(np.abs(b1 - ref) > bound)
         assert bad.size == 0, f"{bad.size} banded rows outside the bound, first {bad[:5]}"
+    say("  col, val and x as one shared read-only copy, K=4 (default and banded forms)")
+    assert np.array_equal(_spmv_dev(rp, col, val, x, 4, whole=jacc.SHARED), y4)
+    assert np.array_equal(_spmv_dev(rp, col, val, x, 4, cfg, whole=jacc.SHARED), b1)  # b1: the last banded form
 
 
 # ------------------------------------------------------------------ predicate-filtered scatter
@@ -232,3 +235,12 @@ def test_filtered_scatter_matches_oracle(n, K):
         c.scatter_sq(x, idx, o)
         c.exit(o)
     assert np.array_equal(o, ref)
+
+
+@pytest.mark.parametrize("M,N,L,K", [(200, 150, 130, 3), (300, 17, 1000, 4)])
+def test_gemm_shared_b_equals_replicated(M, N, L, K):
+    """B as one shared read-only copy gives the same bits as a replica per
+    partition."""
+    say(f"gemm shared B {M}x{N}x{L} K={K}")
+    A, B = inputs.gemm_inputs(M, N, L, seed=M + K)
+    assert np.array_equal(_gemm_dev(A, B, K, whole=jacc.SHARED), _gemm_dev(A, B, K))

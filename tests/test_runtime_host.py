@@ -1049,3 +1049,44 @@ def test_loop_log_unwritable_path_refused(monkeypatch, tmp_path):
     h = ctypes.c_void_p()
     assert jacc.lib().jacc_init(ctypes.byref(h), 2, None, None, DRY) == jacc.ERR_INVALID
     assert "JACC_LOG" in jacc.lib().jacc_last_error(None).decode()
+
+
+# ------------------------------------------------------------------ shared read-only copies
+def test_shared_whole_arrays_one_copy_read_by_every_partition():
+    """whole = SHARED: one allocation and one host-to-device copy, every
+    partition's reads ordered after that copy (accesses of all partitions
+    land on the one copy), update(DEVICE) writes it once, a loop that
+    writes it is refused, and the plans stay race-free and fresh."""
+    c = dry(4)
+    n = 50
+    rp = np.zeros(n + 1, dtype=np.int32)
+    col = np.zeros(3, dtype=np.int32)
+    val = np.zeros(3)
+    x = np.zeros(n)
+    y = np.zeros(n)
+    c.trace_clear()
+    c.enter(rp, halo=(1, 1))
+    for arr in (col, val, x):
+        c.enter(arr, whole=jacc.SHARED)
+    c.enter(y, clause=jacc.CREATE)
+    c.spmv(rp, col, val, x, y)
+    c.update(x, jacc.UPDATE_DEVICE)
+    c.spmv(rp, col, val, x, y)
+    c.exit(y)
+    tr = c.trace()
+    x_id = 3
+    assert len([t for t in tr if t["op"] == "ALLOC" and t["array"] == x_id]) == 1
+    assert len([t for t in tr if t["op"] == "H2D" and t["array"] == x_id]) == 2  # enter, update
+    reads = [t for t in tr if t["op"] == "ACCESS" and t["array"] == x_id and t["kind"] == 1]
+    assert len(reads) == 8 and {t["dst"] for t in reads} == {0}
+    assert race_check(tr) == [] and freshness_check(tr) == []
+    # a loop may not write a shared copy; the scatter writes out FILTERED
+    a = np.zeros(40)
+    idx = np.zeros(40, dtype=np.int32)
+    out = np.zeros(40)
+    c.enter(a, whole=True)
+    c.enter(idx, whole=True)
+    c.enter(out, whole=jacc.SHARED)
+    assert c.scatter_sq(a, idx, out, raw=True) == jacc.ERR_INVALID and "shared" in c.last_error()
+    assert c.enter(np.zeros(5), whole=3, raw=True) == jacc.ERR_INVALID
+    c.close()
