@@ -21,18 +21,6 @@ __device__ __forceinline__ void load_vec(const double *p, double (&v)[VEC]) {
     }
 }
 
-template <int VEC>
-__device__ __forceinline__ void store_vec(double *p, const double (&v)[VEC]) {
-    if constexpr (VEC == 2) {
-        dvec2 t;
-        t.x = v[0];
-        t.y = v[1];
-        __builtin_nontemporal_store(t, reinterpret_cast<dvec2 *>(p));
-    } else {
-        __builtin_nontemporal_store(v[0], p);
-    }
-}
-
 // Sum of `v` over the 64 lanes of a wave by a fixed butterfly (xor 1, 2, 4,
 // ..., 32); every lane ends with the same value.
 __device__ __forceinline__ double wave_sum(double v) {

@@ -67,37 +67,34 @@ __device__ __forceinline__ void horizontal(const Row<VEC> &mid, int lane, double
     for (int v = 0; v < VEC - 1; ++v) right[v] = mid.v[v + 1];
 }
 
+// Output stores (the box's own rows and every mirror) go through a
+// global-address-space pointer: a pointer read from a descriptor table or
+// picked by a loop index is otherwise generic, and stored through with flat
+// operations, which count against the counter the cross-lane shuffles wait
+// on.  Full-vector stores are non-temporal: a sweep's output is not read
+// again in the same launch.
 template <int VEC>
-__device__ __forceinline__ void store_masked(double *q, const double (&o)[VEC], bool all, const bool (&comp)[VEC]) {
-    if (all) {
-        store_vec<VEC>(q, o);
-    } else {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v)
-            if (comp[v]) q[v] = o[v];
-    }
-}
-
-// A mirror store goes through a global-address-space pointer: a mirror
-// pointer read from a descriptor table and picked by a loop index is
-// otherwise a generic pointer, stored through with flat operations, which
-// count against the counter the cross-lane shuffles wait on.
-template <int VEC>
-__device__ __forceinline__ void store_masked_global(double *p, const double (&o)[VEC], bool all,
-                                                    const bool (&comp)[VEC]) {
+__device__ __forceinline__ void store_nt(double *p, const double (&o)[VEC]) {
     typedef __attribute__((address_space(1))) double GDouble;
     typedef __attribute__((address_space(1))) dvec2 GDvec2;
     GDouble *q = (GDouble *)p;
-    if (all) {
-        if constexpr (VEC == 2) {
-            dvec2 t;
-            t.x = o[0];
-            t.y = o[1];
-            __builtin_nontemporal_store(t, (GDvec2 *)q);
-        } else {
-            __builtin_nontemporal_store(o[0], q);
-        }
+    if constexpr (VEC == 2) {
+        dvec2 t;
+        t.x = o[0];
+        t.y = o[1];
+        __builtin_nontemporal_store(t, (GDvec2 *)q);
     } else {
+        __builtin_nontemporal_store(o[0], q);
+    }
+}
+
+template <int VEC>
+__device__ __forceinline__ void store_masked(double *p, const double (&o)[VEC], bool all, const bool (&comp)[VEC]) {
+    if (all) {
+        store_nt<VEC>(p, o);
+    } else {
+        typedef __attribute__((address_space(1))) double GDouble;
+        GDouble *q = (GDouble *)p;
 #pragma unroll
         for (int v = 0; v < VEC; ++v)
             if (comp[v]) q[v] = o[v];
@@ -123,12 +120,12 @@ __device__ __forceinline__ void store_out(double *out, int64_t off, int64_t r, c
     store_masked<VEC>(out + off, o, all, comp);
     if constexpr (MM == 1) {
         for (int k = 0; k < mir.n; ++k)
-            if (r >= mir.m[k].lo && r < mir.m[k].hi) store_masked_global<VEC>(mir.m[k].ptr + off, o, all, comp);
+            if (r >= mir.m[k].lo && r < mir.m[k].hi) store_masked<VEC>(mir.m[k].ptr + off, o, all, comp);
     } else if constexpr (MM == 2) {
 #pragma unroll
         for (int k = 0; k < 2; ++k)
             if (k < mir.n && r >= mir.m[k].lo && r < mir.m[k].hi)
-                store_masked_global<VEC>(mir.m[k].ptr + off, o, all, comp);
+                store_masked<VEC>(mir.m[k].ptr + off, o, all, comp);
     }
 }
 
