@@ -1565,11 +1565,9 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
                 trace(c, JACC_OP_KERNEL, s, -1, -1, p, kind, plan[p].iters.lo, plan[p].iters.hi, c->st[s].seq);
         rc = post_op(c);
         if (rc) return rc;
-        if (nstreams(c) > 1 && !one_stream) {
-            int idx;
-            rc = ensure_event(c, s, c->st[s].seq, &idx);
-            if (rc) return rc;
-        }
+        // no event is recorded here: the packed launch's stream carries the
+        // loop's every partition, and a later wait on it records one then
+        // (ensure_wait), covering at least this launch
         for (int p = 0; p < K; ++p) {
             if (plan[p].iters.empty()) continue;
             for (int i = 0; i < nargs; ++i)
