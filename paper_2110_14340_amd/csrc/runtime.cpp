@@ -1677,7 +1677,10 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
         trace(c, JACC_OP_KERNEL, s, -1, -1, p, kind, pp.iters.lo, pp.iters.hi, c->st[s].seq);
         rc = post_op(c);
         if (rc) return rc;
-        if (nstreams(c) > 1 && !one_stream) {  // a precise event for partitions that will read these rows
+        // a precise event for the other partitions, which read these rows in
+        // the next loop from their own streams; a loop of one partition
+        // records none (a later wait on this stream records one then)
+        if (nstreams(c) > 1 && !one_stream && K > 1) {
             int idx;
             rc = ensure_event(c, s, c->st[s].seq, &idx);
             if (rc) return rc;
