@@ -1575,6 +1575,22 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             for (auto &m : mirs[(size_t)p]) P->valid[m.first].add(m.second);
         }
     }
+    if (nstreams(c) > 1 && !one_stream && !persistent && K > 1) {
+        // the pieces below issue on several streams and wait on earlier work
+        // of each other's streams: a stream whose last op carries no event
+        // yet (a packed launch, a loop of one partition) gets one now, before
+        // this loop adds its own ops there, so a wait on it does not also
+        // cover them
+        for (const Piece &pc : pieces) {
+            if (pc.pp.iters.empty()) continue;
+            const int s = stream_for(pc.p);
+            if (c->st[s].recorded < c->st[s].seq) {
+                int idx;
+                rc = ensure_event(c, s, c->st[s].seq, &idx);
+                if (rc) return rc;
+            }
+        }
+    }
     for (const Piece &piece_ : pieces) {
         const int p = piece_.p;
         const PartPlan &pp = piece_.pp;

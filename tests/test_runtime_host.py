@@ -1114,3 +1114,40 @@ def test_banded_spmv_packs_its_partitions():
         kern = [t for t in ops if t["op"] == "KERNEL"]
         assert len(kern) == 4 and len({(t["stream"], t["seq"]) for t in kern}) == keys
         c.close()
+
+
+def test_packed_loop_events_recorded_only_when_waited_on():
+    """Packed sweeps record no event after their launch; the GEMM that
+    follows on the partitions' own streams waits for them through an event
+    recorded at its first wait, and the whole trace stays race-free."""
+    c = dry(4)
+    n = 32
+    a, b = np.zeros((n, n)), np.zeros((n, n))
+    B, C = np.zeros((n, 8)), np.zeros((n, 8))
+    c.enter(a, halo=(1, 1))
+    c.enter(b, halo=(1, 1))
+    c.enter(B, whole=True)
+    c.enter(C, clause=jacc.CREATE)
+    c.trace_clear()
+    for t in range(4):
+        (c.jacobi2d(a, b) if t % 2 == 0 else c.jacobi2d(b, a))
+    sweeps = c.trace()
+    packed = {t["stream"] for t in sweeps if t["op"] == "KERNEL"}
+    assert len(packed) == 1
+    s0 = packed.pop()
+    # the only events are those the first sweep waits on (the entered data's copies)
+    assert not [t for t in sweeps if t["op"] == "RECORD" and t["stream"] == s0]
+    c.gemm(a, B, C)
+    c.exit(C)
+    tr = c.trace()
+    after = tr[len(sweeps):]
+    gemm_streams = {t["stream"] for t in after if t["op"] == "KERNEL"}
+    assert len(gemm_streams - {s0}) > 0
+    last_sweep = max(t["seq"] for t in sweeps if t["op"] == "KERNEL")
+    rec = [t for t in after if t["op"] == "RECORD" and t["stream"] == s0]
+    assert rec and rec[0]["seq"] == last_sweep  # recorded before the GEMM adds its own op to that stream
+    waits = [t for t in after if t["op"] == "WAIT" and t["src"] == s0]
+    assert {t["stream"] for t in waits} == gemm_streams - {s0}
+    assert all(t["seq"] == last_sweep for t in waits)  # no GEMM partition waits for another's kernel
+    assert race_check(tr) == []
+    assert freshness_check(tr) == []
