@@ -31,11 +31,17 @@
  *     slabs hold as halo (a write-through restricted to the holders of each
  *     row), so no copy is needed at all.  Both replace the paper's
  *     send-everything-after-each-kernel scheme with range-driven transfers.
- *   - Asynchrony: partition p's work runs on stream p.  Cross-stream waits
- *     are inserted only for the rows actually shared (read-after-write and
- *     write-after-read), skipping waits already satisfied (the paper keeps
- *     access timestamps and the most recent synchronisation among queues,
- *     Sec. "Automated Asynchronous Execution").
+ *   - Asynchrony: partition p's work runs on stream p (outside batches the
+ *     partitions of a JACOBI2D, HEAT3D, SUM or column-banded SPMV_CSR loop
+ *     instead run as one packed launch on one stream; see
+ *     JACC_INIT_NO_PACK).  Cross-stream waits are inserted only for the
+ *     rows actually shared (read-after-write and write-after-read),
+ *     skipping waits already satisfied (the paper keeps access timestamps
+ *     and the most recent synchronisation among queues, Sec. "Automated
+ *     Asynchronous Execution").  The events these waits use are recorded
+ *     after each partition's kernel of a loop spread over several streams;
+ *     after a packed launch or a loop of one partition an event is
+ *     recorded only when some other stream first waits on it.
  *
  * Conventions
  *   - Every call returns a jacc_status (0 = success, negative = error).  The
