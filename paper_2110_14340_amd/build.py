@@ -54,23 +54,39 @@ def _compile(src, bid):
     return obj
 
 
-def build(verbose=False):
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = sources()
-    bid = build_id()
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda src: _compile(src, bid), srcs))
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+def build(verbose=False, asan=False):
+    """Compiles every source and links the library.  asan=True builds a
+    second library, libjacc_asan.so, whose host code (the runtime) carries
+    AddressSanitizer checks (device code is built as usual); it is for the
+    CPU tests, loaded through JACC_LIB with the sanitizer runtime preloaded."""
+    global COMMON, BUILD
+    saved = COMMON, BUILD
+    lib = LIB
+    link_extra = []
+    if asan:
+        COMMON = COMMON + ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+        BUILD = BUILD + "_asan"
+        lib = os.path.join(HERE, "libjacc_asan.so")
+        link_extra = ["-fsanitize=address", "-shared-libasan"]
+    try:
+        os.makedirs(BUILD, exist_ok=True)
+        srcs = sources()
+        bid = build_id()
+        with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+            objs = list(ex.map(lambda src: _compile(src, bid), srcs))
+        tmp = lib + ".tmp"
+        cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *link_extra, *objs, "-o", tmp]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        os.replace(tmp, lib)
+    finally:
+        COMMON, BUILD = saved
     if verbose:
-        print(LIB)
-    return LIB
+        print(lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, asan="--asan" in sys.argv[1:])
     sys.exit(0)

@@ -2101,7 +2101,8 @@ int jacc_finalize(jacc_ctx *c) {
         }
         if (c->model && c->model_release) c->model_release(c->model);  // its buffers come from this context
         c->model = nullptr;
-        if (c->cur) {  // abandon an open capture
+        if (c->cur) {  // abandon an open capture (its op log goes with it)
+            c->oplog = nullptr;
             if (live(c)) {
                 hipGraph_t g = nullptr;
                 (void)hipStreamEndCapture(c->st[0].s, &g);

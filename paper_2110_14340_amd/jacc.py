@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libjacc.so")
+# JACC_LIB names another build of the library (e.g. the sanitizer build of
+# `python -m paper_2110_14340_amd.build --asan`)
+LIB_PATH = os.environ.get("JACC_LIB") or os.path.join(HERE, "libjacc.so")
 
 # ---- constants mirrored from jacc.h --------------------------------------
 OK, ERR_INVALID, ERR_NOT_PRESENT, ERR_ALREADY_PRESENT, ERR_RANGE, ERR_ALLOC, ERR_DEVICE, ERR_UNSUPPORTED = \
