@@ -54,20 +54,24 @@ def _compile(src, bid):
     return obj
 
 
-def build(verbose=False, asan=False):
-    """Compiles every source and links the library.  asan=True builds a
-    second library, libjacc_asan.so, whose host code (the runtime) carries
-    AddressSanitizer checks (device code is built as usual); it is for the
-    CPU tests, loaded through JACC_LIB with the sanitizer runtime preloaded."""
+def build(verbose=False, sanitizer=None):
+    """Compiles every source and links the library.  sanitizer = "address"
+    or "undefined" builds a second library, libjacc_asan.so or
+    libjacc_ubsan.so, whose host code (the runtime) carries that
+    sanitizer's checks (device code is built as usual); it is for the CPU
+    tests, loaded through JACC_LIB with the sanitizer's runtime preloaded."""
     global COMMON, BUILD
     saved = COMMON, BUILD
     lib = LIB
     link_extra = []
-    if asan:
-        COMMON = COMMON + ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
-        BUILD = BUILD + "_asan"
-        lib = os.path.join(HERE, "libjacc_asan.so")
-        link_extra = ["-fsanitize=address", "-shared-libasan"]
+    if sanitizer:
+        tag = {"address": "asan", "undefined": "ubsan"}[sanitizer]
+        COMMON = COMMON + ["-Xarch_host", f"-fsanitize={sanitizer}", "-Xarch_host", "-fno-omit-frame-pointer"]
+        if sanitizer == "undefined":
+            COMMON = COMMON + ["-Xarch_host", "-fno-sanitize-recover=all"]
+        BUILD = BUILD + "_" + tag
+        lib = os.path.join(HERE, f"libjacc_{tag}.so")
+        link_extra = [f"-fsanitize={sanitizer}", "-shared-libsan"]
     try:
         os.makedirs(BUILD, exist_ok=True)
         srcs = sources()
@@ -88,5 +92,6 @@ def build(verbose=False, asan=False):
 
 
 if __name__ == "__main__":
-    build(verbose=True, asan="--asan" in sys.argv[1:])
+    args = sys.argv[1:]
+    build(verbose=True, sanitizer="address" if "--asan" in args else "undefined" if "--ubsan" in args else None)
     sys.exit(0)
