@@ -114,8 +114,10 @@ typedef enum { JACC_F64 = 0, JACC_F32 = 1, JACC_I32 = 2, JACC_I64 = 3 } jacc_dty
  * global columns sit on 16-byte boundaries; its transfers are strided 2-D
  * copies.  Such arrays are never whole (JACC_ERR_INVALID) and take JACOBI2D
  * loops only, with both arguments split along dimension 1 (otherwise
- * JACC_ERR_UNSUPPORTED): no mirror stores (halo columns are pulled, or sent
- * under JACC_INIT_EAGER), no FILTERED output, no persistent execution, no
+ * JACC_ERR_UNSUPPORTED).  By default the kernel writes each column another
+ * slab keeps into that slab too (column mirrors) and the partitions run as
+ * one packed launch; halo columns are pulled under JACC_INIT_LAZY, or sent
+ * under JACC_INIT_EAGER.  No FILTERED output, no persistent execution, no
  * tuning or cost-model picks (JACC_ERR_UNSUPPORTED). */
 typedef struct {
     int32_t dtype;
@@ -292,6 +294,7 @@ enum {
     JACC_INIT_NO_PACK = 1u << 10   /* a launch per partition on its own stream for every loop.
                                       Default: outside batches, a JACOBI2D, HEAT3D, SUM or
                                       column-banded SPMV_CSR loop of 2 to 16 row-split partitions
+                                      (JACOBI2D also over arrays split along dim 1)
                                       without a FILTERED output runs all its partitions in one
                                       launch on one stream, each partition's tiles a run of the
                                       workgroups, in the loop's configuration (halo pulls before

@@ -102,7 +102,10 @@ __device__ __forceinline__ void store_masked(double *p, const double (&o)[VEC], 
 }
 
 // Mirror handling of a kernel (MM): 0 the launch writes no mirrors (the
-// code is left out), 1 a loop over mirrors passed as kernel arguments, 2
+// code is left out), 1 a loop over mirrors passed as kernel arguments, 3
+// the same loop over column mirrors (ColMirrors: an array split along dim
+// 1, where the lanes holding a column another slab keeps store that
+// element there too), 4 the column mirrors of a descriptor, unrolled, 2
 // the two mirrors of a descriptor read from memory, unrolled (a loop index
 // into a descriptor held in registers puts the whole descriptor in scratch
 // memory: 40 % slower).  The forms schedule differently: without the loop
@@ -113,12 +116,29 @@ __device__ __forceinline__ void store_masked(double *p, const double (&o)[VEC], 
 // launches without mirrors take form 0.
 //
 // Stores an output row (or plane) `r` at offset `off` from its row start,
-// and again into every mirror holding row r (uniform test per row).
-template <int VEC, int MM>
-__device__ __forceinline__ void store_out(double *out, int64_t off, int64_t r, const Mirrors &mir,
+// and again into every mirror holding row r (uniform test per row); with
+// column mirrors (MM 3 and 4) each computed element of columns col ..
+// col+VEC-1 that a holder keeps goes to that holder's slab as well.
+template <int VEC, int MM, typename MT = Mirrors>
+__device__ __forceinline__ void store_out(double *out, int64_t off, int64_t r, int64_t col, const MT &mir,
                                           const double (&o)[VEC], bool all, const bool (&comp)[VEC]) {
     store_masked<VEC>(out + off, o, all, comp);
-    if constexpr (MM == 1) {
+    if constexpr (MM == 3 || MM == 4) {
+        typedef __attribute__((address_space(1))) double GDouble;
+        constexpr int kN = MM == 4 ? 2 : 0;  // 4: unrolled over the descriptor's two entries
+        auto one = [&](const ColMirror &m) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+                if (comp[v] && col + v >= m.lo && col + v < m.hi) *(GDouble *)(m.ptr + r * m.pitch + col + v) = o[v];
+        };
+        if constexpr (kN == 2) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                if (k < mir.n) one(mir.m[k]);
+        } else {
+            for (int k = 0; k < mir.n; ++k) one(mir.m[k]);
+        }
+    } else if constexpr (MM == 1) {
         for (int k = 0; k < mir.n; ++k)
             if (r >= mir.m[k].lo && r < mir.m[k].hi) store_masked<VEC>(mir.m[k].ptr + off, o, all, comp);
     } else if constexpr (MM == 2) {
@@ -140,10 +160,10 @@ __device__ __forceinline__ int64_t march_dir(int march, int64_t q) { return (mar
 // ---------------------------------------------------------------------------
 // Jacobi-2D tile: lanes [tx] of row-group [ty] of workgroup tile (bxi, byi)
 // ---------------------------------------------------------------------------
-template <int VEC, int MM>
+template <int VEC, int MM, typename MT = Mirrors>
 __device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, double *__restrict__ out, int64_t nx,
                                             int64_t pitch, int64_t r_lo, int64_t r_hi, int64_t c_lo, int64_t c_hi,
-                                            int64_t col0, int tile, int march, const Mirrors &mir, int64_t bxi,
+                                            int64_t col0, int tile, int march, const MT &mir, int64_t bxi,
                                             int64_t byi, int tx, int ty, int bdx, int bdy,
                                             int64_t own_lo = INT64_MIN, int64_t own_hi = INT64_MAX) {
     const int lane = tx & (kWave - 1);
@@ -194,7 +214,7 @@ __device__ __forceinline__ void jacobi_tile(const double *__restrict__ in, doubl
                 }
                 // write guard of a filtered loop (every partition computes the
                 // whole box and keeps its owner rows); uniform per row
-                if (row >= own_lo && row < own_hi) store_out<VEC, MM>(out, row * pitch + j, row, mir, o, all, comp);
+                if (row >= own_lo && row < own_hi) store_out<VEC, MM, MT>(out, row * pitch + j, row, j, mir, o, all, comp);
             }
         }
 #pragma unroll
@@ -221,6 +241,18 @@ jacobi2d_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t
     const int64_t t = tile_of(order);
     jacobi_tile<VEC, MM>(in, out, nx, pitch, r_lo, r_hi, c_lo, c_hi, col0, tile, march, mir, t % gx, t / gx, threadIdx.x,
                      threadIdx.y, blockDim.x, blockDim.y, own_lo, own_hi);
+}
+
+// The same sweep over a column slab of an array split along dim 1 whose
+// written columns other slabs keep (column mirrors).
+template <int VEC>
+__global__ void __launch_bounds__(1024)
+jacobi2d_cols_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t nx, int64_t pitch, int64_t r_lo,
+                     int64_t r_hi, int64_t c_lo, int64_t c_hi, int64_t col0, int tile, int march, ColMirrors mir,
+                     int64_t gx, int order) {
+    const int64_t t = tile_of(order);
+    jacobi_tile<VEC, 3, ColMirrors>(in, out, nx, pitch, r_lo, r_hi, c_lo, c_hi, col0, tile, march, mir, t % gx, t / gx,
+                                    threadIdx.x, threadIdx.y, blockDim.x, blockDim.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -300,7 +332,7 @@ __device__ __forceinline__ double heat_tile(const double *__restrict__ in, doubl
                         acc += dd * dd;
                     }
                 }
-                if (keep) store_out<VEC, MM>(out, z * plane + y * nx + x, z, mir, o, all, comp);
+                if (keep) store_out<VEC, MM>(out, z * plane + y * nx + x, z, x, mir, o, all, comp);
             }
         }
 #pragma unroll
@@ -418,7 +450,7 @@ __device__ __forceinline__ double heat_rows_tile(const double *__restrict__ in, 
                         acc += dd * dd;
                     }
                 }
-                if (keep) store_out<VEC, MM>(out, z * plane + (yb + i) * nx + x, z, mir, o, all, comp);
+                if (keep) store_out<VEC, MM>(out, z * plane + (yb + i) * nx + x, z, x, mir, o, all, comp);
             }
         }
     };
@@ -649,6 +681,60 @@ jacobi2d_parts_kernel(PartPack pk, int64_t nx, int64_t c_lo, int64_t c_hi, int64
                      threadIdx.x, threadIdx.y, blockDim.x, blockDim.y);
 }
 
+// Packed partitions of a JACOBI2D loop over arrays split along dim 1: each
+// partition has its own columns, slab pitch and column mirrors.
+struct ColPartDesc {
+    const double *in;
+    double *out;
+    int64_t tiles, begin;              // its tile count and first workgroup
+    int64_t c_lo, c_hi, col0, pitch;  // its columns, first lane column, slab row pitch
+    int64_t gx;                        // tiles per row of tiles
+    ColMirrors mir;
+};
+struct ColPartPack {
+    ColPartDesc p[kMaxPack];
+    int32_t n;
+};
+typedef const __attribute__((address_space(4))) ColPartDesc ConstColPart;
+
+__device__ __forceinline__ ColPartDesc load_colpart(ConstColPart *p) {
+    ColPartDesc d;
+    d.in = p->in;
+    d.out = p->out;
+    d.tiles = p->tiles;
+    d.begin = p->begin;
+    d.c_lo = p->c_lo;
+    d.c_hi = p->c_hi;
+    d.col0 = p->col0;
+    d.pitch = p->pitch;
+    d.gx = p->gx;
+    d.mir.n = p->mir.n;
+    for (int k = 0; k < 2; ++k) {
+        d.mir.m[k].ptr = p->mir.m[k].ptr;
+        d.mir.m[k].lo = p->mir.m[k].lo;
+        d.mir.m[k].hi = p->mir.m[k].hi;
+        d.mir.m[k].pitch = p->mir.m[k].pitch;
+    }
+    return d;
+}
+
+template <int VEC>
+__global__ void __launch_bounds__(1024)
+jacobi2d_colparts_kernel(ColPartPack pk, int64_t nx, int64_t r_lo, int64_t r_hi, int tile, int march, int order) {
+    ConstColPart *cp = (ConstColPart *)&pk.p[0];
+    const int64_t b = blockIdx.x;
+    int q = 0;
+    for (int k = 1; k < pk.n; ++k)
+        if (cp[k].begin <= b) q = k;
+    const ColPartDesc d = load_colpart(cp + q);
+    const int64_t span = (q + 1 < pk.n ? cp[q + 1].begin : (int64_t)gridDim.x) - d.begin;
+    const int64_t local = b - d.begin;
+    const int64_t t = order >= 2 ? (local & 7) * (span >> 3) + (local >> 3) : local;
+    if (t >= d.tiles) return;
+    jacobi_tile<VEC, 4, ColMirrors>(d.in, d.out, nx, d.pitch, r_lo, r_hi, d.c_lo, d.c_hi, d.col0, tile, march, d.mir,
+                                    t % d.gx, t / d.gx, threadIdx.x, threadIdx.y, blockDim.x, blockDim.y);
+}
+
 template <int VEC, int R, bool RES, int MM>
 __global__ void __launch_bounds__(R == 1 ? 1024 : 256)
 heat3d_parts_kernel(PartPack pk, int64_t ny, int64_t nx, int64_t y_lo, int64_t y_hi, int64_t x_lo, int64_t x_hi,
@@ -705,6 +791,17 @@ hipError_t launch_jacobi2d(const Launch &L, hipStream_t s) {
 #define JACOBI_LAUNCH(V, M)                                                                                   \
     hipLaunchKernelGGL((jacobi2d_kernel<V, M>), grid, block, 0, s, in, out, nx, pitch, L.lo[0], L.hi[0], L.lo[1], \
                        L.hi[1], col0, c.tile, c.march, L.mir, gx, c.order, own_lo, own_hi)
+    if (L.cmir.n > 0) {  // column mirrors: an array split along dim 1
+#define JCOLS_LAUNCH(V)                                                                                           \
+    hipLaunchKernelGGL((jacobi2d_cols_kernel<V>), grid, block, 0, s, in, out, nx, pitch, L.lo[0], L.hi[0], L.lo[1], \
+                       L.hi[1], col0, c.tile, c.march, L.cmir, gx, c.order)
+        if (c.vec == 2)
+            JCOLS_LAUNCH(2);
+        else
+            JCOLS_LAUNCH(1);
+#undef JCOLS_LAUNCH
+        return hipGetLastError();
+    }
     // the mirror-free form for launches of at least 2^22 cells without mirrors
     const bool lean = L.mir.n == 0 && nrows * (L.hi[1] - L.lo[1]) >= ((int64_t)1 << 22);
     if (c.vec == 2) {
@@ -790,6 +887,47 @@ int64_t parts_partials(const Launch *L, int n) {
     return total;
 }
 
+// The partitions of a JACOBI2D loop over arrays split along dim 1 in one
+// launch: every partition has its own columns, pitch and column mirrors.
+static hipError_t launch_col_parts(const Launch *L, int n, hipStream_t s) {
+    const Launch &L0 = L[0];
+    const Cfg &c = L0.cfg;
+    const bool xcd = c.order == 2;
+    ColPartPack pk{};
+    int64_t begin = 0;
+    for (int k = 0; k < n; ++k) {
+        const Launch &Lk = L[k];
+        if (Lk.a[1].row_elems != Lk.a[0].row_elems || Lk.lo[0] != L0.lo[0] || Lk.hi[0] != L0.hi[0])
+            return hipErrorInvalidValue;
+        if (Lk.hi[0] <= Lk.lo[0] || Lk.hi[1] <= Lk.lo[1]) continue;
+        const int64_t col0 = col_start(Lk.lo[1], c.vec);
+        const int64_t gx = cdiv(Lk.hi[1] - col0, (int64_t)c.bx * c.vec);
+        const int64_t tiles = gx * cdiv(Lk.hi[0] - Lk.lo[0], (int64_t)c.by * c.tile);
+        ColPartDesc &d = pk.p[pk.n++];
+        d.in = (const double *)Lk.a[0].ptr;
+        d.out = (double *)Lk.a[1].ptr;
+        d.tiles = tiles;
+        d.begin = begin;
+        d.c_lo = Lk.lo[1];
+        d.c_hi = Lk.hi[1];
+        d.col0 = col0;
+        d.pitch = Lk.a[0].row_elems;
+        d.gx = gx;
+        d.mir = Lk.cmir;
+        begin += xcd ? (tiles + 7) / 8 * 8 : tiles;
+    }
+    if (pk.n == 0) return hipSuccess;
+    if (begin > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)begin), block(c.bx, c.by);
+    if (c.vec == 2)
+        hipLaunchKernelGGL((jacobi2d_colparts_kernel<2>), grid, block, 0, s, pk, L0.ext[1], L0.lo[0], L0.hi[0], c.tile,
+                           c.march, c.order);
+    else
+        hipLaunchKernelGGL((jacobi2d_colparts_kernel<1>), grid, block, 0, s, pk, L0.ext[1], L0.lo[0], L0.hi[0], c.tile,
+                           c.march, c.order);
+    return hipGetLastError();
+}
+
 hipError_t launch_parts(const Launch *L, int n, double *wg_partials, int64_t wg_capacity, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (n > kMaxPack) return hipErrorInvalidValue;
@@ -798,6 +936,7 @@ hipError_t launch_parts(const Launch *L, int n, double *wg_partials, int64_t wg_
     const Cfg &c = L0.cfg;
     const bool heat = L0.kind == JACC_LOOP_HEAT3D;
     if (!heat && L0.kind != JACC_LOOP_JACOBI2D) return hipErrorInvalidValue;
+    if (!heat && L0.part_dim == 1) return launch_col_parts(L, n, s);  // column slabs
     const bool res = heat && L0.part_out != nullptr;
     const bool xcd = heat ? c.order >= 2 : c.order == 2;
     const int64_t col0 = col_start(L0.lo[heat ? 2 : 1], c.vec);

@@ -34,6 +34,17 @@ struct Mirrors {
     Mirror m[2];
     int n;
 };
+// Column mirrors (a 2-D array split along dim 1): [lo, hi) are the columns
+// the holder slab keeps, pitch its row length in elements, and ptr is biased
+// so that ptr[row * pitch + column] is global (row, column).
+struct ColMirror {
+    double *ptr;
+    int64_t lo, hi, pitch;
+};
+struct ColMirrors {
+    ColMirror m[2];
+    int n;
+};
 
 // One partition's launch of one loop nest.
 struct Launch {
@@ -45,7 +56,9 @@ struct Launch {
     int nargs;
     double scalars[4];
     Cfg cfg;
-    Mirrors mir;  // stencil kinds only
+    int part_dim;     // the dimension the arrays are split along (0, or 1 for 2-D column slabs)
+    Mirrors mir;      // stencil kinds only
+    ColMirrors cmir;  // JACOBI2D on arrays split along dim 1 (mir is then empty)
     int64_t own_lo, own_hi;    // owner rows of a FILTERED output (writes elsewhere are dropped)
     int64_t own2_lo, own2_hi;  // owner rows of a second FILTERED output (PRED_CHAIN's b)
     // reductions: workgroup partials go to `wg_partials` (capacity

@@ -1333,7 +1333,8 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
                   K <= jk::kMaxPack && !persistent && !dup &&
                   (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D || kind == JACC_LOOP_SUM ||
                    (kind == JACC_LOOP_SPMV_CSR && L.cfg.order == 4 && L.cfg.rows <= 1)) &&
-                  !(args[primary].mode & JACC_FILTERED) && P->pdim == 0 && !P->whole;
+                  !(args[primary].mode & JACC_FILTERED) && (P->pdim == 0 || kind == JACC_LOOP_JACOBI2D) &&
+                  !P->whole;
     if (packed && want_red) {
         int64_t total = 0;
         for (int p = 0; p < K; ++p) {
@@ -1396,8 +1397,10 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
         if (args[i].mode & JACC_WRITE) arr[i]->last_stream = base;
     // mirrors: a stencil partition also writes the rows of its output that
     // other slabs hold as halo (at most one neighbour block on each side)
+    // (for an array split along dim 1, the JACOBI2D kernel writes the
+    // columns other slabs keep: column mirrors)
     const bool can_mirror = !c->lazy && !c->eager && (kind == JACC_LOOP_JACOBI2D || kind == JACC_LOOP_HEAT3D) &&
-                            !P->whole && K > 1 && P->pdim == 0;
+                            !P->whole && K > 1 && (P->pdim == 0 || kind == JACC_LOOP_JACOBI2D);
     const int red_slot = slot >= 0 ? slot : kSlots - 1;  // a synchronous-only reduction uses the last slot
     std::vector<int> order;       // partitions that reduce, in partition order
     std::vector<int> red_streams;  // their streams
@@ -1469,6 +1472,7 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
         }
         LP.lo[P->pdim] = pp.iters.lo;
         LP.hi[P->pdim] = pp.iters.hi;
+        LP.part_dim = P->pdim;
         for (int i = 0; i < nargs; ++i) {
             // biased so that global indices address the slab: by whole rows,
             // or by elements for column slabs (whose width is the row pitch)
@@ -1488,12 +1492,24 @@ int loop_impl(jacc_ctx *c, int kind, const jacc_bounds *b, int nargs, const jacc
             LP.own2_lo = pp.rng[1].lo;
             LP.own2_hi = pp.rng[1].hi;
         }
-        LP.mir.n = (int)mirrors.size();
-        for (size_t k = 0; k < mirrors.size(); ++k) {
-            const Slab &sq = P->slabs[mirrors[k].first];
-            LP.mir.m[k].ptr = (double *)((char *)sq.dev - (intptr_t)((size_t)sq.rows.lo * P->row_bytes));
-            LP.mir.m[k].lo = mirrors[k].second.lo;
-            LP.mir.m[k].hi = mirrors[k].second.hi;
+        if (P->pdim == 0) {
+            LP.mir.n = (int)mirrors.size();
+            for (size_t k = 0; k < mirrors.size(); ++k) {
+                const Slab &sq = P->slabs[mirrors[k].first];
+                LP.mir.m[k].ptr = (double *)((char *)sq.dev - (intptr_t)((size_t)sq.rows.lo * P->row_bytes));
+                LP.mir.m[k].lo = mirrors[k].second.lo;
+                LP.mir.m[k].hi = mirrors[k].second.hi;
+            }
+        } else {  // column slabs, each biased by its first stored column
+            LP.mir.n = 0;
+            LP.cmir.n = (int)mirrors.size();
+            for (size_t k = 0; k < mirrors.size(); ++k) {
+                const Slab &sq = P->slabs[mirrors[k].first];
+                LP.cmir.m[k].ptr = (double *)sq.dev - sq.base;
+                LP.cmir.m[k].pitch = sq.pitch;
+                LP.cmir.m[k].lo = mirrors[k].second.lo;
+                LP.cmir.m[k].hi = mirrors[k].second.hi;
+            }
         }
         return LP;
     };

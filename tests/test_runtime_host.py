@@ -745,9 +745,10 @@ def test_heat_batch_with_residual_slots_on_their_own_streams():
 def test_column_split_jacobi_plan_matches_model(K, lazy):
     """A 2-D array split along dimension 1 holds column blocks with halo
     columns; the plan is the row-split plan with columns in place of rows:
-    kernels cover each partition's interior columns, and a sweep reading the
-    last sweep's output pulls one halo column across each boundary side (as
-    strided copies; no mirror stores of columns)."""
+    kernels cover each partition's interior columns; in lazy mode a sweep
+    reading the last sweep's output pulls one halo column across each
+    boundary side (as strided copies), by default the kernel writes the
+    columns the neighbours keep (column mirrors) and nothing is copied."""
     ny, E = 20, 67
     c = dry(K, lazy)
     a = np.zeros((ny, E))
@@ -762,13 +763,13 @@ def test_column_split_jacobi_plan_matches_model(K, lazy):
         tr = _loop_trace(c, lambda: c.jacobi2d(src, dst))
         full += tr
         ps = P.plan_loop(model, 1, E - 1, [(names[id(src)], "r", -1, 1, False), (names[id(dst)], "w", 0, 0, False)],
-                         refresh="pull")
+                         refresh="pull" if lazy else "holders")
         kernels = [t for t in tr if t["op"] == "KERNEL"]
         assert [(t["dst"], t["lo"], t["hi"]) for t in kernels] == \
             [(p, min(pp["I"]), max(pp["I"]) + 1) for p, pp in enumerate(ps) if pp["I"]]
         copies = sorted((t["dst"], t["src"], t["lo"], t["hi"]) for t in tr if t["op"] == "COPY")
         assert copies == sorted((p, s, lo, hi) for p, pp in enumerate(ps) for (_, s, lo, hi) in pp["copies"])
-        assert len(copies) == (0 if step == 0 else 2 * (K - 1))
+        assert len(copies) == (0 if step == 0 or not lazy else 2 * (K - 1))
         src, dst = dst, src
     assert race_check(full) == [] and freshness_check(full) == []
     c.close()
@@ -862,7 +863,7 @@ def test_poison_fills_exactly_the_rows_left_stale(mode, part_dim):
     full = [t for tr in per_sweep for t in tr]
     fills = [[t for t in tr if t["op"] == "POISON"] for tr in per_sweep]
     # the written array of each sweep: b (id 1), a (0), b (1)
-    want = 2 * (K - 1) if (mode == "lazy" or (mode == "mirror" and part_dim == 1)) else 0
+    want = 2 * (K - 1) if mode == "lazy" else 0
     assert [len(f) for f in fills] == [want] * 3
     for f, arr_id in zip(fills, (1, 0, 1)):
         assert all(t["array"] == arr_id and t["hi"] - t["lo"] == 1 for t in f)
