@@ -224,13 +224,17 @@ def test_filtered_jacobi_equals_hoisted_form(shape, K):
     ((66, 1030), 8, jacc.INIT_LAZY, _cfg(128, 2, 5, 1, march=2), 5), ((1030, 130), 2, 0, _cfg(256, 1, 32, 1, order=2), 4),
     ((512, 512), 4, 0, None, 100), ((131, 258), 3, 0, _cfg(64, 1, 3, 2, march=2), 5),
     ((70, 1030), 7, jacc.INIT_LAZY, _cfg(128, 2, 5, 2), 4), ((33, 514), 5, jacc.INIT_EAGER, _cfg(256, 1, 4, 2), 4),
+    ((130, 67), 5, jacc.INIT_NO_PACK, _cfg(64, 2, 3, 1), 6), ((131, 258), 3, jacc.INIT_NO_PACK, _cfg(64, 1, 3, 2), 5),
+    ((512, 512), 4, jacc.INIT_NO_PACK, None, 40), ((40, 9), 4, 0, _cfg(64, 1, 2, 1), 5),
 ])
 def test_jacobi_column_split_bit_exact(shape, K, flags, cfg, T):
     """Arrays split into column blocks with one halo column on each side
     (stored from an even column with an even pitch, so two-double lanes stay
-    aligned): halo columns move as strided 2-D copies (pulled, or sent after
-    each sweep under eager coherence), and every sweep is bit-identical to
-    the oracle's, with one or two doubles per lane."""
+    aligned): by default the kernel writes the columns the neighbouring
+    slabs keep (column mirrors) in one packed launch (NO_PACK: a launch per
+    partition); under lazy or eager coherence halo columns move as strided
+    2-D copies (pulled, or sent after each sweep); every sweep is
+    bit-identical to the oracle's, with one or two doubles per lane."""
     say(f"jacobi column split {shape} K={K} flags={flags} T={T}")
     u0 = inputs.jacobi_grid(*shape, seed=17)
     u0[:, 0] = 0.5  # a nonzero boundary column must be held
