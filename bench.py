@@ -325,8 +325,8 @@ def main():
             wall, _ = run_jacobi(jacc, torch, u0, K, args.steps, args.warmup, flags=fl)
             modes.setdefault(name, {})[str(K)] = {"ms_per_step": round(wall / args.steps * 1e3, 5),
                                                   "gbps": round(step_bytes * args.steps / wall / 1e9, 1)}
-    # the arrays split into column blocks instead (halo columns pulled as
-    # strided 2-D copies before each sweep)
+    # the arrays split into column blocks instead (one packed launch per
+    # sweep whose tiles write the columns the neighbouring slabs keep)
     for K in ks:
         log(f"jacobi K={K} column blocks")
         wall, _ = run_jacobi(jacc, torch, u0, K, args.steps, args.warmup, part_dim=1)
