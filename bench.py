@@ -108,13 +108,14 @@ def run_jacobi_graph(jacc, torch, u0, K, steps, warmup, per_graph=2, persistent=
     c.batch_launch(g, max(1, warmup // per_graph))
     c.wait()
     torch.cuda.synchronize()
+    reps = max(1, steps // per_graph)
     t0 = time.perf_counter()
-    c.batch_launch(g, steps // per_graph)
+    c.batch_launch(g, reps)
     c.wait()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     c.close()
-    return t1 - t0
+    return (t1 - t0) * steps / (reps * per_graph)  # scaled to `steps` steps
 
 
 def cpu_baseline(u0, budget_s=8.0):
@@ -333,12 +334,13 @@ def main():
         modes.setdefault("column_split", {})[str(K)] = {"ms_per_step": round(wall / args.steps * 1e3, 5),
                                                         "gbps": round(step_bytes * args.steps / wall / 1e9, 1)}
     graph, graph_plain = {}, {}
+    per_graph = 10 if args.steps >= 10 else 2  # steps per captured graph
     for K in ks:
         log(f"jacobi K={K} as a replayed graph")
-        wall = run_jacobi_graph(jacc, torch, u0, K, args.steps, args.warmup)
+        wall = run_jacobi_graph(jacc, torch, u0, K, args.steps, args.warmup, per_graph=per_graph)
         graph[K] = {"ms_per_step": round(wall / args.steps * 1e3, 5),
                     "gbps": round(step_bytes * args.steps / wall / 1e9, 1)}
-        wall = run_jacobi_graph(jacc, torch, u0, K, args.steps, args.warmup, persistent=False)
+        wall = run_jacobi_graph(jacc, torch, u0, K, args.steps, args.warmup, per_graph=per_graph, persistent=False)
         graph_plain[K] = {"ms_per_step": round(wall / args.steps * 1e3, 5),
                           "gbps": round(step_bytes * args.steps / wall / 1e9, 1)}
     main_k = max(ks)
@@ -364,6 +366,7 @@ def main():
                    "grid": [n, n], "K": main_k, "iterations": args.steps, "seed": 1},
         "frac_hbm_peak": round(value / HBM_PEAK_GBS, 4),
         "per_k": {str(k): v for k, v in per_k.items()},
+        "per_k_graph_steps_per_graph": per_graph,
         "per_k_graph": {str(k): v for k, v in graph.items()},
         "per_k_graph_plain_launches": {str(k): v for k, v in graph_plain.items()},
         "per_k_modes": modes,
