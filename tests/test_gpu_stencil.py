@@ -226,6 +226,7 @@ def test_filtered_jacobi_equals_hoisted_form(shape, K):
     ((70, 1030), 7, jacc.INIT_LAZY, _cfg(128, 2, 5, 2), 4), ((33, 514), 5, jacc.INIT_EAGER, _cfg(256, 1, 4, 2), 4),
     ((130, 67), 5, jacc.INIT_NO_PACK, _cfg(64, 2, 3, 1), 6), ((131, 258), 3, jacc.INIT_NO_PACK, _cfg(64, 1, 3, 2), 5),
     ((512, 512), 4, jacc.INIT_NO_PACK, None, 40), ((40, 9), 4, 0, _cfg(64, 1, 2, 1), 5),
+    ((40, 1030), 16, 0, None, 4), ((40, 1030), 20, 0, None, 4),
 ])
 def test_jacobi_column_split_bit_exact(shape, K, flags, cfg, T):
     """Arrays split into column blocks with one halo column on each side
