@@ -31,6 +31,7 @@ def test_jacobi_512_100_steps_bit_exact(K):
     ((9, 9), 7, _cfg(64, 1, 1, 1)), ((300, 130), 4, _cfg(256, 4, 64, 2)),
     ((131, 258), 3, _cfg(128, 2, 5, 2, march=2)), ((77, 67), 1, _cfg(64, 1, 4, 1, order=2, march=2)),
     ((1030, 1026), 4, _cfg(256, 1, 32, 2, order=2, march=2)), ((5, 130), 2, _cfg(64, 1, 3, 2, march=2)),
+    ((1030, 66), 16, None), ((1030, 66), 20, None), ((200, 130), 64, _cfg(64, 1, 2, 2)),
 ])
 def test_jacobi_ragged_shapes_partitions_configs(shape, K, cfg):
     say(f"jacobi ragged {shape} K={K}")
@@ -108,6 +109,7 @@ def _rel_close(a, b, tol=1e-13):
     ((9, 3, 64), 2, _cfg(64, 1, 2, 2, rows=4)), ((12, 37, 70), 2, _cfg(256, 1, 5, 2, march=2, rows=2)),
     ((30, 75, 130), 2, _cfg(64, 2, 3, 2, order=3, march=2, rows=4)), ((19, 9, 66), 1, _cfg(128, 1, 4, 1, order=3)),
     ((26, 140, 258), 3, _cfg(128, 2, 8, 2, order=3, rows=4)),
+    ((40, 9, 66), 16, None), ((44, 9, 66), 20, None),
 ])
 def test_heat_small_bit_exact_and_residual(shape, K, cfg):
     say(f"heat {shape} K={K}")
