@@ -16,7 +16,8 @@ pytestmark = pytest.mark.gpu
 
 
 # ------------------------------------------------------------------ sum
-@pytest.mark.parametrize("n,K", [(1, 1), (1000, 1), (1000, 3), (123_457, 4), (2_000_003, 8)])
+@pytest.mark.parametrize("n,K", [(1, 1), (1000, 1), (1000, 3), (123_457, 4), (2_000_003, 8), (2_000_003, 16),
+                                 (123_457, 20)])
 def test_sum_small(n, K):
     say(f"sum n={n} K={K}")
     x = inputs.uniform(n, seed=n, lo=-1.0, hi=1.0)
@@ -138,7 +139,7 @@ def _row_bound(rp, col, val, x):
     return cs[rp[1:]] - cs[rp[:-1]]
 
 
-@pytest.mark.parametrize("n,K", [(1, 1), (100, 1), (1000, 3), (5000, 4)])
+@pytest.mark.parametrize("n,K", [(1, 1), (100, 1), (1000, 3), (5000, 4), (5000, 16), (5000, 20)])
 def test_spmv_small(n, K):
     say(f"spmv n={n} K={K}")
     rp, col, val, x = inputs.csr_matrix(n, n, 16, seed=8)
