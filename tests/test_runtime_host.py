@@ -770,6 +770,8 @@ def test_column_split_jacobi_plan_matches_model(K, lazy):
         copies = sorted((t["dst"], t["src"], t["lo"], t["hi"]) for t in tr if t["op"] == "COPY")
         assert copies == sorted((p, s, lo, hi) for p, pp in enumerate(ps) for (_, s, lo, hi) in pp["copies"])
         assert len(copies) == (0 if step == 0 or not lazy else 2 * (K - 1))
+        # the partitions of a sweep run as one packed launch (one stream, one op)
+        assert len({(t["stream"], t["seq"]) for t in kernels}) == 1
         src, dst = dst, src
     assert race_check(full) == [] and freshness_check(full) == []
     c.close()
